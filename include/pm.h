@@ -1,0 +1,205 @@
+/*
+ * libpm: particle-mesh step of FastPM with massive-neutrino particles on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bayer, Banerjee & Feng, "A fast particle-mesh simulation of
+ * non-linear cosmological structure formation with massive neutrinos"
+ * (arXiv:2007.13394).  CDM particles sit on a lattice; neutrino particles sit
+ * on a coarser staggered lattice of sites, N_shell x (2 N_fib + 1) per site,
+ * with quasi-randomly sampled Fermi-Dirac speeds (Sec. 2.1).  Each step paints
+ * all particles to a mesh with cloud-in-cell weights, solves Poisson's
+ * equation with the matter-only source (Sec. 2.2, "Om_pois" eq.) by FFT,
+ * reads the force back at the particles and applies FastPM's modified kick and
+ * drift, which keep the Zel'dovich trajectory x = q + D(a) s exact (Sec. 2.3).
+ *
+ * Conventions used by every entry point
+ *   - Mesh index (i0, i1, i2), i2 fastest; particle coordinate d lies along
+ *     mesh axis d.  Positions are float32 in mesh-cell units, in [0, N).
+ *   - Particle arrays are structure-of-arrays: x[d * stride + i].  For the
+ *     calls that take a context, stride = P, the particle count of the
+ *     configuration (pm_sizes).
+ *   - Particle order: segment 0 holds the N_c CDM particles in lattice order
+ *     ((i0 * n + i1) * n + i2); segment 1 + s holds neutrino shell s, ordered
+ *     by site (row-major) then direction.  Each segment has one particle mass.
+ *   - Momenta are canonical, p = a^2 dx/dt / H0, in mesh-cell units, so that
+ *     dx/da = p / (a^3 E) and dp/da = F / (a^2 E).
+ *   - The force is F = -grad phi with lap phi = 1.5 Omega_m delta in mesh
+ *     units; masses are normalised to a mean of one unit per cell.
+ *   - Mass is accumulated in fixed point: one unit of mass is 2^shift.
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory owned by the caller.  The library
+ *     never allocates device memory: all scratch lives in the caller's
+ *     workspace.  All device work is enqueued on the HIP stream passed in
+ *     (a hipStream_t; NULL is the null stream).
+ *   - Every call returns a pm_status.  Argument errors are detected before
+ *     any device work is enqueued.  pm_last_error() describes the most
+ *     recent failure on the calling thread.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PM_OK = 0,
+    PM_ERR_ARG = -1,      /* invalid argument or configuration */
+    PM_ERR_SIZE = -2,     /* workspace too small */
+    PM_ERR_DEVICE = -3,   /* a HIP call failed */
+    PM_ERR_OVERFLOW = -4, /* a density cell left the fixed-point range */
+    PM_ERR_NAN = -5,      /* a particle position or momentum became non-finite */
+    PM_ERR_STATE = -6     /* call not valid for this context */
+} pm_status;
+
+/* pm_config.flags */
+enum {
+    PM_FLAG_NO_FLIP = 1,   /* keep one direction set on every neutrino site */
+    PM_FLAG_NO_GUARDS = 2, /* skip the end-of-call device flag check (no host sync) */
+};
+
+/* Simulation parameters (Table 1 of the paper names the counts).  All
+ * fields are read by pm_sizes and copied by pm_init. */
+typedef struct {
+    int32_t n_mesh;   /* N: force mesh cells per side, power of two, 16..2048 */
+    int32_t n_cdm;    /* CDM lattice sites per side; power of two, 8..N */
+    int32_t n_sites;  /* neutrino sites per side; 0 = no neutrino particles,
+                         otherwise a power of two dividing n_cdm */
+    int32_t n_shell;  /* Fermi-Dirac speed shells, 1..64 */
+    int32_t n_fib;    /* 2 n_fib + 1 directions per shell, 0..1000 */
+    int32_t n_nu;     /* neutrino eigenstates in the background, 0..3 */
+    int32_t shift;    /* fixed-point shift S, 16..52 */
+    int32_t flags;    /* PM_FLAG_* */
+    double box;       /* side length, Mpc/h */
+    double omega_m;   /* total matter today (CDM + neutrinos) */
+    double h;
+    double n_s;
+    double sigma8;    /* normalises the linear CDM spectrum at z = 0 */
+    double T_cmb;     /* K */
+    double N_eff;
+    double m_nu[3];   /* eigenstate masses, eV (first n_nu used) */
+    double a0;        /* initial scale factor of the initial conditions */
+} pm_config;
+
+typedef struct pm_ctx pm_ctx;
+
+/* Sizes implied by a configuration.  Any output pointer may be NULL.
+ *   n_particles : P = n_cdm^3 + n_sites^3 n_shell (2 n_fib + 1)
+ *   n_segments  : 1 + n_shell (1 when n_sites = 0)
+ *   workspace   : bytes of device workspace pm_init needs
+ * Errors: PM_ERR_ARG for an invalid configuration. */
+pm_status pm_sizes(const pm_config *cfg, int64_t *n_particles, int32_t *n_segments,
+                   size_t *workspace_bytes);
+
+/* Create a context.  Computes the background, growth and neutrino shell
+ * tables on the host (Sec. 2.1, 2.3), uploads FFT tables into the workspace
+ * on `stream` and waits for that upload.  workspace: device, at least
+ * pm_sizes' bytes, 256-byte aligned, owned by the caller, must outlive the
+ * context.  Errors: PM_ERR_ARG, PM_ERR_SIZE, PM_ERR_DEVICE. */
+pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes, void *stream,
+                  pm_ctx **out);
+
+/* Release the host-side context (the workspace is the caller's). */
+void pm_free(pm_ctx *ctx);
+
+/* Human-readable description of the last error on this thread. */
+const char *pm_last_error(void);
+
+/* Segment table (host outputs, each may be NULL):
+ *   offsets[n_segments + 1] particle index ranges, mass[n_segments] particle
+ *   masses in mean-cell units (Sec. 2.1 "m_shell" eq.), quantum[n_segments]
+ *   = llrint(mass 2^shift). */
+pm_status pm_segments(const pm_ctx *ctx, int64_t *offsets, double *mass, int64_t *quantum);
+
+/* Neutrino shell table (host outputs, n_shell entries each, may be NULL):
+ * speeds q_shell and mass fractions m_shell (Sec. 2.1 eqs. "q_shell",
+ * "m_shell"), edges[n_shell + 1] with equal area under q f(q) ("N_shell" eq.,
+ * effective distribution of the "FD_deg" eq. for unequal masses). */
+pm_status pm_shells(const pm_ctx *ctx, double *edges, double *q_shell, double *m_shell);
+
+/* Linear growth (Sec. 2.3, "growthDE" eq.): D(a) and G(a) = a^2 E dD/dlna for
+ * n host values a[i] >= 1/160.  Host arrays.  Errors: PM_ERR_ARG. */
+pm_status pm_growth(const pm_ctx *ctx, int32_t n, const double *a, double *D, double *G);
+
+/* FastPM factors of one KDK call (Sec. 2.3): kick from a_kick0 to a_kick1
+ * with the force at a_force, drift from a_force to a_drift1 with the
+ * momentum at a_kick1.  Host outputs. */
+pm_status pm_kdk_factors(const pm_ctx *ctx, double a_force, double a_kick0, double a_kick1,
+                         double a_drift1, double *kick, double *drift);
+
+/* Zel'dovich initial conditions at a0 (Sec. 2.1, 2.2).
+ *   white : device float32 [n_cdm]^3 unit Gaussian white noise (the random
+ *           numbers of the realisation; the caller draws them)
+ *   x, p  : device float32 [3][P] outputs
+ * CDM: lattice plus displacement, p = (G/D)(a0) s.  Neutrinos: staggered
+ * sites, shells of radius proportional to speed, Fibonacci directions (set
+ * reversed on odd sites unless PM_FLAG_NO_FLIP), bulk displacement from the
+ * same noise with free-streaming suppression. */
+pm_status pm_ic(pm_ctx *ctx, const float *white, float *x, float *p, void *stream);
+
+/* Cloud-in-cell assignment of particles [first, first + count) with one mass
+ * quantum, ADDED to the int64 mesh (caller zeroes it).
+ *   x      : device float32, coordinate d of particle i at x[d * stride + i],
+ *            every value in [0, N)
+ *   mesh_q : device int64 [N]^3
+ * Corner weights are products of (1 - d, d) per axis in double precision,
+ * rounded to nearest integer quanta, the last corner taking the remainder, so
+ * each particle adds exactly `quantum` and the result does not depend on the
+ * order of the particles. */
+pm_status pm_paint_q(pm_ctx *ctx, const float *x, int64_t stride, int64_t first, int64_t count,
+                     int64_t quantum, int64_t *mesh_q, void *stream);
+
+/* pm_paint_q over segments [seg_lo, seg_hi) of a [3][P] particle array, each
+ * with its own quantum; added to mesh_q (device int64 [N]^3). */
+pm_status pm_paint(pm_ctx *ctx, const float *x, int32_t seg_lo, int32_t seg_hi, int64_t *mesh_q,
+                   void *stream);
+
+/* Forward 3D real-to-complex transform, unnormalised, X_k = sum_j x_j
+ * exp(-2 pi i j.k / N).  real: device float32 [N]^3; out: device interleaved
+ * complex64 [N][N][N/2 + 1].  Uses the workspace. */
+pm_status pm_fft_r2c(pm_ctx *ctx, const float *real, float *out, void *stream);
+
+/* Inverse 3D complex-to-real transform, unnormalised (returns N^3 times the
+ * field whose forward transform is `spec`).  spec: device complex64
+ * [N][N][N/2 + 1] (planes k2 = 0 and N/2 must be Hermitian); real: device
+ * float32 [N]^3. */
+pm_status pm_fft_c2r(pm_ctx *ctx, const float *spec, float *real, void *stream);
+
+/* Force meshes from a fixed-point density: delta = Q 2^-shift - 1, F_d(k) =
+ * 1.5 Omega_m i k_d / k^2 delta(k) (zero at k = 0 and on the Nyquist plane of
+ * component d).  mesh_q: device int64 [N]^3; out: device float32 [3][N]^3. */
+pm_status pm_force_mesh(pm_ctx *ctx, const int64_t *mesh_q, float *out, void *stream);
+
+/* Force on every particle at positions x: paint all segments, solve, read
+ * back with cloud-in-cell weights.  x: device [3][P]; acc: device [3][P]. */
+pm_status pm_force(pm_ctx *ctx, const float *x, float *acc, void *stream);
+
+/* One call of the kick-drift-kick loop (Sec. 2.3): force at x (time
+ * a_force), p += K F with K the kick from a_kick0 to a_kick1, then
+ * x += D p with D the drift from a_force to a_drift1 (momentum at a_kick1),
+ * wrapped into [0, N).  A run of n steps is n + 1 calls with merged kicks;
+ * the last call has a_kick1 = a_drift1 = a_force.  x, p: device [3][P],
+ * updated in place.  Errors: PM_ERR_NAN if a result is non-finite,
+ * PM_ERR_OVERFLOW if a density cell overflowed (checked at the end of the
+ * call, which then waits for the stream, unless PM_FLAG_NO_GUARDS). */
+pm_status pm_step(pm_ctx *ctx, float *x, float *p, double a_force, double a_kick0, double a_kick1,
+                  double a_drift1, void *stream);
+
+/* Binned power spectrum of the particles (Sec. 3): painted density contrast
+ * of segments [a_lo, a_hi) crossed with that of [b_lo, b_hi) (auto power if
+ * the ranges are equal).  Bins are [b, b+1) in units of 2 pi / L by |k|; k = 0
+ * is excluded; each mode of the full mesh counts once.  compensate != 0
+ * divides each field by the cloud-in-cell window prod_d sinc^2(pi n_d / N).
+ * Host outputs k_mean (h/Mpc), pk ((Mpc/h)^3), n_modes, each nbins long,
+ * nbins in 1..2048.  Waits for the stream before returning. */
+pm_status pm_power(pm_ctx *ctx, const float *x, int32_t a_lo, int32_t a_hi, int32_t b_lo,
+                   int32_t b_hi, int32_t nbins, int32_t compensate, double *k_mean, double *pk,
+                   double *n_modes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PM_H */

@@ -1,0 +1,495 @@
+// Mesh FFT passes for the particle-mesh Poisson solve on gfx950.
+//
+// The 3D transform of an N^3 mesh (i0, i1, i2; i2 contiguous) is done as
+// three passes, each one HBM read and one HBM write of the mesh:
+//   * rows (axis 2): real-to-complex of every contiguous row, computed as an
+//     N/2-point complex FFT of the even/odd samples packed as (re, im) plus a
+//     split step; the int64 fixed-point density is converted to the density
+//     contrast on the fly.  The complex-to-real inverse mirrors it.
+//   * columns (axis 1): tiles of TILE_W contiguous complex columns (64 bytes)
+//     x N rows are staged in LDS and transformed along the strided axis.
+//   * axis 0: the same column tiles, forward transform, then for each output
+//     a per-mode multiplier (the gradient of the inverse Laplacian, or the
+//     initial-condition transfer function) and an inverse transform, so the
+//     forward spectrum is read once and the k-space multiply never touches
+//     HBM on its own.
+// Transforms inside LDS are Stockham autosort stages of radix 2..16 held in
+// registers (two barriers per stage, in place), twiddles from an FP64-derived
+// table.  Consecutive workgroups are spread over the eight XCDs by the
+// hardware, so tiles are renumbered to give each XCD a contiguous run of
+// tiles (neighbouring 64-byte half lines then meet in the same L2).
+#include <type_traits>
+
+#include "pm_internal.h"
+
+namespace pm {
+namespace {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+// cos(2 pi j / 16)
+constexpr float c16(int j)
+{
+    switch (j & 15) {
+    case 0: return 1.0f;
+    case 1: return 0.92387953251128674f;
+    case 2: return 0.70710678118654752f;
+    case 3: return 0.38268343236508977f;
+    case 4: return 0.0f;
+    case 5: return -0.38268343236508977f;
+    case 6: return -0.70710678118654752f;
+    case 7: return -0.92387953251128674f;
+    case 8: return -1.0f;
+    case 9: return -0.92387953251128674f;
+    case 10: return -0.70710678118654752f;
+    case 11: return -0.38268343236508977f;
+    case 12: return 0.0f;
+    case 13: return 0.38268343236508977f;
+    case 14: return 0.70710678118654752f;
+    default: return 0.92387953251128674f;
+    }
+}
+
+// a * exp(-/+ 2 pi i j / 16) (minus for the forward transform)
+template <bool INV>
+__device__ __forceinline__ float2 rot16(float2 a, int j)
+{
+    j &= 15;
+    if (j == 0) return a;
+    if (j == 8) return make_float2(-a.x, -a.y);
+    if (j == 4) return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+    if (j == 12) return INV ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+    const float c = c16(j), s = INV ? c16(j - 4) : -c16(j - 4);
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+// In-register DFT of size R (natural order in and out), radix-2 recursion.
+template <int R, bool INV>
+struct Dft {
+    __device__ __forceinline__ static void run(float2 *v)
+    {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; i++) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        Dft<R / 2, INV>::run(e);
+        Dft<R / 2, INV>::run(o);
+#pragma unroll
+        for (int k = 0; k < R / 2; k++) {
+            const float2 t = rot16<INV>(o[k], k * (16 / R));
+            v[k] = cadd(e[k], t);
+            v[k + R / 2] = csub(e[k], t);
+        }
+    }
+};
+template <bool INV>
+struct Dft<1, INV> {
+    __device__ __forceinline__ static void run(float2 *) {}
+};
+
+// One Stockham stage of radix R over NC independent transforms of length L
+// held in LDS: element (c, l) at buf[c * SC + l * SL].  NS = product of the
+// radices already applied.  All butterflies of a thread are read before the
+// barrier and written after it, so the stage runs in place.
+template <int L, int R, int NS, int NC, int T, bool COLMAJ, int SL, int SC, bool INV>
+__device__ __forceinline__ void stage(float2 *buf, const float2 *__restrict__ twL)
+{
+    constexpr int NB = NC * (L / R);
+    constexpr int PER = (NB + T - 1) / T;
+    float2 v[PER][R];
+    int dst[PER];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int b = 0; b < PER; b++) {
+        const int bf = tid + b * T;
+        if ((NB % T == 0) || bf < NB) {
+            int c, j;
+            if (COLMAJ) {
+                c = bf % NC;
+                j = bf / NC;
+            } else {
+                j = bf % (L / R);
+                c = bf / (L / R);
+            }
+            const int k = j & (NS - 1);
+#pragma unroll
+            for (int r = 0; r < R; r++) v[b][r] = buf[c * SC + (j + r * (L / R)) * SL];
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; r++) {
+                    float2 w = twL[r * k * (L / (NS * R))];
+                    if (INV) w.y = -w.y;
+                    v[b][r] = cmul(v[b][r], w);
+                }
+            }
+            Dft<R, INV>::run(v[b]);
+            dst[b] = c * SC + ((j / NS) * NS * R + k) * SL;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < PER; b++) {
+        const int bf = tid + b * T;
+        if ((NB % T == 0) || bf < NB) {
+#pragma unroll
+            for (int r = 0; r < R; r++) buf[dst[b] + r * NS * SL] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform: stages of at most 2^MAXB, bits split as evenly as possible.
+template <int L, int NS, int NC, int T, bool COLMAJ, int SL, int SC, bool INV, int MAXB>
+__device__ __forceinline__ void fft_from(float2 *buf, const float2 *__restrict__ twL)
+{
+    if constexpr (NS < L) {
+        constexpr int rem = ilog2c(L / NS);
+        constexpr int nst = (rem + MAXB - 1) / MAXB;
+        constexpr int bits = (rem + nst - 1) / nst;
+        constexpr int R = 1 << bits;
+        stage<L, R, NS, NC, T, COLMAJ, SL, SC, INV>(buf, twL);
+        fft_from<L, NS * R, NC, T, COLMAJ, SL, SC, INV, MAXB>(buf, twL);
+    }
+}
+
+// Renumber workgroups so that each XCD (b mod 8) owns a contiguous tile range.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+template <int LOGN>
+struct RowCfg {
+    static constexpr int N = 1 << LOGN, L = N / 2;
+    static constexpr int RB = (8192 / N) < (N * N) ? (8192 / N) : (N * N);
+    static constexpr int T = 256;
+};
+
+template <int LOGN>
+struct ColCfg {
+    static constexpr int N = 1 << LOGN, W = TILE_W, E = N * W;
+    static constexpr int T = (E / 32) > 64 ? (E / 32) : 64;
+    static constexpr int PER = E / T;
+};
+
+// ---------------------------------------------------------------- rows
+template <int LOGN, typename SRC>
+__global__ __launch_bounds__(256) void k_r2c_rows(const SRC *src, int64_t src_stride,
+                                                  float2 *dst, int64_t dst_stride, double scale,
+                                                  double offset, const float2 *__restrict__ tw, int *flag)
+{
+    using C = RowCfg<LOGN>;
+    constexpr int N = C::N, L = C::L, RB = C::RB, T = C::T;
+    __shared__ float2 buf[RB * L];
+    const int64_t row0 = (int64_t)blockIdx.x * RB;
+    const int tid = threadIdx.x;
+    bool bad = false;
+#pragma unroll 8
+    for (int e = tid; e < RB * L; e += T) {
+        const int r = e / L, m = e % L;
+        const SRC *s = src + (row0 + r) * src_stride + 2 * m;
+        float a, b;
+        if constexpr (std::is_same<SRC, int64_t>::value) {
+            const longlong2 q = *reinterpret_cast<const longlong2 *>(s);
+            bad |= (q.x < -(1LL << 40)) | (q.y < -(1LL << 40));
+            a = (float)((double)q.x * scale + offset);
+            b = (float)((double)q.y * scale + offset);
+        } else {
+            const float2 q = *reinterpret_cast<const float2 *>(s);
+            a = q.x;
+            b = q.y;
+        }
+        buf[e] = make_float2(a, b);
+    }
+    if (bad) atomicOr(flag, FLAG_OVERFLOW);
+    __syncthreads();
+    fft_from<L, 1, RB, T, false, 1, L, false, 4>(buf, tw + L);
+    // X_k = (Z_k + conj Z_{L-k}) / 2 - i w^k (Z_k - conj Z_{L-k}) / 2, w = exp(-2 pi i / N)
+    for (int e = tid; e < RB * (L + 1); e += T) {
+        const int r = e / (L + 1), k = e % (L + 1);
+        const float2 zk = buf[r * L + (k & (L - 1))];
+        const float2 zc = cconj(buf[r * L + ((L - k) & (L - 1))]);
+        const float2 w = tw[N + k];
+        const float2 sum = cadd(zk, zc), t = cmul(w, csub(zk, zc));
+        dst[(row0 + r) * dst_stride + k] = make_float2(0.5f * (sum.x + t.y), 0.5f * (sum.y - t.x));
+    }
+    constexpr int PADC = (int)half_pad(N) - (L + 1);
+    for (int e = tid; e < RB * PADC; e += T) {
+        const int r = e / PADC, k = L + 1 + e % PADC;
+        dst[(row0 + r) * dst_stride + k] = make_float2(0.f, 0.f);
+    }
+}
+
+template <int LOGN>
+__global__ __launch_bounds__(256) void k_c2r_rows(const float2 *src, int64_t src_stride, float *dst,
+                                                  int64_t dst_stride, const float2 *__restrict__ tw)
+{
+    using C = RowCfg<LOGN>;
+    constexpr int N = C::N, L = C::L, RB = C::RB, T = C::T, LS = L + 1;
+    __shared__ float2 buf[RB * LS];
+    const int64_t row0 = (int64_t)blockIdx.x * RB;
+    const int tid = threadIdx.x;
+#pragma unroll 8
+    for (int e = tid; e < RB * LS; e += T) {
+        const int r = e / LS, k = e % LS;
+        buf[e] = src[(row0 + r) * src_stride + k];
+    }
+    __syncthreads();
+    // Z_k = A + i B, A = X_k + conj X_{L-k}, B = (X_k - conj X_{L-k}) exp(+2 pi i k / N);
+    // Z_{L-k} = conj A + i conj B.
+    for (int e = tid; e < RB * (L / 2 + 1); e += T) {
+        const int r = e / (L / 2 + 1), k = e % (L / 2 + 1);
+        const float2 X = buf[r * LS + k], Y = cconj(buf[r * LS + L - k]);
+        const float2 A = cadd(X, Y), B = cmul(cconj(tw[N + k]), csub(X, Y));
+        buf[r * LS + k] = make_float2(A.x - B.y, A.y + B.x);
+        if (k != 0 && k != L / 2) buf[r * LS + L - k] = make_float2(A.x + B.y, B.x - A.y);
+    }
+    __syncthreads();
+    fft_from<L, 1, RB, T, false, 1, LS, true, 4>(buf, tw + L);
+#pragma unroll 8
+    for (int e = tid; e < RB * L; e += T) {
+        const int r = e / L, m = e % L;
+        *reinterpret_cast<float2 *>(dst + (row0 + r) * dst_stride + 2 * m) = buf[r * LS + m];
+    }
+}
+
+// ---------------------------------------------------------------- columns
+template <int LOGN, bool INV>
+__global__ __launch_bounds__(ColCfg<LOGN>::T) void k_cols(float2 *base, int64_t stride_l, int64_t stride_o,
+                                                          int n_cb, const float2 *__restrict__ tw)
+{
+    using C = ColCfg<LOGN>;
+    constexpr int N = C::N, W = C::W, E = C::E, T = C::T;
+    __shared__ float2 buf[E];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int o = tile / n_cb, cb = tile % n_cb;
+    float2 *p = base + (int64_t)o * stride_o + cb * W;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < C::PER; i++) {
+        const int e = tid + i * T;
+        buf[e] = p[(int64_t)(e / W) * stride_l + (e % W)];
+    }
+    __syncthreads();
+    fft_from<N, 1, W, T, true, W, 1, INV, 4>(buf, tw + N);
+#pragma unroll
+    for (int i = 0; i < C::PER; i++) {
+        const int e = tid + i * T;
+        p[(int64_t)(e / W) * stride_l + (e % W)] = buf[e];
+    }
+}
+
+// ---------------------------------------------------------------- axis 0 + multiplier
+__device__ __forceinline__ int signed_mode(int k, int n) { return k <= n / 2 ? k : k - n; }
+
+// i k_d / k^2 * coef (coef = 1.5 Omega_m / N^3), zero at k = 0 and on the
+// Nyquist plane of component d; k in mesh units.
+__device__ __forceinline__ float2 mult_force(float2 v, int d, int l, int o, int k2, int n, float coef)
+{
+    if (k2 > n / 2) return make_float2(0.f, 0.f);
+    const int n0 = signed_mode(l, n), n1 = signed_mode(o, n), n2 = k2;
+    const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
+    if (nd == n / 2 || nd == -n / 2) return make_float2(0.f, 0.f);
+    const float s = 6.28318530717958648f / (float)n;
+    const float k0 = s * n0, k1 = s * n1, kz = s * n2;
+    const float kk = k0 * k0 + k1 * k1 + kz * kz;
+    if (kk == 0.f) return make_float2(0.f, 0.f);
+    const float kd = d == 0 ? k0 : (d == 1 ? k1 : kz);
+    const float g = coef * kd / kk;
+    return make_float2(-g * v.y, g * v.x);
+}
+
+// Zel'dovich displacement of component d from a white-noise mode (FP64):
+// i k_d / k^2 sqrt(A P(k) / V_cell) [1 + (k/k_fs)^2]^-1 exp(i k.h) / M_ic,
+// P(k) = k^n_s T_BBKS^2(k / (Omega_m h)); zero at k = 0 and on every Nyquist plane.
+__device__ __forceinline__ float2 mult_ic(float2 v, int d, int l, int o, int k2, int n, const IcParams &p)
+{
+    if (k2 >= n / 2) return make_float2(0.f, 0.f);
+    const int n0 = signed_mode(l, n), n1 = signed_mode(o, n), n2 = k2;
+    if (n0 == -n / 2 || n0 == n / 2 || n1 == -n / 2 || n1 == n / 2) return make_float2(0.f, 0.f);
+    if (n0 == 0 && n1 == 0 && n2 == 0) return make_float2(0.f, 0.f);
+    const double s = 6.283185307179586476925 / p.box;
+    const double k0 = s * n0, k1 = s * n1, kz = s * n2;
+    const double kk = k0 * k0 + k1 * k1 + kz * kz, k = sqrt(kk);
+    const double q = k / p.omh;
+    const double poly = 1.0 + 3.89 * q + (16.1 * q) * (16.1 * q) + (5.46 * q) * (5.46 * q) * (5.46 * q) +
+                        (6.71 * q) * (6.71 * q) * (6.71 * q) * (6.71 * q);
+    const double T = log(1.0 + 2.34 * q) / (2.34 * q) * pow(poly, -0.25);
+    double amp = sqrt(p.amp_over_vcell * pow(k, p.n_s)) * T * p.scale;
+    if (p.kfs > 0) amp /= 1.0 + (k / p.kfs) * (k / p.kfs);
+    const double kd = d == 0 ? k0 : (d == 1 ? k1 : kz);
+    const double g = amp * kd / kk;
+    double re = -g * v.y, im = g * v.x;   // i g v
+    if (p.half_cell != 0) {
+        const double ph = (k0 + k1 + kz) * p.half_cell;
+        const double c = cos(ph), sn = sin(ph);
+        const double r2 = re * c - im * sn, i2 = re * sn + im * c;
+        re = r2;
+        im = i2;
+    }
+    return make_float2((float)re, (float)im);
+}
+
+template <int LOGN, int MODE, int NOUT>
+__global__ __launch_bounds__(ColCfg<LOGN>::T) void k_axis0(const float2 *src, int64_t s_l, int64_t s_o,
+                                                           float2 *out0, float2 *out1, float2 *out2,
+                                                           int64_t o_l, int64_t o_o, int n_cb, float coef,
+                                                           IcParams icp, const float2 *__restrict__ tw)
+{
+    using C = ColCfg<LOGN>;
+    constexpr int N = C::N, W = C::W, E = C::E, T = C::T, PER = C::PER;
+    __shared__ float2 buf[E];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int o = tile / n_cb, cb = tile % n_cb;
+    const float2 *p = src + (int64_t)o * s_o + cb * W;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        const int e = tid + i * T;
+        buf[e] = p[(int64_t)(e / W) * s_l + (e % W)];
+    }
+    __syncthreads();
+    fft_from<N, 1, W, T, true, W, 1, false, 4>(buf, tw + N);
+    if constexpr (NOUT == 0) {
+        float2 *q = out0 + (int64_t)o * o_o + cb * W;
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const int e = tid + i * T;
+            q[(int64_t)(e / W) * o_l + (e % W)] = buf[e];
+        }
+    } else {
+        float2 keep[PER];
+#pragma unroll
+        for (int i = 0; i < PER; i++) keep[i] = buf[tid + i * T];
+#pragma unroll 1
+        for (int d = 0; d < NOUT; d++) {
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int e = tid + i * T;
+                const int l = e / W, k2 = cb * W + (e % W);
+                buf[e] = MODE == MULT_FORCE ? mult_force(keep[i], d, l, o, k2, N, coef)
+                                            : mult_ic(keep[i], d, l, o, k2, N, icp);
+            }
+            __syncthreads();
+            fft_from<N, 1, W, T, true, W, 1, true, 4>(buf, tw + N);
+            float2 *q = (d == 0 ? out0 : (d == 1 ? out1 : out2)) + (int64_t)o * o_o + cb * W;
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int e = tid + i * T;
+                q[(int64_t)(e / W) * o_l + (e % W)] = buf[e];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+#define PM_DISPATCH_LOGN(logn, MACRO) \
+    switch (logn) {                    \
+    case 3: MACRO(3); break;           \
+    case 4: MACRO(4); break;           \
+    case 5: MACRO(5); break;           \
+    case 6: MACRO(6); break;           \
+    case 7: MACRO(7); break;           \
+    case 8: MACRO(8); break;           \
+    case 9: MACRO(9); break;           \
+    case 10: MACRO(10); break;         \
+    case 11: MACRO(11); break;         \
+    default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_r2c_rows_i64(int logn, const int64_t *src, int64_t src_stride, float2 *dst,
+                               int64_t dst_stride, int64_t nrows, double scale, double offset,
+                               const float2 *tw, int *flag, hipStream_t s)
+{
+#define R2C_I64(LG)                                                                                  \
+    {                                                                                                \
+        const int64_t nb = nrows / RowCfg<LG>::RB;                                                   \
+        hipLaunchKernelGGL((k_r2c_rows<LG, int64_t>), dim3((unsigned)nb), dim3(256), 0, s, src,      \
+                           src_stride, dst, dst_stride, scale, offset, tw, flag);                   \
+    }
+    PM_DISPATCH_LOGN(logn, R2C_I64)
+    return hipGetLastError();
+}
+
+hipError_t launch_r2c_rows_f32(int logn, const float *src, int64_t src_stride, float2 *dst,
+                               int64_t dst_stride, int64_t nrows, const float2 *tw, hipStream_t s)
+{
+#define R2C_F32(LG)                                                                                  \
+    {                                                                                                \
+        const int64_t nb = nrows / RowCfg<LG>::RB;                                                   \
+        hipLaunchKernelGGL((k_r2c_rows<LG, float>), dim3((unsigned)nb), dim3(256), 0, s, src,        \
+                           src_stride, dst, dst_stride, 1.0, 0.0, tw, nullptr);                     \
+    }
+    PM_DISPATCH_LOGN(logn, R2C_F32)
+    return hipGetLastError();
+}
+
+hipError_t launch_c2r_rows(int logn, const float2 *src, int64_t src_stride, float *dst, int64_t dst_stride,
+                           int64_t nrows, const float2 *tw, hipStream_t s)
+{
+#define C2R(LG)                                                                                      \
+    {                                                                                                \
+        const int64_t nb = nrows / RowCfg<LG>::RB;                                                   \
+        hipLaunchKernelGGL((k_c2r_rows<LG>), dim3((unsigned)nb), dim3(256), 0, s, src, src_stride,   \
+                           dst, dst_stride, tw);                                                     \
+    }
+    PM_DISPATCH_LOGN(logn, C2R)
+    return hipGetLastError();
+}
+
+hipError_t launch_cols(int logn, bool inverse, float2 *base, int64_t stride_l, int64_t stride_o, int n_o,
+                       int n_cb, const float2 *tw, hipStream_t s)
+{
+    const unsigned nb = (unsigned)n_o * (unsigned)n_cb;
+#define COLS(LG)                                                                                     \
+    {                                                                                                \
+        if (inverse)                                                                                 \
+            hipLaunchKernelGGL((k_cols<LG, true>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base,        \
+                               stride_l, stride_o, n_cb, tw);                                       \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_cols<LG, false>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base,       \
+                               stride_l, stride_o, n_cb, tw);                                       \
+    }
+    PM_DISPATCH_LOGN(logn, COLS)
+    return hipGetLastError();
+}
+
+hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int64_t s_o, float2 *out0,
+                        float2 *out1, float2 *out2, int64_t o_l, int64_t o_o, int n_cb, double coef,
+                        const IcParams *ic, const float2 *tw, hipStream_t s)
+{
+    const int n = 1 << logn;
+    const unsigned nb = (unsigned)n * (unsigned)n_cb;
+    IcParams icp{};
+    if (ic) icp = *ic;
+    const float fc = (float)coef;
+#define AX0(LG)                                                                                      \
+    {                                                                                                \
+        const dim3 g(nb), b(ColCfg<LG>::T);                                                          \
+        if (mode == MULT_FORCE)                                                                      \
+            hipLaunchKernelGGL((k_axis0<LG, MULT_FORCE, 3>), g, b, 0, s, src, s_l, s_o, out0, out1,  \
+                               out2, o_l, o_o, n_cb, fc, icp, tw);                                  \
+        else if (mode == MULT_IC)                                                                    \
+            hipLaunchKernelGGL((k_axis0<LG, MULT_IC, 3>), g, b, 0, s, src, s_l, s_o, out0, out1,     \
+                               out2, o_l, o_o, n_cb, fc, icp, tw);                                  \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_axis0<LG, MULT_NONE, 0>), g, b, 0, s, src, s_l, s_o, out0, out1,   \
+                               out2, o_l, o_o, n_cb, fc, icp, tw);                                  \
+    }
+    PM_DISPATCH_LOGN(logn, AX0)
+    return hipGetLastError();
+}
+
+}  // namespace pm

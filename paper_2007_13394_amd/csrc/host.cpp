@@ -1,0 +1,486 @@
+// C-ABI entry points of libpm: argument checking, workspace layout, and the
+// orchestration of the device passes on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <new>
+
+#include "pm_internal.h"
+
+struct pm_ctx : pm::Ctx {};
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+pm_status fail(pm_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(PM_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2i(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) r++;
+    return r;
+}
+
+struct Layout {
+    size_t q, f, tw, flag, partial, tables, total;
+};
+
+Layout layout(const pm_config &c)
+{
+    const int64_t n = c.n_mesh, nhp = pm::half_pad(c.n_mesh);
+    Layout L;
+    size_t off = 0;
+    L.q = off;
+    off = align256(off + (size_t)(8 * n * n * n));
+    L.f = off;
+    off = align256(off + (size_t)(3 * n * n * nhp * 8));
+    L.tw = off;
+    off = align256(off + (size_t)(2 * n * 8));
+    L.flag = off;
+    off = align256(off + 256);
+    L.partial = off;
+    off = align256(off + (size_t)(pm::POWER_BLOCKS + 1) * 3 * pm::MAX_BINS * 8);
+    L.tables = off;
+    off = align256(off + (size_t)(3 * (2 * c.n_fib + 1) + 2 * c.n_shell) * 4);
+    L.total = off;
+    return L;
+}
+
+pm_status check_config(const pm_config *c)
+{
+    if (!c) return fail(PM_ERR_ARG, "config is NULL");
+    if (!pow2(c->n_mesh) || c->n_mesh < 16 || c->n_mesh > 2048)
+        return fail(PM_ERR_ARG, "n_mesh must be a power of two in [16, 2048], got %d", c->n_mesh);
+    if (!pow2(c->n_cdm) || c->n_cdm < 8 || c->n_cdm > c->n_mesh)
+        return fail(PM_ERR_ARG, "n_cdm must be a power of two in [8, n_mesh], got %d", c->n_cdm);
+    if (c->n_sites < 0 || (c->n_sites > 0 && (!pow2(c->n_sites) || c->n_sites > c->n_cdm)))
+        return fail(PM_ERR_ARG, "n_sites must be 0 or a power of two dividing n_cdm, got %d", c->n_sites);
+    if (c->n_shell < 1 || c->n_shell > pm::MAX_SEG - 1)
+        return fail(PM_ERR_ARG, "n_shell must be in [1, %d]", pm::MAX_SEG - 1);
+    if (c->n_fib < 0 || c->n_fib > 1000) return fail(PM_ERR_ARG, "n_fib must be in [0, 1000]");
+    if (c->n_nu < 0 || c->n_nu > 3) return fail(PM_ERR_ARG, "n_nu must be in [0, 3]");
+    if (c->shift < 16 || c->shift > 52) return fail(PM_ERR_ARG, "shift must be in [16, 52]");
+    if (!(c->box > 0) || !(c->omega_m > 0) || !(c->h > 0) || !(c->a0 > 1.0 / 160.0) || !(c->a0 <= 1.0))
+        return fail(PM_ERR_ARG, "box, omega_m, h must be positive and a0 in (1/160, 1]");
+    if (!(c->T_cmb >= 0) || !(c->N_eff >= 0)) return fail(PM_ERR_ARG, "T_cmb and N_eff must be >= 0");
+    double m1 = 0;
+    for (int j = 0; j < c->n_nu; j++) {
+        if (!(c->m_nu[j] >= 0)) return fail(PM_ERR_ARG, "neutrino masses must be >= 0");
+        m1 = fmax(m1, c->m_nu[j]);
+    }
+    if (c->n_sites > 0 && !(m1 > 0))
+        return fail(PM_ERR_ARG, "neutrino particles need a positive neutrino mass");
+    double Mnu = 0;
+    for (int j = 0; j < c->n_nu; j++) Mnu += c->m_nu[j];
+    if (!(c->omega_m - Mnu / (93.14 * c->h * c->h) > 0)) return fail(PM_ERR_ARG, "omega_m below omega_nu");
+    return PM_OK;
+}
+
+void counts(const pm_config &c, int64_t *P, int64_t *nc, int64_t *nn, int *nseg)
+{
+    *nc = (int64_t)c.n_cdm * c.n_cdm * c.n_cdm;
+    *nn = (int64_t)c.n_sites * c.n_sites * c.n_sites * c.n_shell * (2 * c.n_fib + 1);
+    *P = *nc + *nn;
+    *nseg = c.n_sites > 0 ? 1 + c.n_shell : 1;
+}
+
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+pm_status check_guards(pm_ctx *c, hipStream_t s)
+{
+    if (c->cfg.flags & PM_FLAG_NO_GUARDS) return PM_OK;
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, c->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h) {
+        HIPCHK(hipMemsetAsync(c->ws.flag, 0, sizeof(int), s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h & pm::FLAG_NAN) return fail(PM_ERR_NAN, "a particle position or momentum became non-finite");
+        return fail(PM_ERR_OVERFLOW, "a density cell left the fixed-point range");
+    }
+    return PM_OK;
+}
+
+// Paint every segment of x into the zeroed Q mesh.
+pm_status paint_all(pm_ctx *c, const float *x, hipStream_t s)
+{
+    const int64_t n = c->n;
+    HIPCHK(pm::launch_fill_i64(c->ws.q, n * n * n, s));
+    for (int g = 0; g < c->nseg; g++)
+        HIPCHK(pm::launch_paint(x, c->P, c->seg_off[g], c->seg_off[g + 1] - c->seg_off[g], c->seg_q[g], c->n,
+                                c->ws.q, s));
+    return PM_OK;
+}
+
+// From the int64 density at `src` (row stride n int64) to the three real
+// force meshes in the F region (row stride 2 Nhp floats).
+pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s)
+{
+    const int n = c->n, lg = c->logn;
+    const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    float2 *S = reinterpret_cast<float2 *>(c->ws.q);
+    float2 *F = c->ws.f;
+    const int64_t cs = n2 * nhp;
+    const double scale = ldexp(1.0, -c->cfg.shift);
+    // axis 2: density contrast, real-to-complex rows (in place when src is Q)
+    HIPCHK(pm::launch_r2c_rows_i64(lg, src, n, S, n, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
+    // axis 1
+    HIPCHK(pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
+    // axis 0 forward, gradient of the inverse Laplacian, axis 0 inverse x 3
+    const double coef = 1.5 * c->cfg.omega_m / ((double)n2 * n);
+    HIPCHK(pm::launch_axis0(lg, pm::MULT_FORCE, S, n2, n, F, F + cs, F + 2 * cs, n * nhp, nhp, ncb, coef, nullptr,
+                            c->ws.tw, s));
+    for (int d = 0; d < 3; d++) {
+        HIPCHK(pm::launch_cols(lg, true, F + d * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        HIPCHK(pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp, n2,
+                                   c->ws.tw, s));
+    }
+    return PM_OK;
+}
+
+// Forward spectrum of a density painted into the int64 mesh `q` (in place,
+// row stride n complex), contrast delta = Q scale - 1.
+pm_status forward_density(pm_ctx *c, int64_t *q, double scale, hipStream_t s)
+{
+    const int n = c->n, lg = c->logn;
+    const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    float2 *S = reinterpret_cast<float2 *>(q);
+    HIPCHK(pm::launch_r2c_rows_i64(lg, q, n, S, n, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
+    HIPCHK(pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
+    HIPCHK(pm::launch_axis0(lg, pm::MULT_NONE, S, n2, n, S, nullptr, nullptr, n2, n, ncb, 0.0, nullptr, c->ws.tw, s));
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pm_last_error(void) { return g_err; }
+
+pm_status pm_sizes(const pm_config *cfg, int64_t *n_particles, int32_t *n_segments, size_t *workspace_bytes)
+{
+    pm_status st = check_config(cfg);
+    if (st != PM_OK) return st;
+    int64_t P, nc, nn;
+    int nseg;
+    counts(*cfg, &P, &nc, &nn, &nseg);
+    if (n_particles) *n_particles = P;
+    if (n_segments) *n_segments = nseg;
+    if (workspace_bytes) *workspace_bytes = layout(*cfg).total;
+    return PM_OK;
+}
+
+pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes, void *stream, pm_ctx **out)
+{
+    pm_status st = check_config(cfg);
+    if (st != PM_OK) return st;
+    if (!out) return fail(PM_ERR_ARG, "out is NULL");
+    const Layout L = layout(*cfg);
+    if (!workspace) return fail(PM_ERR_ARG, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(PM_ERR_ARG, "workspace must be 256-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(PM_ERR_SIZE, "workspace of %zu bytes is below the %zu required", workspace_bytes, L.total);
+    pm_ctx *c = new (std::nothrow) pm_ctx();
+    if (!c) return fail(PM_ERR_ARG, "out of host memory");
+    c->cfg = *cfg;
+    c->n = cfg->n_mesh;
+    c->logn = ilog2i(cfg->n_mesh);
+    int nseg;
+    counts(*cfg, &c->P, &c->nc, &c->nn, &nseg);
+    pm::cosmo_setup(*c);
+    char *b = reinterpret_cast<char *>(workspace);
+    c->ws.base = b;
+    c->ws.bytes = workspace_bytes;
+    c->ws.q = reinterpret_cast<int64_t *>(b + L.q);
+    c->ws.f = reinterpret_cast<float2 *>(b + L.f);
+    c->ws.tw = reinterpret_cast<float2 *>(b + L.tw);
+    c->ws.flag = reinterpret_cast<int *>(b + L.flag);
+    c->ws.partial = reinterpret_cast<double *>(b + L.partial);
+    c->ws.tables = reinterpret_cast<float *>(b + L.tables);
+    // twiddles for every power-of-two length L <= N: tw[L + m] = exp(-2 pi i m / L)
+    const int n = c->n;
+    c->tw_host.assign(2 * (size_t)n, make_float2(0.f, 0.f));
+    for (int Ln = 1; Ln <= n; Ln *= 2)
+        for (int m = 0; m < Ln; m++) {
+            const double ang = -2.0 * M_PI * (double)m / (double)Ln;
+            c->tw_host[Ln + m] = make_float2((float)cos(ang), (float)sin(ang));
+        }
+    hipStream_t s = S(stream);
+    std::vector<float> tables(c->dirs);
+    if (c->nn > 0) {
+        const double spacing = (double)n / cfg->n_sites;   // mesh cells between sites
+        const double qlast = c->q_shell.back();
+        const double pth_unit = c->kT_nu / c->m1 * 299792.458 / 100.0 * n / cfg->box;
+        for (int s2 = 0; s2 < cfg->n_shell; s2++) tables.push_back((float)(0.4 * spacing * c->q_shell[s2] / qlast));
+        for (int s2 = 0; s2 < cfg->n_shell; s2++) tables.push_back((float)(c->q_shell[s2] * pth_unit));
+    }
+    hipError_t e = hipMemcpyAsync(c->ws.tw, c->tw_host.data(), sizeof(float2) * c->tw_host.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !tables.empty())
+        e = hipMemcpyAsync(c->ws.tables, tables.data(), sizeof(float) * tables.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws.flag, 0, 256, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(PM_ERR_DEVICE, "uploading tables: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return PM_OK;
+}
+
+void pm_free(pm_ctx *ctx) { delete ctx; }
+
+pm_status pm_segments(const pm_ctx *c, int64_t *offsets, double *mass, int64_t *quantum)
+{
+    if (!c) return fail(PM_ERR_ARG, "ctx is NULL");
+    for (int g = 0; g < c->nseg; g++) {
+        if (offsets) offsets[g] = c->seg_off[g];
+        if (mass) mass[g] = c->seg_mass[g];
+        if (quantum) quantum[g] = c->seg_q[g];
+    }
+    if (offsets) offsets[c->nseg] = c->seg_off[c->nseg];
+    return PM_OK;
+}
+
+pm_status pm_shells(const pm_ctx *c, double *edges, double *q_shell, double *m_shell)
+{
+    if (!c) return fail(PM_ERR_ARG, "ctx is NULL");
+    if (c->q_shell.empty()) return fail(PM_ERR_STATE, "configuration has no neutrino particles");
+    const int ns = c->cfg.n_shell;
+    for (int s = 0; s < ns; s++) {
+        if (q_shell) q_shell[s] = c->q_shell[s];
+        if (m_shell) m_shell[s] = c->m_shell[s];
+    }
+    if (edges)
+        for (int s = 0; s <= ns; s++) edges[s] = c->edges[s];
+    return PM_OK;
+}
+
+pm_status pm_growth(const pm_ctx *c, int32_t n, const double *a, double *D, double *G)
+{
+    if (!c || n < 0 || (n > 0 && (!a || !D || !G))) return fail(PM_ERR_ARG, "bad growth arguments");
+    for (int i = 0; i < n; i++) {
+        if (!(a[i] >= 1.0 / 160.0) || !(a[i] <= 2.0)) return fail(PM_ERR_ARG, "a out of [1/160, 2]");
+        D[i] = pm::growth_D(*c, a[i]);
+        G[i] = pm::growth_G(*c, a[i]);
+    }
+    return PM_OK;
+}
+
+pm_status pm_kdk_factors(const pm_ctx *c, double a_force, double a_kick0, double a_kick1, double a_drift1,
+                         double *kick, double *drift)
+{
+    if (!c || !kick || !drift) return fail(PM_ERR_ARG, "bad factor arguments");
+    const double a[4] = {a_force, a_kick0, a_kick1, a_drift1};
+    for (double v : a)
+        if (!(v >= 1.0 / 160.0) || !(v <= 2.0)) return fail(PM_ERR_ARG, "scale factor out of [1/160, 2]");
+    const double Df = pm::growth_D(*c, a_force);
+    *kick = (pm::growth_G(*c, a_kick1) - pm::growth_G(*c, a_kick0)) / (1.5 * c->cfg.omega_m * Df);
+    *drift = (pm::growth_D(*c, a_drift1) - Df) / pm::growth_G(*c, a_kick1);
+    return PM_OK;
+}
+
+pm_status pm_ic(pm_ctx *c, const float *white, float *x, float *p, void *stream)
+{
+    if (!c || !white || !x || !p) return fail(PM_ERR_ARG, "NULL argument to pm_ic");
+    hipStream_t s = S(stream);
+    const pm_config &g = c->cfg;
+    const int nic = g.n_cdm, lg = ilog2i(nic), n = c->n;
+    const int64_t nhp = pm::half_pad(nic), n2 = (int64_t)nic * nic;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    float2 *S0 = reinterpret_cast<float2 *>(c->ws.q);
+    float2 *F = c->ws.f;
+    const int64_t cs = n2 * nhp;
+    // white-noise spectrum (rows, then axis 1); axis 0 is done per output
+    HIPCHK(pm::launch_r2c_rows_f32(lg, white, nic, S0, nic, n2, c->ws.tw, s));
+    HIPCHK(pm::launch_cols(lg, false, S0, nic, n2, nic, ncb, c->ws.tw, s));
+    const double a0 = g.a0;
+    const double D0 = pm::growth_D(*c, a0), D1 = pm::growth_D(*c, 1.0), G0 = pm::growth_G(*c, a0);
+    pm::IcParams ip{};
+    ip.amp_over_vcell = pm::pk_amplitude(*c) * (D0 / D1) * (D0 / D1) / pow(g.box / nic, 3);
+    ip.box = g.box;
+    ip.omh = g.omega_m * g.h;
+    ip.n_s = g.n_s;
+    ip.kfs = 0;
+    ip.half_cell = 0;
+    ip.scale = ((double)n / g.box) / ((double)n2 * nic);
+    const double vfac = G0 / D0;
+    for (int pass = 0; pass < (c->nn > 0 ? 2 : 1); pass++) {
+        if (pass == 1) {
+            ip.kfs = 0.82 * sqrt(c->omega_L + g.omega_m / (a0 * a0 * a0)) * a0 * a0 * c->m1;
+            ip.half_cell = 0.5 * g.box / nic;
+        }
+        HIPCHK(pm::launch_axis0(lg, pm::MULT_IC, S0, n2, nic, F, F + cs, F + 2 * cs, nic * nhp, nhp, ncb, 0.0, &ip,
+                                c->ws.tw, s));
+        for (int d = 0; d < 3; d++) {
+            HIPCHK(pm::launch_cols(lg, true, F + d * cs, nhp, nic * nhp, nic, ncb, c->ws.tw, s));
+            HIPCHK(pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp, n2,
+                                       c->ws.tw, s));
+        }
+        if (pass == 0)
+            HIPCHK(pm::launch_ic_cdm(F, nhp, cs, nic, n, vfac, x, p, c->P, s));
+        else
+            HIPCHK(pm::launch_ic_nu(F, nhp, cs, nic, n, g.n_sites, 2 * g.n_fib + 1, g.n_shell, c->ws.tables, vfac,
+                                    (g.flags & PM_FLAG_NO_FLIP) ? 0 : 1, x, p, c->P, c->nc, s));
+    }
+    return PM_OK;
+}
+
+pm_status pm_paint_q(pm_ctx *c, const float *x, int64_t stride, int64_t first, int64_t count, int64_t quantum,
+                     int64_t *mesh_q, void *stream)
+{
+    if (!c || !x || !mesh_q) return fail(PM_ERR_ARG, "NULL argument to pm_paint_q");
+    if (first < 0 || count < 0 || first + count > stride) return fail(PM_ERR_ARG, "particle range outside stride");
+    HIPCHK(pm::launch_paint(x, stride, first, count, quantum, c->n, mesh_q, S(stream)));
+    return PM_OK;
+}
+
+pm_status pm_paint(pm_ctx *c, const float *x, int32_t seg_lo, int32_t seg_hi, int64_t *mesh_q, void *stream)
+{
+    if (!c || !x || !mesh_q) return fail(PM_ERR_ARG, "NULL argument to pm_paint");
+    if (seg_lo < 0 || seg_hi > c->nseg || seg_lo > seg_hi) return fail(PM_ERR_ARG, "bad segment range");
+    for (int g = seg_lo; g < seg_hi; g++)
+        HIPCHK(pm::launch_paint(x, c->P, c->seg_off[g], c->seg_off[g + 1] - c->seg_off[g], c->seg_q[g], c->n,
+                                mesh_q, S(stream)));
+    return PM_OK;
+}
+
+pm_status pm_fft_r2c(pm_ctx *c, const float *real, float *out, void *stream)
+{
+    if (!c || !real || !out) return fail(PM_ERR_ARG, "NULL argument to pm_fft_r2c");
+    hipStream_t s = S(stream);
+    const int n = c->n, lg = c->logn;
+    const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    float2 *S0 = reinterpret_cast<float2 *>(c->ws.q);
+    HIPCHK(pm::launch_r2c_rows_f32(lg, real, n, S0, n, n2, c->ws.tw, s));
+    HIPCHK(pm::launch_cols(lg, false, S0, n, n2, n, ncb, c->ws.tw, s));
+    HIPCHK(pm::launch_cols(lg, false, S0, n2, n, n, ncb, c->ws.tw, s));
+    HIPCHK(pm::launch_copy_half(S0, n, n, reinterpret_cast<float2 *>(out), s));
+    return PM_OK;
+}
+
+pm_status pm_fft_c2r(pm_ctx *c, const float *spec, float *real, void *stream)
+{
+    if (!c || !spec || !real) return fail(PM_ERR_ARG, "NULL argument to pm_fft_c2r");
+    hipStream_t s = S(stream);
+    const int n = c->n, lg = c->logn;
+    const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    float2 *F = c->ws.f;
+    HIPCHK(pm::launch_load_half(reinterpret_cast<const float2 *>(spec), n, F, nhp, s));
+    HIPCHK(pm::launch_cols(lg, true, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    HIPCHK(pm::launch_cols(lg, true, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    HIPCHK(pm::launch_c2r_rows(lg, F, nhp, reinterpret_cast<float *>(F), 2 * nhp, n2, c->ws.tw, s));
+    HIPCHK(pm::launch_copy_real(reinterpret_cast<const float *>(F), 2 * nhp, n, real, s));
+    return PM_OK;
+}
+
+pm_status pm_force_mesh(pm_ctx *c, const int64_t *mesh_q, float *out, void *stream)
+{
+    if (!c || !mesh_q || !out) return fail(PM_ERR_ARG, "NULL argument to pm_force_mesh");
+    hipStream_t s = S(stream);
+    pm_status st = solve(c, mesh_q, s);
+    if (st != PM_OK) return st;
+    const int64_t n = c->n, nhp = pm::half_pad(c->n), cs = n * n * nhp;
+    for (int d = 0; d < 3; d++)
+        HIPCHK(pm::launch_copy_real(reinterpret_cast<const float *>(c->ws.f + d * cs), 2 * nhp, c->n,
+                                    out + d * n * n * n, s));
+    return check_guards(c, s);
+}
+
+pm_status pm_force(pm_ctx *c, const float *x, float *acc, void *stream)
+{
+    if (!c || !x || !acc) return fail(PM_ERR_ARG, "NULL argument to pm_force");
+    hipStream_t s = S(stream);
+    pm_status st = paint_all(c, x, s);
+    if (st == PM_OK) st = solve(c, c->ws.q, s);
+    if (st != PM_OK) return st;
+    const int64_t n = c->n, nhp = pm::half_pad(c->n);
+    HIPCHK(pm::launch_readout(x, c->P, c->ws.f, nhp, n * n * nhp, c->n, acc, s));
+    return check_guards(c, s);
+}
+
+pm_status pm_step(pm_ctx *c, float *x, float *p, double a_force, double a_kick0, double a_kick1, double a_drift1,
+                  void *stream)
+{
+    if (!c || !x || !p) return fail(PM_ERR_ARG, "NULL argument to pm_step");
+    double kick, drift;
+    pm_status st = pm_kdk_factors(c, a_force, a_kick0, a_kick1, a_drift1, &kick, &drift);
+    if (st != PM_OK) return st;
+    hipStream_t s = S(stream);
+    st = paint_all(c, x, s);
+    if (st == PM_OK) st = solve(c, c->ws.q, s);
+    if (st != PM_OK) return st;
+    const int64_t n = c->n, nhp = pm::half_pad(c->n);
+    HIPCHK(pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, n * n * nhp, c->n, (float)kick, (float)drift,
+                                         c->ws.flag, s));
+    return check_guards(c, s);
+}
+
+pm_status pm_power(pm_ctx *c, const float *x, int32_t a_lo, int32_t a_hi, int32_t b_lo, int32_t b_hi,
+                   int32_t nbins, int32_t compensate, double *k_mean, double *pk, double *n_modes, void *stream)
+{
+    if (!c || !x || !k_mean || !pk || !n_modes) return fail(PM_ERR_ARG, "NULL argument to pm_power");
+    if (nbins < 1 || nbins > pm::MAX_BINS) return fail(PM_ERR_ARG, "nbins must be in [1, %d]", pm::MAX_BINS);
+    if (a_lo < 0 || a_hi > c->nseg || a_lo >= a_hi || b_lo < 0 || b_hi > c->nseg || b_lo >= b_hi)
+        return fail(PM_ERR_ARG, "bad segment ranges");
+    hipStream_t s = S(stream);
+    const int n = c->n;
+    const int64_t M = (int64_t)n * n * n;
+    auto scale_of = [&](int lo, int hi) {
+        double tot = 0;
+        for (int g = lo; g < hi; g++) tot += (double)(c->seg_off[g + 1] - c->seg_off[g]) * (double)c->seg_q[g];
+        return (double)M / tot;
+    };
+    HIPCHK(pm::launch_fill_i64(c->ws.q, M, s));
+    pm_status st = pm_paint(c, x, a_lo, a_hi, c->ws.q, stream);
+    if (st == PM_OK) st = forward_density(c, c->ws.q, scale_of(a_lo, a_hi), s);
+    if (st != PM_OK) return st;
+    const float2 *A = reinterpret_cast<const float2 *>(c->ws.q), *B = A;
+    if (a_lo != b_lo || a_hi != b_hi) {
+        int64_t *qb = reinterpret_cast<int64_t *>(c->ws.f);
+        HIPCHK(pm::launch_fill_i64(qb, M, s));
+        st = pm_paint(c, x, b_lo, b_hi, qb, stream);
+        if (st == PM_OK) st = forward_density(c, qb, scale_of(b_lo, b_hi), s);
+        if (st != PM_OK) return st;
+        B = reinterpret_cast<const float2 *>(qb);
+    }
+    const double V = pow(c->cfg.box, 3);
+    double *out = c->ws.partial + (size_t)pm::POWER_BLOCKS * 3 * pm::MAX_BINS;
+    HIPCHK(pm::launch_power_bin(A, B, n, n, nbins, compensate, V / ((double)M * (double)M), 2.0 * M_PI / c->cfg.box,
+                                c->ws.partial, s));
+    HIPCHK(pm::launch_power_reduce(c->ws.partial, nbins, out, s));
+    std::vector<double> h(3 * (size_t)nbins);
+    HIPCHK(hipMemcpyAsync(h.data(), out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < nbins; b++) {
+        const double w = h[3 * b + 2];
+        n_modes[b] = w;
+        pk[b] = w > 0 ? h[3 * b] / w : 0.0;
+        k_mean[b] = w > 0 ? h[3 * b + 1] / w : 0.0;
+    }
+    return check_guards(c, s);
+}
+
+}  // extern "C"

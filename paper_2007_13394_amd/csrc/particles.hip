@@ -1,0 +1,330 @@
+// Particle-side kernels: force readout fused with the FastPM kick and drift,
+// Zel'dovich initial conditions, power-spectrum binning and layout copies.
+#include "pm_internal.h"
+
+namespace pm {
+namespace {
+
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536LL * 16)
+{
+    int64_t b = (n + block - 1) / block;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t count)
+{
+    const int64_t n2 = count / 2;
+    longlong2 *q = reinterpret_cast<longlong2 *>(p);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+        q[i] = make_longlong2(0, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (count & 1)) p[count - 1] = 0;
+}
+
+// Cloud-in-cell interpolation of the three force meshes at u (float32
+// weights; the force field is float32).
+__device__ __forceinline__ void cic_gather(const float *__restrict__ F, int64_t rs, int64_t cs, int n, float u0,
+                                           float u1, float u2, float out[3])
+{
+    const int mask = n - 1;
+    const float f0 = floorf(u0), f1 = floorf(u1), f2 = floorf(u2);
+    const float d0 = u0 - f0, d1 = u1 - f1, d2 = u2 - f2;
+    const int a0 = (int)f0 & mask, a1 = (int)f1 & mask, a2 = (int)f2 & mask;
+    const int b0 = (a0 + 1) & mask, b1 = (a1 + 1) & mask, b2 = (a2 + 1) & mask;
+    const float w0[2] = {1.f - d0, d0}, w1[2] = {1.f - d1, d1}, w2[2] = {1.f - d2, d2};
+    const int i0[2] = {a0, b0}, i1[2] = {a1, b1}, i2[2] = {a2, b2};
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            const int64_t row = ((int64_t)i0[a] * n + i1[b]) * rs;
+            const float wab = w0[a] * w1[b];
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                const int64_t idx = row + i2[c];
+                const float w = wab * w2[c];
+                s0 += w * F[idx];
+                s1 += w * F[cs + idx];
+                s2 += w * F[2 * cs + idx];
+            }
+        }
+    out[0] = s0;
+    out[1] = s1;
+    out[2] = s2;
+}
+
+__device__ __forceinline__ float wrapf(float v, float nf)
+{
+    float t = fmodf(v, nf);
+    if (t < 0.f) t += nf;
+    if (t >= nf) t -= nf;
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_readout(const float *__restrict__ x, int64_t P, const float *__restrict__ F,
+                                                 int64_t rs, int64_t cs, int n, float *acc)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        float f[3];
+        cic_gather(F, rs, cs, n, x[i], x[P + i], x[2 * P + i], f);
+        acc[i] = f[0];
+        acc[P + i] = f[1];
+        acc[2 * P + i] = f[2];
+    }
+}
+
+// p += kick F(x); x += drift p; x wrapped into [0, n).
+__global__ __launch_bounds__(256) void k_readout_kick_drift(float *x, float *p, int64_t P,
+                                                            const float *__restrict__ F, int64_t rs, int64_t cs,
+                                                            int n, float kick, float drift, int *flag)
+{
+    const float nf = (float)n;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const float u0 = x[i], u1 = x[P + i], u2 = x[2 * P + i];
+        float f[3];
+        cic_gather(F, rs, cs, n, u0, u1, u2, f);
+        const float p0 = p[i] + kick * f[0];
+        const float p1 = p[P + i] + kick * f[1];
+        const float p2 = p[2 * P + i] + kick * f[2];
+        const float x0 = wrapf(u0 + drift * p0, nf);
+        const float x1 = wrapf(u1 + drift * p1, nf);
+        const float x2 = wrapf(u2 + drift * p2, nf);
+        bad |= !(isfinite(p0) && isfinite(p1) && isfinite(p2) && isfinite(x0) && isfinite(x1) && isfinite(x2));
+        p[i] = p0;
+        p[P + i] = p1;
+        p[2 * P + i] = p2;
+        x[i] = x0;
+        x[P + i] = x1;
+        x[2 * P + i] = x2;
+    }
+    if (bad) atomicOr(flag, FLAG_NAN);
+}
+
+__global__ void k_copy_real(const float *src, int64_t rs, int n, float *dst)
+{
+    const int64_t m = (int64_t)n * n * n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = src[(t / n) * rs + t % n];
+}
+
+__global__ void k_copy_half(const float2 *src, int64_t rs, int n, float2 *dst)
+{
+    const int nh = n / 2 + 1;
+    const int64_t m = (int64_t)n * n * nh;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = src[(t / nh) * rs + t % nh];
+}
+
+__global__ void k_load_half(const float2 *src, int n, float2 *dst, int64_t rs)
+{
+    const int nh = n / 2 + 1;
+    const int64_t m = (int64_t)n * n * rs;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = t / rs;
+        const int k = (int)(t % rs);
+        dst[t] = k < nh ? src[row * nh + k] : make_float2(0.f, 0.f);
+    }
+}
+
+__device__ __forceinline__ float wrap_to_float(double v, int n)
+{
+    double t = fmod(v, (double)n);
+    if (t < 0) t += n;
+    float r = (float)t;
+    if (r >= (float)n) r = 0.f;
+    return r;
+}
+
+// CDM: lattice point + displacement; p = vfac s (mesh units).
+__global__ void k_ic_cdm(const float *__restrict__ F, int64_t rs, int64_t cs, int nic, int n, double vfac,
+                         float *x, float *p, int64_t P)
+{
+    const int64_t m = (int64_t)nic * nic * nic;
+    const double dc = (double)n / nic;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i0 = (int)(t / ((int64_t)nic * nic)), i1 = (int)((t / nic) % nic), i2 = (int)(t % nic);
+        const int64_t idx = ((int64_t)i0 * nic + i1) * rs + i2;
+        const int ii[3] = {i0, i1, i2};
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const double s = F[d * cs + idx];
+            x[d * P + t] = wrap_to_float(ii[d] * dc + s, n);
+            p[d * P + t] = (float)(vfac * s);
+        }
+    }
+}
+
+// Neutrinos: shell s, site j (row-major), direction t: position = site +
+// r_s v_t + s_nu(site), momentum = p_s v_t + vfac s_nu(site), with the
+// direction set reversed on odd sites when `flip`.
+// tables: dirs[n_dir][3], radius[n_shell], pth[n_shell].
+__global__ void k_ic_nu(const float *__restrict__ F, int64_t rs, int64_t cs, int nic, int n, int ns, int n_dir,
+                        int n_shell, const float *__restrict__ tables, double vfac, int flip, float *x, float *p,
+                        int64_t P, int64_t nc)
+{
+    const int64_t nsites = (int64_t)ns * ns * ns;
+    const int64_t per = nsites * n_dir;
+    const int64_t total = per * n_shell;
+    const int R = nic / ns;
+    const double dc = (double)n / nic;
+    const float *dirs = tables, *radius = tables + 3 * n_dir, *pth = radius + n_shell;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int sh = (int)(t / per);
+        const int64_t rem = t % per;
+        const int64_t site = rem / n_dir;
+        const int dir = (int)(rem % n_dir);
+        const int j0 = (int)(site / ((int64_t)ns * ns)), j1 = (int)((site / ns) % ns), j2 = (int)(site % ns);
+        const int jj[3] = {j0, j1, j2};
+        const double sign = (flip && ((j0 + j1 + j2) & 1)) ? -1.0 : 1.0;
+        const int64_t g = ((int64_t)(j0 * R + R / 2) * nic + (j1 * R + R / 2)) * rs + (j2 * R + R / 2);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const double s = F[d * cs + g];
+            const double v = sign * (double)dirs[dir * 3 + d];
+            const double centre = (jj[d] * R + R / 2 + 0.5) * dc;
+            x[d * P + nc + t] = wrap_to_float(centre + (double)radius[sh] * v + s, n);
+            p[d * P + nc + t] = (float)((double)pth[sh] * v + vfac * s);
+        }
+    }
+}
+
+__device__ __forceinline__ int isqrt_i(int64_t v)
+{
+    int64_t b = (int64_t)sqrt((double)v);
+    while (b * b > v) b--;
+    while ((b + 1) * (b + 1) <= v) b++;
+    return (int)b;
+}
+
+__device__ __forceinline__ double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+// Per-block partial sums over the half spectrum: (sum w P, sum w |k|, sum w)
+// per bin, w = 2 for 0 < k2 < N/2 (the mode and its conjugate), else 1.
+__global__ __launch_bounds__(256) void k_power_bin(const float2 *__restrict__ A, const float2 *__restrict__ B,
+                                                   int64_t rs, int n, int nbins, int compensate, double norm,
+                                                   double kf, double *partial)
+{
+    __shared__ double sh[3 * MAX_BINS];
+    for (int i = threadIdx.x; i < 3 * nbins; i += blockDim.x) sh[i] = 0.0;
+    __syncthreads();
+    const int nh = n / 2 + 1;
+    const int64_t m = (int64_t)n * n * nh;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int k2 = (int)(t % nh);
+        const int64_t row = t / nh;
+        const int k1 = (int)(row % n), k0 = (int)(row / n);
+        const int64_t n0 = k0 < n / 2 ? k0 : k0 - n, n1 = k1 < n / 2 ? k1 : k1 - n, n2 = k2;
+        const int64_t nn2 = n0 * n0 + n1 * n1 + n2 * n2;
+        if (nn2 == 0) continue;
+        const int b = isqrt_i(nn2);
+        if (b >= nbins) continue;
+        const double w = (k2 == 0 || k2 == n / 2) ? 1.0 : 2.0;
+        const float2 a = A[row * rs + k2], c = B[row * rs + k2];
+        double v = ((double)a.x * c.x + (double)a.y * c.y) * norm;
+        if (compensate) {
+            const double pi_n = 3.141592653589793238 / n;
+            const double s0 = sinc(pi_n * n0), s1 = sinc(pi_n * n1), s2 = sinc(pi_n * n2);
+            const double win = s0 * s0 * s1 * s1 * s2 * s2;
+            v /= win * win;
+        }
+        atomicAdd(&sh[3 * b], w * v);
+        atomicAdd(&sh[3 * b + 1], w * kf * sqrt((double)nn2));
+        atomicAdd(&sh[3 * b + 2], w);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * nbins; i += blockDim.x) partial[(int64_t)blockIdx.x * 3 * nbins + i] = sh[i];
+}
+
+// Sum the block partials in block order (deterministic).
+__global__ void k_power_reduce(const double *partial, int nblocks, int nbins, double *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * nbins) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; b++) s += partial[(int64_t)b * 3 * nbins + i];
+    out[i] = s;
+}
+
+}  // namespace
+
+hipError_t launch_fill_i64(int64_t *p, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(count / 2, 256)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs_f, int64_t comp_stride, int n,
+                          float *acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_readout, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P,
+                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f,
+                                     int64_t comp_stride, int n, float kick, float drift, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_readout_kick_drift, dim3(grid_for(P, 256)), dim3(256), 0, s, x, p, P,
+                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_real(const float *src, int64_t rs, int n, float *dst, hipStream_t s)
+{
+    const int64_t m = (int64_t)n * n * n;
+    hipLaunchKernelGGL(k_copy_real, dim3(grid_for(m, 256)), dim3(256), 0, s, src, rs, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_half(const float2 *src, int64_t rs, int n, float2 *dst, hipStream_t s)
+{
+    const int64_t m = (int64_t)n * n * (n / 2 + 1);
+    hipLaunchKernelGGL(k_copy_half, dim3(grid_for(m, 256)), dim3(256), 0, s, src, rs, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_half(const float2 *src, int n, float2 *dst, int64_t rs, hipStream_t s)
+{
+    const int64_t m = (int64_t)n * n * rs;
+    hipLaunchKernelGGL(k_load_half, dim3(grid_for(m, 256)), dim3(256), 0, s, src, n, dst, rs);
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_cdm(const float2 *f, int64_t rs, int64_t comp_stride, int nic, int n, double vfac, float *x,
+                         float *p, int64_t P, hipStream_t s)
+{
+    const int64_t m = (int64_t)nic * nic * nic;
+    hipLaunchKernelGGL(k_ic_cdm, dim3(grid_for(m, 256)), dim3(256), 0, s, reinterpret_cast<const float *>(f),
+                       2 * rs, 2 * comp_stride, nic, n, vfac, x, p, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_nu(const float2 *f, int64_t rs, int64_t comp_stride, int nic, int n, int ns, int n_dir,
+                        int n_shell, const float *tables, double vfac, int flip, float *x, float *p, int64_t P,
+                        int64_t nc, hipStream_t s)
+{
+    const int64_t total = (int64_t)ns * ns * ns * n_dir * n_shell;
+    hipLaunchKernelGGL(k_ic_nu, dim3(grid_for(total, 256)), dim3(256), 0, s, reinterpret_cast<const float *>(f),
+                       2 * rs, 2 * comp_stride, nic, n, ns, n_dir, n_shell, tables, vfac, flip, x, p, P, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_bin(const float2 *A, const float2 *B, int64_t rs, int n, int nbins, int compensate,
+                            double norm, double kf, double *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_power_bin, dim3(POWER_BLOCKS), dim3(256), 0, s, A, B, rs, n, nbins, compensate, norm, kf,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_reduce(const double *partial, int nbins, double *out, hipStream_t s)
+{
+    const int m = 3 * nbins;
+    hipLaunchKernelGGL(k_power_reduce, dim3((m + 255) / 256), dim3(256), 0, s, partial, POWER_BLOCKS, nbins, out);
+    return hipGetLastError();
+}
+
+}  // namespace pm

@@ -1,0 +1,114 @@
+// Private declarations shared by the libpm translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pm.h"
+
+namespace pm {
+
+// Strided FFT passes work on tiles of TILE_W contiguous complex columns.
+constexpr int TILE_W = 8;
+// Half-spectrum rows (N/2 + 1 complex values) are padded to a whole number of
+// column tiles.
+constexpr int64_t half_pad(int n) { return ((n / 2 + 1 + TILE_W - 1) / TILE_W) * TILE_W; }
+
+constexpr int MAX_SEG = 65;
+constexpr int MAX_BINS = 2048;
+constexpr int POWER_BLOCKS = 512;
+
+// Device-side guard bits (workspace flag word).
+enum { FLAG_OVERFLOW = 1, FLAG_NAN = 2 };
+
+struct Workspace {
+    char *base = nullptr;
+    size_t bytes = 0;
+    int64_t *q = nullptr;        // int64 [N]^3 density; spectrum in place, row stride N complex
+    float2 *f = nullptr;         // 3 x [N][N][Nhp] complex spectra / real force meshes
+    float2 *tw = nullptr;        // twiddles: length L at tw + L, tw[L + m] = exp(-2 pi i m / L)
+    int *flag = nullptr;         // guard bits
+    double *partial = nullptr;   // power-spectrum block partials
+    float *tables = nullptr;     // small per-run tables (IC directions, shells)
+};
+
+struct Ctx {
+    pm_config cfg;
+    int n;                        // mesh size
+    int logn;
+    int64_t P, nc, nn;            // particles, CDM, neutrinos
+    int nseg;
+    std::vector<int64_t> seg_off; // nseg + 1
+    std::vector<double> seg_mass;
+    std::vector<int64_t> seg_q;
+    // background / growth tables (host, FP64)
+    double omega_g, omega_nu0, omega_c, omega_L, kT_nu, m1;
+    std::vector<double> gx, gD, gDp, gDpp;  // growth on a uniform ln a grid
+    double gx0, gdx;
+    // neutrino shells
+    std::vector<double> edges, q_shell, m_shell;
+    std::vector<float> dirs;      // (2 n_fib + 1) x 3
+    Workspace ws;
+    std::vector<float2> tw_host;
+};
+
+// ---- host numerics (host_cosmo.cpp)
+void cosmo_setup(Ctx &c);                         // background, growth table, shells, masses
+double growth_D(const Ctx &c, double a);
+double growth_G(const Ctx &c, double a);
+double E_of_a(const Ctx &c, double a);
+double pk_amplitude(const Ctx &c);                // sigma8 normalisation of k^ns T^2
+
+// ---- launchers (fft.hip)
+struct IcParams {
+    double amp_over_vcell;   // A (D0/D1)^2 / V_cell
+    double box;              // Mpc/h
+    double omh;              // Omega_m h
+    double n_s;
+    double kfs;              // free-streaming wavenumber (h/Mpc), <= 0: none
+    double half_cell;        // phase shift (Mpc/h) or 0
+    double scale;            // 1/M_ic x mesh cells per Mpc/h
+};
+
+hipError_t launch_r2c_rows_i64(int logn, const int64_t *src, int64_t src_stride, float2 *dst,
+                               int64_t dst_stride, int64_t nrows, double scale, double offset,
+                               const float2 *tw, int *flag, hipStream_t s);
+hipError_t launch_r2c_rows_f32(int logn, const float *src, int64_t src_stride, float2 *dst,
+                               int64_t dst_stride, int64_t nrows, const float2 *tw, hipStream_t s);
+hipError_t launch_c2r_rows(int logn, const float2 *src, int64_t src_stride, float *dst,
+                           int64_t dst_stride, int64_t nrows, const float2 *tw, hipStream_t s);
+hipError_t launch_cols(int logn, bool inverse, float2 *base, int64_t stride_l, int64_t stride_o,
+                       int n_o, int n_cb, const float2 *tw, hipStream_t s);
+// axis-0 pass: forward FFT, then per output a multiplier and an inverse FFT.
+enum { MULT_FORCE = 0, MULT_IC = 1, MULT_NONE = 2 };
+hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int64_t s_o, float2 *out0,
+                        float2 *out1, float2 *out2, int64_t o_l, int64_t o_o, int n_cb, double coef,
+                        const IcParams *ic, const float2 *tw, hipStream_t s);
+
+// ---- launchers (paint.hip)
+hipError_t launch_paint(const float *x, int64_t stride, int64_t first, int64_t count, int64_t quantum,
+                        int n, int64_t *mesh, hipStream_t s);
+
+// ---- launchers (particles.hip)
+hipError_t launch_fill_i64(int64_t *p, int64_t count, hipStream_t s);
+hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs_f, int64_t comp_stride,
+                          int n, float *acc, hipStream_t s);
+hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f,
+                                     int64_t comp_stride, int n, float kick, float drift, int *flag,
+                                     hipStream_t s);
+hipError_t launch_copy_real(const float *src, int64_t rs, int n, float *dst, hipStream_t s);
+hipError_t launch_copy_half(const float2 *src, int64_t rs, int n, float2 *dst, hipStream_t s);
+hipError_t launch_load_half(const float2 *src, int n, float2 *dst, int64_t rs, hipStream_t s);
+hipError_t launch_ic_cdm(const float2 *f, int64_t rs, int64_t comp_stride, int nic, int n, double vfac,
+                         float *x, float *p, int64_t P, hipStream_t s);
+hipError_t launch_ic_nu(const float2 *f, int64_t rs, int64_t comp_stride, int nic, int n, int ns,
+                        int n_dir, int n_shell, const float *tables, double vfac, int flip, float *x,
+                        float *p, int64_t P, int64_t nc, hipStream_t s);
+hipError_t launch_power_bin(const float2 *A, const float2 *B, int64_t rs, int n, int nbins, int compensate,
+                            double norm, double kf, double *partial, hipStream_t s);
+hipError_t launch_power_reduce(const double *partial, int nbins, double *out, hipStream_t s);
+
+}  // namespace pm

@@ -134,3 +134,19 @@ def adversarial_positions(n, count, seed):
     x = np.concatenate([faces, top, centres, clump], axis=1)
     x[x >= n] = 0
     return np.ascontiguousarray(x)
+
+
+def synthetic_density_q(n, seed, shift=40):
+    """A clustered int64 fixed-point density mesh (mean about 2^shift per cell):
+    lognormal fluctuations on a smooth random field plus a few dense cells."""
+    rng = np.random.default_rng(seed)
+    g = rng.normal(size=(n, n, n))
+    # smooth by averaging neighbours a few times (no spectral arithmetic)
+    for _ in range(3):
+        g = (g + np.roll(g, 1, 0) + np.roll(g, -1, 0) + np.roll(g, 1, 1) + np.roll(g, -1, 1)
+             + np.roll(g, 1, 2) + np.roll(g, -1, 2)) / 7.0
+    rho = np.exp(2.0 * g)
+    rho /= rho.mean()
+    idx = rng.integers(0, n, size=(3, 8))
+    rho[idx[0], idx[1], idx[2]] += 500.0
+    return np.rint(np.ldexp(rho, shift)).astype(np.int64)
