@@ -1,0 +1,203 @@
+#!/usr/bin/env python
+"""Benchmark of the FastPM-with-neutrinos particle-mesh step on one MI355X.
+
+A step is one pm_step call of a kick-drift-kick run: paint of all CDM and
+neutrino particles, forward FFT, gradient of the inverse Laplacian, three
+inverse FFTs, readout, kick and drift.  The workload is the paper-scale
+configuration: 1024^3 CDM + 128^3 x 70 neutrino particles on a 2048^3 mesh in
+a 1024 Mpc/h box, M_nu = 0.06 eV normal hierarchy as one effective species,
+z = 99 -> 0 in 5 log + 20 linear steps, Zel'dovich initial conditions from
+seeded white noise generated on the GPU.  The default run warms up with the
+first call of the schedule and times the remaining 25 calls.
+
+Prints one JSON line (rank 0) with particle-steps/s, the roofline position of
+the dominant kernel (durations from HIP events recorded around every launch
+on the launch stream during the timed region) and, unless --no-cpu-baseline,
+the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+METRIC = "particle-steps/s at 1024^3 CDM; learned vs plain PM at equal 1% P(k) error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def model_bytes(P, n):
+    """Algorithmic HBM bytes per kernel kind per launch, and per step (fused
+    minimum: one read and one write of each mesh per pass)."""
+    M = n ** 3
+    Mc = n * n * (n // 2 + 1)
+    per_launch = {
+        "r2c_rows": 8 * M + 8 * Mc,       # int64 density in, half spectrum out
+        "cols_fwd": 16 * Mc,
+        "axis0": 8 * Mc + 24 * Mc,        # spectrum in, three force spectra out
+        "cols_inv": 16 * Mc,
+        "c2r_rows": 8 * Mc + 4 * M,
+        "readout_kick_drift": 12 * M + 48 * P,
+    }
+    paint_step = 12 * P + 8 * M           # positions in, int64 mesh written once
+    step = 60 * P + 40 * M + 128 * Mc
+    return per_launch, paint_step, step
+
+
+def cpu_baseline(P_target, n_target):
+    """The oracle as it stands, one step on the C2 shape (512^3 mesh, 19.07M
+    particles, synthetic evolved state), particle and mesh parts timed apart
+    and scaled to the target workload (particle part x P, mesh part x M log M)."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import numpy as np
+    import oracle as O
+    from paper_2007_13394_amd import inputs as I
+    cfg = I.config("C2")
+    s = O.make_sim(cfg)
+    x32, p32 = I.synthetic_state(cfg, seed=99)
+    x, p = x32.astype(np.float64), p32.astype(np.float64)
+    P = x.shape[1]
+    n = cfg["n_mesh"]
+    t0 = time.perf_counter()
+    mesh = O.paint_sim(s, x)
+    t1 = time.perf_counter()
+    F = O.force_mesh(mesh, cfg["shift"], cfg["omega_m"])
+    t2 = time.perf_counter()
+    acc = O.readout(F, x)
+    p += 0.5 * acc
+    x = np.mod(x + 0.1 * p, n)
+    t3 = time.perf_counter()
+    t_part = (t1 - t0) + (t3 - t2)
+    t_mesh = t2 - t1
+    M, Mt = n ** 3, n_target ** 3
+    t_target = t_part * P_target / P + t_mesh * (Mt * math.log(Mt)) / (M * math.log(M))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": P_target / t_target,
+        "unit": "particle-steps/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"one FP64 oracle step on the C2 shape ({n}^3 mesh, {P} particles, synthetic evolved state): "
+                   f"paint+readout+kick/drift {t_part:.2f} s, FFT+Green {t_mesh:.2f} s, scaled to "
+                   f"{P_target} particles (x P) and a {n_target}^3 mesh (x M log M); measured C2 rate "
+                   f"{P / (t_part + t_mesh):.3g} particle-steps/s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=25)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="C3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU slab "
+              "decomposition is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import numpy as np
+    import torch
+    from paper_2007_13394_amd import inputs as I
+    from paper_2007_13394_amd import pm
+    from paper_2007_13394_amd import run as R
+
+    cfg = I.config(args.config)
+    n = cfg["n_mesh"]
+    log(f"[bench] config {args.config}: mesh {n}^3, CDM {cfg['n_cdm']}^3, sites {cfg['n_sites']}^3")
+    ctx = pm.Ctx(pm.make_config(cfg))
+    P = ctx.P
+    log(f"[bench] particles {P}, workspace {ctx.workspace.numel() / 2**30:.1f} GiB")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(cfg["seed"])
+    nc = cfg["n_cdm"]
+    white = torch.randn((nc, nc, nc), generator=gen, device="cuda", dtype=torch.float32)
+    x, p = ctx.particles()
+    t = time.perf_counter()
+    pm.pm_ic(ctx, white, x, p)
+    torch.cuda.synchronize()
+    del white
+    log(f"[bench] initial conditions {time.perf_counter() - t:.2f} s")
+    a, half = R.schedule(cfg["a0"], cfg["n_lin"], cfg["n_log"], cfg["a_mid"])
+    calls = R.kdk_calls(a, half)
+    for i in range(args.warmup):
+        pm.pm_step(ctx, x, p, *calls[i % len(calls)])
+        torch.cuda.synchronize()
+        log(f"[bench] warmup call {i}")
+    pm.pm_trace_begin(ctx, capacity=64 * max(1, args.steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        pm.pm_step(ctx, x, p, *calls[i % len(calls)])
+        if (i - args.warmup) % 5 == 4:
+            log(f"[bench] timed call {i}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    trace = pm.pm_trace_end(ctx)
+    if not bool(torch.isfinite(x).all()) or not bool(torch.isfinite(p).all()):
+        raise RuntimeError("non-finite particle state after the timed steps")
+
+    per_launch, paint_step, step_bytes = model_bytes(P, n)
+    tot = {}
+    cnt = {}
+    for name, ms in trace:
+        tot[name] = tot.get(name, 0.0) + ms
+        cnt[name] = cnt.get(name, 0) + 1
+    K = args.steps
+    kernels = {k: {"ms_per_step": tot[k] / K, "launches_per_step": cnt[k] / K, "avg_ms": tot[k] / cnt[k]}
+               for k in tot}
+    # paint = zero fill + one launch per segment: one unit per step
+    paint_ms = (tot.get("paint", 0.0) + tot.get("fill", 0.0)) / K
+    candidates = {k: v["ms_per_step"] for k, v in kernels.items() if k in per_launch}
+    candidates["paint"] = paint_ms
+    dom = max(candidates, key=candidates.get)
+    if dom == "paint":
+        bytes_unit, ms_unit = paint_step, paint_ms
+    else:
+        bytes_unit, ms_unit = per_launch[dom], kernels[dom]["avg_ms"]
+    achieved = bytes_unit / (ms_unit * 1e-3) / 1e9
+    for k, v in kernels.items():
+        b = per_launch.get(k)
+        if b:
+            v["gbs"] = round(b / (v["avg_ms"] * 1e-3) / 1e9, 1)
+    ms_per_step = elapsed / K * 1e3
+    value = P * K / elapsed
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {cfg['n_cdm']}^3 CDM + {cfg['n_sites']}^3 sites x 70 neutrinos "
+                               f"on a {n}^3 mesh, L={cfg['box']:g} Mpc/h, M_nu={sum(cfg['m_nu']):g} eV, "
+                               f"{cfg['n_log']} log + {cfg['n_lin']} linear steps from z=99, int64 fixed-point paint",
+                   "particles": P, "mesh": n},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "step_roofline": {"model_bytes_per_step": step_bytes,
+                          "frac": round(step_bytes / (HBM_PEAK_GBS * 1e9) / (ms_per_step * 1e-3), 4)},
+        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle sample")
+        del ctx, x, p
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(P, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

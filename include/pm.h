@@ -21,6 +21,12 @@
  *   - Particle order: segment 0 holds the N_c CDM particles in lattice order
  *     ((i0 * n + i1) * n + i2); segment 1 + s holds neutrino shell s, ordered
  *     by site (row-major) then direction.  Each segment has one particle mass.
+ *     This canonical order holds after pm_ic (or pm_reset_order).  Unless
+ *     PM_FLAG_NO_SORT is set (or N < 32 or P >= 2^31), pm_step sorts the
+ *     particles by 16^3-cell mesh tile and leaves x and p in that order; the
+ *     context then tracks each particle's segment (pm_segment_tags) and
+ *     carries an attached id array along (pm_attach_ids).  Every call taking
+ *     particles expects them in the context's current order.
  *   - Momenta are canonical, p = a^2 dx/dt / H0, in mesh-cell units, so that
  *     dx/da = p / (a^3 E) and dp/da = F / (a^2 E).
  *   - The force is F = -grad phi with lap phi = 1.5 Omega_m delta in mesh
@@ -59,6 +65,8 @@ typedef enum {
 enum {
     PM_FLAG_NO_FLIP = 1,   /* keep one direction set on every neutrino site */
     PM_FLAG_NO_GUARDS = 2, /* skip the end-of-call device flag check (no host sync) */
+    PM_FLAG_NO_SORT = 4,   /* keep particles in segment order (pm_step paints with
+                              global atomics and gathers the force: slower) */
 };
 
 /* Simulation parameters (Table 1 of the paper names the counts).  All
@@ -198,6 +206,35 @@ pm_status pm_step(pm_ctx *ctx, float *x, float *p, double a_force, double a_kick
 pm_status pm_power(pm_ctx *ctx, const float *x, int32_t a_lo, int32_t a_hi, int32_t b_lo,
                    int32_t b_hi, int32_t nbins, int32_t compensate, double *k_mean, double *pk,
                    double *n_modes, void *stream);
+
+/* Attach a caller-owned device array of P uint32 ids (or NULL to detach)
+ * that pm_step permutes together with the particles; its initial content is
+ * the caller's (for instance 0..P-1 in canonical order).  Errors: PM_ERR_STATE
+ * when the configuration cannot sort (N < 32 or P >= 2^31). */
+pm_status pm_attach_ids(pm_ctx *ctx, uint32_t *ids);
+
+/* Segment of every particle in the context's current order: tags is a
+ * device uint8 array of P entries, written on `stream`. */
+pm_status pm_segment_tags(pm_ctx *ctx, uint8_t *tags, void *stream);
+
+/* Declare that the particle arrays passed from now on are in canonical
+ * segment order again (as written by pm_ic). */
+pm_status pm_reset_order(pm_ctx *ctx);
+
+/* Launch trace, for measuring kernel durations on the stream they run on.
+ * pm_trace_begin makes every later kernel launch of this context record a
+ * HIP event before and after it on the launch stream (no host waits are
+ * added); at most `capacity` launches are recorded, later ones are not.
+ * pm_trace_end stops recording, waits for the recorded launches, and writes
+ * up to `max` records: kind[i] (see pm_kernel_name) and ms[i], the elapsed
+ * time between the two events of launch i, in launch order; *count receives
+ * the number recorded.  Host arrays.  Errors: PM_ERR_ARG, PM_ERR_STATE (no
+ * trace in progress), PM_ERR_DEVICE. */
+pm_status pm_trace_begin(pm_ctx *ctx, int32_t capacity);
+pm_status pm_trace_end(pm_ctx *ctx, int32_t max, int32_t *kind, float *ms, int32_t *count);
+
+/* Name of a kernel kind reported by pm_trace_end ("paint", "axis0", ...). */
+const char *pm_kernel_name(int32_t kind);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,7 @@ SOURCES = {
     "fft.hip": [],
     "paint.hip": ["-ffp-contract=off"],
     "particles.hip": [],
+    "sort.hip": [],
     "host_cosmo.cpp": ["-ffp-contract=off", "-x", "hip"],
     "host.cpp": ["-x", "hip"],
 }

@@ -179,9 +179,22 @@ struct RowCfg {
 template <int LOGN>
 struct ColCfg {
     static constexpr int N = 1 << LOGN, W = TILE_W, E = N * W;
-    static constexpr int T = (E / 32) > 64 ? (E / 32) : 64;
+    // 16 elements per thread (at least one wavefront): keeps a tile's
+    // register footprint below the 128-VGPR budget of 16 waves per CU.
+    static constexpr int T = (E / 16) > 64 ? ((E / 16) < 1024 ? (E / 16) : 1024) : 64;
     static constexpr int PER = E / T;
 };
+
+// The axis-0 pass keeps part of a spectrum in registers across an inverse
+// transform; stages of radix <= 8 (AX0_MAXB) and 16 elements per thread keep
+// it within the 128-VGPR budget of 16 waves per CU.
+template <int LOGN>
+struct Ax0Cfg {
+    static constexpr int N = 1 << LOGN, W = TILE_W, E = N * W;
+    static constexpr int T = (E / 16) > 64 ? ((E / 16) < 1024 ? (E / 16) : 1024) : 64;
+    static constexpr int PER = E / T;
+};
+constexpr int AX0_MAXB = 3;
 
 // ---------------------------------------------------------------- rows
 template <int LOGN, typename SRC>
@@ -274,41 +287,20 @@ __global__ __launch_bounds__(ColCfg<LOGN>::T) void k_cols(float2 *base, int64_t 
     __shared__ float2 buf[E];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int o = tile / n_cb, cb = tile % n_cb;
-    float2 *p = base + (int64_t)o * stride_o + cb * W;
     const int tid = threadIdx.x;
+    // thread owns column tid % W and rows tid / W + i T / W (T is a multiple of W)
+    float2 *p = base + (int64_t)o * stride_o + cb * W + (tid % W) + (int64_t)(tid / W) * stride_l;
+    const int64_t step = (int64_t)(T / W) * stride_l;
 #pragma unroll
-    for (int i = 0; i < C::PER; i++) {
-        const int e = tid + i * T;
-        buf[e] = p[(int64_t)(e / W) * stride_l + (e % W)];
-    }
+    for (int i = 0; i < C::PER; i++) buf[tid + i * T] = p[i * step];
     __syncthreads();
     fft_from<N, 1, W, T, true, W, 1, INV, 4>(buf, tw + N);
 #pragma unroll
-    for (int i = 0; i < C::PER; i++) {
-        const int e = tid + i * T;
-        p[(int64_t)(e / W) * stride_l + (e % W)] = buf[e];
-    }
+    for (int i = 0; i < C::PER; i++) p[i * step] = buf[tid + i * T];
 }
 
 // ---------------------------------------------------------------- axis 0 + multiplier
 __device__ __forceinline__ int signed_mode(int k, int n) { return k <= n / 2 ? k : k - n; }
-
-// i k_d / k^2 * coef (coef = 1.5 Omega_m / N^3), zero at k = 0 and on the
-// Nyquist plane of component d; k in mesh units.
-__device__ __forceinline__ float2 mult_force(float2 v, int d, int l, int o, int k2, int n, float coef)
-{
-    if (k2 > n / 2) return make_float2(0.f, 0.f);
-    const int n0 = signed_mode(l, n), n1 = signed_mode(o, n), n2 = k2;
-    const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
-    if (nd == n / 2 || nd == -n / 2) return make_float2(0.f, 0.f);
-    const float s = 6.28318530717958648f / (float)n;
-    const float k0 = s * n0, k1 = s * n1, kz = s * n2;
-    const float kk = k0 * k0 + k1 * k1 + kz * kz;
-    if (kk == 0.f) return make_float2(0.f, 0.f);
-    const float kd = d == 0 ? k0 : (d == 1 ? k1 : kz);
-    const float g = coef * kd / kk;
-    return make_float2(-g * v.y, g * v.x);
-}
 
 // Zel'dovich displacement of component d from a white-noise mode (FP64):
 // i k_d / k^2 sqrt(A P(k) / V_cell) [1 + (k/k_fs)^2]^-1 exp(i k.h) / M_ic,
@@ -342,32 +334,89 @@ __device__ __forceinline__ float2 mult_ic(float2 v, int d, int l, int o, int k2,
 }
 
 template <int LOGN, int MODE, int NOUT>
-__global__ __launch_bounds__(ColCfg<LOGN>::T) void k_axis0(const float2 *src, int64_t s_l, int64_t s_o,
+__global__ __launch_bounds__(Ax0Cfg<LOGN>::T) void k_axis0(const float2 *src, int64_t s_l, int64_t s_o,
                                                            float2 *out0, float2 *out1, float2 *out2,
                                                            int64_t o_l, int64_t o_o, int n_cb, float coef,
                                                            IcParams icp, const float2 *__restrict__ tw)
 {
-    using C = ColCfg<LOGN>;
+    using C = Ax0Cfg<LOGN>;
     constexpr int N = C::N, W = C::W, E = C::E, T = C::T, PER = C::PER;
     __shared__ float2 buf[E];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int o = tile / n_cb, cb = tile % n_cb;
-    const float2 *p = src + (int64_t)o * s_o + cb * W;
     const int tid = threadIdx.x;
+    const int col = tid % W, row0 = tid / W;
+    constexpr int RSTEP = T / W;
+    {
+        const float2 *p = src + (int64_t)o * s_o + cb * W + col + (int64_t)row0 * s_l;
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
-        const int e = tid + i * T;
-        buf[e] = p[(int64_t)(e / W) * s_l + (e % W)];
+        for (int i = 0; i < PER; i++) buf[tid + i * T] = p[i * (RSTEP * s_l)];
     }
     __syncthreads();
-    fft_from<N, 1, W, T, true, W, 1, false, 4>(buf, tw + N);
+    fft_from<N, 1, W, T, true, W, 1, false, AX0_MAXB>(buf, tw + N);
+    const int64_t out_off = (int64_t)o * o_o + cb * W + col + (int64_t)row0 * o_l;
+    const int64_t ostep = (int64_t)RSTEP * o_l;
     if constexpr (NOUT == 0) {
-        float2 *q = out0 + (int64_t)o * o_o + cb * W;
+        float2 *q = out0 + out_off;
 #pragma unroll
-        for (int i = 0; i < PER; i++) {
-            const int e = tid + i * T;
-            q[(int64_t)(e / W) * o_l + (e % W)] = buf[e];
+        for (int i = 0; i < PER; i++) q[i * ostep] = buf[tid + i * T];
+    } else if constexpr (MODE == MULT_FORCE) {
+        // Within a column (k1, k2) the axis-1 and axis-2 components are k1 and
+        // k2 times one common transform of T(k) = coef i S / k^2, and the
+        // axis-0 component is the transform of k0 T: two inverse FFTs give
+        // all three outputs.  The inverses run on one half of the tile's
+        // columns at a time while the forward spectrum of the other half waits
+        // in LDS, so a thread keeps only its half's T values in registers.
+        constexpr int HW = W / 2, HE = N * HW, HPER = HE / T > 0 ? HE / T : 1;
+        constexpr int HSTEP = T / HW;
+        if constexpr (HE % T == 0 && T % HW == 0) {
+        const int hcol = tid % HW, hrow0 = tid / HW;
+        const int n1 = signed_mode(o, N);
+        const float s = 6.28318530717958648f / (float)N;
+        const float k1 = s * n1;
+        const float f1 = (n1 == N / 2 || n1 == -N / 2) ? 0.f : k1;
+        const int64_t hstep = (int64_t)HSTEP * o_l;
+#pragma unroll 1
+        for (int h = 0; h < 2; h++) {
+            const int k2 = cb * W + h * HW + hcol;
+            const float kz = s * k2;
+            const float kperp = k1 * k1 + kz * kz;
+            float2 *hb = buf + h * HW;
+            float2 keep[HPER];
+#pragma unroll
+            for (int i = 0; i < HPER; i++) {
+                const int row = hrow0 + i * HSTEP;
+                const int n0 = signed_mode(row, N);
+                const float k0 = s * n0;
+                const float kk = k0 * k0 + kperp;
+                const float2 v = hb[row * W + hcol];
+                const float g = (k2 > N / 2 || kk == 0.f) ? 0.f : coef / kk;
+                keep[i] = make_float2(-g * v.y, g * v.x);                       // T = i g S
+                const float g0 = (n0 == N / 2 || n0 == -N / 2) ? 0.f : k0;
+                hb[row * W + hcol] = make_float2(g0 * keep[i].x, g0 * keep[i].y);   // k0 T
+            }
+            __syncthreads();
+            fft_from<N, 1, HW, T, true, W, 1, true, AX0_MAXB>(hb, tw + N);
+            const int64_t hoff = (int64_t)o * o_o + cb * W + h * HW + hcol + (int64_t)hrow0 * o_l;
+            {
+                float2 *q = out0 + hoff;
+#pragma unroll
+                for (int i = 0; i < HPER; i++) q[i * hstep] = hb[(hrow0 + i * HSTEP) * W + hcol];
+            }
+#pragma unroll
+            for (int i = 0; i < HPER; i++) hb[(hrow0 + i * HSTEP) * W + hcol] = keep[i];
+            __syncthreads();
+            fft_from<N, 1, HW, T, true, W, 1, true, AX0_MAXB>(hb, tw + N);
+            const float f2 = (k2 >= N / 2) ? 0.f : kz;
+            float2 *q1 = out1 + hoff, *q2 = out2 + hoff;
+#pragma unroll
+            for (int i = 0; i < HPER; i++) {
+                const float2 v = hb[(hrow0 + i * HSTEP) * W + hcol];
+                q1[i * hstep] = make_float2(f1 * v.x, f1 * v.y);
+                q2[i * hstep] = make_float2(f2 * v.x, f2 * v.y);
+            }
         }
+        }  // meshes below 16^3 never take the force path (launch_axis0 rejects them)
     } else {
         float2 keep[PER];
 #pragma unroll
@@ -375,20 +424,13 @@ __global__ __launch_bounds__(ColCfg<LOGN>::T) void k_axis0(const float2 *src, in
 #pragma unroll 1
         for (int d = 0; d < NOUT; d++) {
 #pragma unroll
-            for (int i = 0; i < PER; i++) {
-                const int e = tid + i * T;
-                const int l = e / W, k2 = cb * W + (e % W);
-                buf[e] = MODE == MULT_FORCE ? mult_force(keep[i], d, l, o, k2, N, coef)
-                                            : mult_ic(keep[i], d, l, o, k2, N, icp);
-            }
+            for (int i = 0; i < PER; i++)
+                buf[tid + i * T] = mult_ic(keep[i], d, row0 + i * RSTEP, o, cb * W + col, N, icp);
             __syncthreads();
-            fft_from<N, 1, W, T, true, W, 1, true, 4>(buf, tw + N);
-            float2 *q = (d == 0 ? out0 : (d == 1 ? out1 : out2)) + (int64_t)o * o_o + cb * W;
+            fft_from<N, 1, W, T, true, W, 1, true, AX0_MAXB>(buf, tw + N);
+            float2 *q = (d == 0 ? out0 : (d == 1 ? out1 : out2)) + out_off;
 #pragma unroll
-            for (int i = 0; i < PER; i++) {
-                const int e = tid + i * T;
-                q[(int64_t)(e / W) * o_l + (e % W)] = buf[e];
-            }
+            for (int i = 0; i < PER; i++) q[i * ostep] = buf[tid + i * T];
         }
     }
 }
@@ -471,13 +513,14 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
                         const IcParams *ic, const float2 *tw, hipStream_t s)
 {
     const int n = 1 << logn;
+    if (mode == MULT_FORCE && n < 16) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)n * (unsigned)n_cb;
     IcParams icp{};
     if (ic) icp = *ic;
     const float fc = (float)coef;
 #define AX0(LG)                                                                                      \
     {                                                                                                \
-        const dim3 g(nb), b(ColCfg<LG>::T);                                                          \
+        const dim3 g(nb), b(Ax0Cfg<LG>::T);                                                          \
         if (mode == MULT_FORCE)                                                                      \
             hipLaunchKernelGGL((k_axis0<LG, MULT_FORCE, 3>), g, b, 0, s, src, s_l, s_o, out0, out1,  \
                                out2, o_l, o_o, n_cb, fc, icp, tw);                                  \

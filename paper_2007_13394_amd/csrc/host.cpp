@@ -29,6 +29,28 @@ pm_status fail(pm_status st, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(PM_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// Launch with optional event bracketing for per-kernel timing.
+#define LAUNCH(kind, expr)                                                                      \
+    do {                                                                                        \
+        hipEvent_t b_ = nullptr;                                                                \
+        if (c->tracing) HIPCHK(trace_open(c, kind, s, &b_));                                    \
+        HIPCHK(expr);                                                                           \
+        if (b_) HIPCHK(hipEventRecord(b_, s));                                                  \
+    } while (0)
+
+hipError_t trace_open(pm::Ctx *c, int kind, hipStream_t s, hipEvent_t *end)
+{
+    *end = nullptr;
+    if (c->ev_used + 2 > c->ev_pool.size()) return hipSuccess;   // pool full: stop recording
+    hipEvent_t a = c->ev_pool[c->ev_used], b = c->ev_pool[c->ev_used + 1];
+    c->ev_used += 2;
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    c->trace.push_back({kind, a, b});
+    *end = b;
+    return hipSuccess;
+}
+
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -40,18 +62,29 @@ int ilog2i(int v)
 }
 
 struct Layout {
-    size_t q, f, tw, flag, partial, tables, total;
+    size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags0, tags1, ids, koff, key, rank, cnt, bsum, total;
+    int64_t nkeys;
 };
+
+void counts(const pm_config &c, int64_t *P, int64_t *nc, int64_t *nn, int *nseg);
+
+bool sort_capable(const pm_config &c, int64_t P) { return c.n_mesh / pm::TILE >= 2 && P < (int64_t(1) << 31); }
 
 Layout layout(const pm_config &c)
 {
     const int64_t n = c.n_mesh, nhp = pm::half_pad(c.n_mesh);
+    int64_t P, nc, nn;
+    int nseg;
+    counts(c, &P, &nc, &nn, &nseg);
+    const int64_t nt = n / pm::TILE;
     Layout L;
+    L.nkeys = sort_capable(c, P) ? 8 * nt * nt * nt : 0;
     size_t off = 0;
     L.q = off;
     off = align256(off + (size_t)(8 * n * n * n));
     L.f = off;
-    off = align256(off + (size_t)(3 * n * n * nhp * 8));
+    const size_t fbytes = (size_t)(3 * n * n * nhp * 8);
+    off = align256(off + fbytes);
     L.tw = off;
     off = align256(off + (size_t)(2 * n * 8));
     L.flag = off;
@@ -60,6 +93,36 @@ Layout layout(const pm_config &c)
     off = align256(off + (size_t)(pm::POWER_BLOCKS + 1) * 3 * pm::MAX_BINS * 8);
     L.tables = off;
     off = align256(off + (size_t)(3 * (2 * c.n_fib + 1) + 2 * c.n_shell) * 4);
+    L.segtab = off;
+    off = align256(off + (size_t)(2 * pm::MAX_SEG + 1) * 8);
+    L.xs = L.ps = L.tags0 = L.tags1 = L.ids = L.koff = L.key = L.rank = L.cnt = L.bsum = 0;
+    if (L.nkeys > 0) {
+        // tile-sorted particle copies and tags survive the whole step
+        L.xs = off;
+        off = align256(off + (size_t)(12 * P));
+        L.ps = off;
+        off = align256(off + (size_t)(12 * P));
+        L.tags0 = off;
+        off = align256(off + (size_t)P);
+        L.tags1 = off;
+        off = align256(off + (size_t)P);
+        L.ids = off;
+        off = align256(off + (size_t)(4 * P));
+        L.koff = off;
+        off = align256(off + (size_t)(4 * (L.nkeys + 1)));
+        // sort scratch is dead before the FFT writes the force region: alias it there when it fits
+        const size_t nb = (size_t)((L.nkeys + 1 + 2047) / 2048 + 1);
+        const size_t scratch = align256(4 * (size_t)P) * 2 + align256(4 * (size_t)(L.nkeys + 1)) + align256(4 * nb);
+        size_t s0 = L.f;
+        if (scratch > fbytes) {
+            s0 = off;
+            off = align256(off + scratch);
+        }
+        L.key = s0;
+        L.rank = L.key + align256(4 * (size_t)P);
+        L.cnt = L.rank + align256(4 * (size_t)P);
+        L.bsum = L.cnt + align256(4 * (size_t)(L.nkeys + 1));
+    }
     L.total = off;
     return L;
 }
@@ -119,15 +182,45 @@ pm_status check_guards(pm_ctx *c, hipStream_t s)
     return PM_OK;
 }
 
-// Paint every segment of x into the zeroed Q mesh.
+bool sorting_on(const pm_ctx *c) { return c->nkeys > 0 && !(c->cfg.flags & PM_FLAG_NO_SORT); }
+
+// Paint segments [lo, hi) of x (in the context's current particle order)
+// into `mesh` with global atomics; the caller zeroes the mesh.
+pm_status paint_atomic(pm_ctx *c, const float *x, int lo, int hi, int64_t *mesh, hipStream_t s)
+{
+    if (c->permuted) {
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tagged(x, c->P, c->ws.tags[c->cur_tag], lo, hi, c->ws.quanta, c->n,
+                                                    mesh, s));
+    } else {
+        for (int g = lo; g < hi; g++)
+            LAUNCH(pm::K_PAINT, pm::launch_paint(x, c->P, c->seg_off[g], c->seg_off[g + 1] - c->seg_off[g],
+                                                 c->seg_q[g], c->n, mesh, s));
+    }
+    return PM_OK;
+}
+
+// Counting sort of (x, p, tags, ids) by tile key into the workspace copies
+// xs, ps, tags[1 - cur_tag], ids_tmp and the key offsets koff.  p may be NULL.
+pm_status tile_sort(pm_ctx *c, const float *x, const float *p, hipStream_t s)
+{
+    const int64_t K = c->nkeys;
+    LAUNCH(pm::K_FILL, pm::launch_fill_i32(c->ws.cnt, K + 1, s));
+    LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, c->ws.cnt, c->ws.key, c->ws.rank, s));
+    LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt, c->ws.koff, K + 1, c->ws.bsum, s));
+    const uint8_t *tin = c->permuted ? c->ws.tags[c->cur_tag] : nullptr;
+    LAUNCH(pm::K_SORT_SCATTER,
+           pm::launch_sort_scatter(x, p, tin, c->P, c->nseg, c->ws.seg_off, c->ws.key, c->ws.rank, c->ws.koff,
+                                   c->ws.xs, p ? c->ws.ps : nullptr, c->ws.tags[1 - c->cur_tag],
+                                   c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
+    return PM_OK;
+}
+
+// Paint every segment of x into the Q mesh (overwritten).
 pm_status paint_all(pm_ctx *c, const float *x, hipStream_t s)
 {
     const int64_t n = c->n;
-    HIPCHK(pm::launch_fill_i64(c->ws.q, n * n * n, s));
-    for (int g = 0; g < c->nseg; g++)
-        HIPCHK(pm::launch_paint(x, c->P, c->seg_off[g], c->seg_off[g + 1] - c->seg_off[g], c->seg_q[g], c->n,
-                                c->ws.q, s));
-    return PM_OK;
+    LAUNCH(pm::K_FILL, pm::launch_fill_i64(c->ws.q, n * n * n, s));
+    return paint_atomic(c, x, 0, c->nseg, c->ws.q, s);
 }
 
 // From the int64 density at `src` (row stride n int64) to the three real
@@ -142,16 +235,16 @@ pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s)
     const int64_t cs = n2 * nhp;
     const double scale = ldexp(1.0, -c->cfg.shift);
     // axis 2: density contrast, real-to-complex rows (in place when src is Q)
-    HIPCHK(pm::launch_r2c_rows_i64(lg, src, n, S, n, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, src, n, S, n, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
     // axis 1
-    HIPCHK(pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
     // axis 0 forward, gradient of the inverse Laplacian, axis 0 inverse x 3
     const double coef = 1.5 * c->cfg.omega_m / ((double)n2 * n);
-    HIPCHK(pm::launch_axis0(lg, pm::MULT_FORCE, S, n2, n, F, F + cs, F + 2 * cs, n * nhp, nhp, ncb, coef, nullptr,
+    LAUNCH(pm::K_AXIS0, pm::launch_axis0(lg, pm::MULT_FORCE, S, n2, n, F, F + cs, F + 2 * cs, n * nhp, nhp, ncb, coef, nullptr,
                             c->ws.tw, s));
     for (int d = 0; d < 3; d++) {
-        HIPCHK(pm::launch_cols(lg, true, F + d * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
-        HIPCHK(pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp, n2,
+        LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + d * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp, n2,
                                    c->ws.tw, s));
     }
     return PM_OK;
@@ -165,9 +258,9 @@ pm_status forward_density(pm_ctx *c, int64_t *q, double scale, hipStream_t s)
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
     const int ncb = (int)(nhp / pm::TILE_W);
     float2 *S = reinterpret_cast<float2 *>(q);
-    HIPCHK(pm::launch_r2c_rows_i64(lg, q, n, S, n, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
-    HIPCHK(pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
-    HIPCHK(pm::launch_axis0(lg, pm::MULT_NONE, S, n2, n, S, nullptr, nullptr, n2, n, ncb, 0.0, nullptr, c->ws.tw, s));
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, q, n, S, n, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_AXIS0, pm::launch_axis0(lg, pm::MULT_NONE, S, n2, n, S, nullptr, nullptr, n2, n, ncb, 0.0, nullptr, c->ws.tw, s));
     return PM_OK;
 }
 
@@ -217,6 +310,21 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
     c->ws.flag = reinterpret_cast<int *>(b + L.flag);
     c->ws.partial = reinterpret_cast<double *>(b + L.partial);
     c->ws.tables = reinterpret_cast<float *>(b + L.tables);
+    c->ws.seg_off = reinterpret_cast<int64_t *>(b + L.segtab);
+    c->ws.quanta = c->ws.seg_off + (pm::MAX_SEG + 1);
+    c->nkeys = L.nkeys;
+    if (L.nkeys > 0) {
+        c->ws.xs = reinterpret_cast<float *>(b + L.xs);
+        c->ws.ps = reinterpret_cast<float *>(b + L.ps);
+        c->ws.tags[0] = reinterpret_cast<uint8_t *>(b + L.tags0);
+        c->ws.tags[1] = reinterpret_cast<uint8_t *>(b + L.tags1);
+        c->ws.ids_tmp = reinterpret_cast<uint32_t *>(b + L.ids);
+        c->ws.koff = reinterpret_cast<int *>(b + L.koff);
+        c->ws.key = reinterpret_cast<int *>(b + L.key);
+        c->ws.rank = reinterpret_cast<int *>(b + L.rank);
+        c->ws.cnt = reinterpret_cast<int *>(b + L.cnt);
+        c->ws.bsum = reinterpret_cast<int *>(b + L.bsum);
+    }
     // twiddles for every power-of-two length L <= N: tw[L + m] = exp(-2 pi i m / L)
     const int n = c->n;
     c->tw_host.assign(2 * (size_t)n, make_float2(0.f, 0.f));
@@ -238,6 +346,12 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !tables.empty())
         e = hipMemcpyAsync(c->ws.tables, tables.data(), sizeof(float) * tables.size(), hipMemcpyHostToDevice, s);
+    c->segtab_host.assign(2 * pm::MAX_SEG + 1, 0);
+    for (int g = 0; g <= c->nseg; g++) c->segtab_host[g] = c->seg_off[g];
+    for (int g = 0; g < c->nseg; g++) c->segtab_host[pm::MAX_SEG + 1 + g] = c->seg_q[g];
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws.seg_off, c->segtab_host.data(), sizeof(int64_t) * c->segtab_host.size(),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws.flag, 0, 256, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -248,7 +362,57 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
     return PM_OK;
 }
 
-void pm_free(pm_ctx *ctx) { delete ctx; }
+void pm_free(pm_ctx *ctx)
+{
+    if (!ctx) return;
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+static const char *kKernelNames[pm::K_COUNT] = {
+    "fill",      "paint",        "r2c_rows",     "cols_fwd",   "axis0",      "cols_inv",   "c2r_rows",
+    "readout_kick_drift", "readout", "power_bin", "power_reduce", "ic_particles", "copy", "sort_count",
+    "sort_scan", "sort_scatter"};
+
+const char *pm_kernel_name(int32_t kind)
+{
+    return (kind >= 0 && kind < pm::K_COUNT) ? kKernelNames[kind] : "unknown";
+}
+
+pm_status pm_trace_begin(pm_ctx *c, int32_t capacity)
+{
+    if (!c || capacity < 1 || capacity > (1 << 20)) return fail(PM_ERR_ARG, "capacity must be in [1, 2^20]");
+    while ((int64_t)c->ev_pool.size() < 2 * (int64_t)capacity) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    c->ev_used = 0;
+    c->trace.clear();
+    c->tracing = true;
+    return PM_OK;
+}
+
+pm_status pm_trace_end(pm_ctx *c, int32_t max, int32_t *kind, float *ms, int32_t *count)
+{
+    if (!c || max < 0 || (max > 0 && (!kind || !ms)) || !count) return fail(PM_ERR_ARG, "bad trace arguments");
+    if (!c->tracing) return fail(PM_ERR_STATE, "no trace in progress");
+    c->tracing = false;
+    *count = (int32_t)c->trace.size();
+    for (size_t i = 0; i < c->trace.size(); i++) {
+        const pm::TraceRec &r = c->trace[i];
+        HIPCHK(hipEventSynchronize(r.b));
+        if ((int32_t)i < max) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+            kind[i] = r.kind;
+            ms[i] = t;
+        }
+    }
+    c->trace.clear();
+    c->ev_used = 0;
+    return PM_OK;
+}
 
 pm_status pm_segments(const pm_ctx *c, int64_t *offsets, double *mass, int64_t *quantum)
 {
@@ -303,6 +467,7 @@ pm_status pm_kdk_factors(const pm_ctx *c, double a_force, double a_kick0, double
 pm_status pm_ic(pm_ctx *c, const float *white, float *x, float *p, void *stream)
 {
     if (!c || !white || !x || !p) return fail(PM_ERR_ARG, "NULL argument to pm_ic");
+    c->permuted = false;
     hipStream_t s = S(stream);
     const pm_config &g = c->cfg;
     const int nic = g.n_cdm, lg = ilog2i(nic), n = c->n;
@@ -312,8 +477,8 @@ pm_status pm_ic(pm_ctx *c, const float *white, float *x, float *p, void *stream)
     float2 *F = c->ws.f;
     const int64_t cs = n2 * nhp;
     // white-noise spectrum (rows, then axis 1); axis 0 is done per output
-    HIPCHK(pm::launch_r2c_rows_f32(lg, white, nic, S0, nic, n2, c->ws.tw, s));
-    HIPCHK(pm::launch_cols(lg, false, S0, nic, n2, nic, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, white, nic, S0, nic, n2, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S0, nic, n2, nic, ncb, c->ws.tw, s));
     const double a0 = g.a0;
     const double D0 = pm::growth_D(*c, a0), D1 = pm::growth_D(*c, 1.0), G0 = pm::growth_G(*c, a0);
     pm::IcParams ip{};
@@ -330,17 +495,17 @@ pm_status pm_ic(pm_ctx *c, const float *white, float *x, float *p, void *stream)
             ip.kfs = 0.82 * sqrt(c->omega_L + g.omega_m / (a0 * a0 * a0)) * a0 * a0 * c->m1;
             ip.half_cell = 0.5 * g.box / nic;
         }
-        HIPCHK(pm::launch_axis0(lg, pm::MULT_IC, S0, n2, nic, F, F + cs, F + 2 * cs, nic * nhp, nhp, ncb, 0.0, &ip,
+        LAUNCH(pm::K_AXIS0, pm::launch_axis0(lg, pm::MULT_IC, S0, n2, nic, F, F + cs, F + 2 * cs, nic * nhp, nhp, ncb, 0.0, &ip,
                                 c->ws.tw, s));
         for (int d = 0; d < 3; d++) {
-            HIPCHK(pm::launch_cols(lg, true, F + d * cs, nhp, nic * nhp, nic, ncb, c->ws.tw, s));
-            HIPCHK(pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp, n2,
+            LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + d * cs, nhp, nic * nhp, nic, ncb, c->ws.tw, s));
+            LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp, n2,
                                        c->ws.tw, s));
         }
         if (pass == 0)
-            HIPCHK(pm::launch_ic_cdm(F, nhp, cs, nic, n, vfac, x, p, c->P, s));
+            LAUNCH(pm::K_IC_PARTICLES, pm::launch_ic_cdm(F, nhp, cs, nic, n, vfac, x, p, c->P, s));
         else
-            HIPCHK(pm::launch_ic_nu(F, nhp, cs, nic, n, g.n_sites, 2 * g.n_fib + 1, g.n_shell, c->ws.tables, vfac,
+            LAUNCH(pm::K_IC_PARTICLES, pm::launch_ic_nu(F, nhp, cs, nic, n, g.n_sites, 2 * g.n_fib + 1, g.n_shell, c->ws.tables, vfac,
                                     (g.flags & PM_FLAG_NO_FLIP) ? 0 : 1, x, p, c->P, c->nc, s));
     }
     return PM_OK;
@@ -351,7 +516,8 @@ pm_status pm_paint_q(pm_ctx *c, const float *x, int64_t stride, int64_t first, i
 {
     if (!c || !x || !mesh_q) return fail(PM_ERR_ARG, "NULL argument to pm_paint_q");
     if (first < 0 || count < 0 || first + count > stride) return fail(PM_ERR_ARG, "particle range outside stride");
-    HIPCHK(pm::launch_paint(x, stride, first, count, quantum, c->n, mesh_q, S(stream)));
+    hipStream_t s = S(stream);
+    LAUNCH(pm::K_PAINT, pm::launch_paint(x, stride, first, count, quantum, c->n, mesh_q, s));
     return PM_OK;
 }
 
@@ -359,10 +525,19 @@ pm_status pm_paint(pm_ctx *c, const float *x, int32_t seg_lo, int32_t seg_hi, in
 {
     if (!c || !x || !mesh_q) return fail(PM_ERR_ARG, "NULL argument to pm_paint");
     if (seg_lo < 0 || seg_hi > c->nseg || seg_lo > seg_hi) return fail(PM_ERR_ARG, "bad segment range");
-    for (int g = seg_lo; g < seg_hi; g++)
-        HIPCHK(pm::launch_paint(x, c->P, c->seg_off[g], c->seg_off[g + 1] - c->seg_off[g], c->seg_q[g], c->n,
-                                mesh_q, S(stream)));
-    return PM_OK;
+    hipStream_t s = S(stream);
+    if (seg_lo == seg_hi) return PM_OK;
+    if (sorting_on(c) && mesh_q != c->ws.q) {
+        // tile sort into the workspace copies, tile paint into Q, add into the caller's mesh
+        pm_status st = tile_sort(c, x, nullptr, s);
+        if (st != PM_OK) return st;
+        const int64_t n = c->n;
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, c->ws.tags[1 - c->cur_tag], c->P, c->ws.koff,
+                                                   c->ws.quanta, c->nseg, seg_lo, seg_hi, c->n, c->ws.q, s));
+        LAUNCH(pm::K_COPY, pm::launch_add_i64(c->ws.q, mesh_q, n * n * n, s));
+        return PM_OK;
+    }
+    return paint_atomic(c, x, seg_lo, seg_hi, mesh_q, s);
 }
 
 pm_status pm_fft_r2c(pm_ctx *c, const float *real, float *out, void *stream)
@@ -373,10 +548,10 @@ pm_status pm_fft_r2c(pm_ctx *c, const float *real, float *out, void *stream)
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
     const int ncb = (int)(nhp / pm::TILE_W);
     float2 *S0 = reinterpret_cast<float2 *>(c->ws.q);
-    HIPCHK(pm::launch_r2c_rows_f32(lg, real, n, S0, n, n2, c->ws.tw, s));
-    HIPCHK(pm::launch_cols(lg, false, S0, n, n2, n, ncb, c->ws.tw, s));
-    HIPCHK(pm::launch_cols(lg, false, S0, n2, n, n, ncb, c->ws.tw, s));
-    HIPCHK(pm::launch_copy_half(S0, n, n, reinterpret_cast<float2 *>(out), s));
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, real, n, S0, n, n2, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S0, n, n2, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S0, n2, n, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COPY, pm::launch_copy_half(S0, n, n, reinterpret_cast<float2 *>(out), s));
     return PM_OK;
 }
 
@@ -388,11 +563,11 @@ pm_status pm_fft_c2r(pm_ctx *c, const float *spec, float *real, void *stream)
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
     const int ncb = (int)(nhp / pm::TILE_W);
     float2 *F = c->ws.f;
-    HIPCHK(pm::launch_load_half(reinterpret_cast<const float2 *>(spec), n, F, nhp, s));
-    HIPCHK(pm::launch_cols(lg, true, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
-    HIPCHK(pm::launch_cols(lg, true, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
-    HIPCHK(pm::launch_c2r_rows(lg, F, nhp, reinterpret_cast<float *>(F), 2 * nhp, n2, c->ws.tw, s));
-    HIPCHK(pm::launch_copy_real(reinterpret_cast<const float *>(F), 2 * nhp, n, real, s));
+    LAUNCH(pm::K_COPY, pm::launch_load_half(reinterpret_cast<const float2 *>(spec), n, F, nhp, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F, nhp, reinterpret_cast<float *>(F), 2 * nhp, n2, c->ws.tw, s));
+    LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(F), 2 * nhp, n, real, s));
     return PM_OK;
 }
 
@@ -404,7 +579,7 @@ pm_status pm_force_mesh(pm_ctx *c, const int64_t *mesh_q, float *out, void *stre
     if (st != PM_OK) return st;
     const int64_t n = c->n, nhp = pm::half_pad(c->n), cs = n * n * nhp;
     for (int d = 0; d < 3; d++)
-        HIPCHK(pm::launch_copy_real(reinterpret_cast<const float *>(c->ws.f + d * cs), 2 * nhp, c->n,
+        LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(c->ws.f + d * cs), 2 * nhp, c->n,
                                     out + d * n * n * n, s));
     return check_guards(c, s);
 }
@@ -417,7 +592,7 @@ pm_status pm_force(pm_ctx *c, const float *x, float *acc, void *stream)
     if (st == PM_OK) st = solve(c, c->ws.q, s);
     if (st != PM_OK) return st;
     const int64_t n = c->n, nhp = pm::half_pad(c->n);
-    HIPCHK(pm::launch_readout(x, c->P, c->ws.f, nhp, n * n * nhp, c->n, acc, s));
+    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, c->ws.f, nhp, n * n * nhp, c->n, acc, s));
     return check_guards(c, s);
 }
 
@@ -429,13 +604,56 @@ pm_status pm_step(pm_ctx *c, float *x, float *p, double a_force, double a_kick0,
     pm_status st = pm_kdk_factors(c, a_force, a_kick0, a_kick1, a_drift1, &kick, &drift);
     if (st != PM_OK) return st;
     hipStream_t s = S(stream);
+    const int64_t n = c->n, nhp = pm::half_pad(c->n);
+    if (sorting_on(c)) {
+        // sort by tile, paint tile by tile, solve, read out tile by tile into
+        // the caller's arrays, which then hold the particles in sorted order
+        st = tile_sort(c, x, p, s);
+        if (st != PM_OK) return st;
+        const uint8_t *tags = c->ws.tags[1 - c->cur_tag];
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, tags, c->P, c->ws.koff, c->ws.quanta, c->nseg, 0,
+                                                   c->nseg, c->n, c->ws.q, s));
+        st = solve(c, c->ws.q, s);
+        if (st != PM_OK) return st;
+        LAUNCH(pm::K_READOUT_KD,
+               pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * n * nhp, c->n,
+                                           (float)kick, (float)drift, x, p, c->ws.ids_tmp, c->ids, c->ws.flag, s));
+        c->cur_tag = 1 - c->cur_tag;
+        c->permuted = true;
+        return check_guards(c, s);
+    }
     st = paint_all(c, x, s);
     if (st == PM_OK) st = solve(c, c->ws.q, s);
     if (st != PM_OK) return st;
-    const int64_t n = c->n, nhp = pm::half_pad(c->n);
-    HIPCHK(pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, n * n * nhp, c->n, (float)kick, (float)drift,
-                                         c->ws.flag, s));
+    LAUNCH(pm::K_READOUT_KD, pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, n * n * nhp, c->n, (float)kick,
+                                                           (float)drift, c->ws.flag, s));
     return check_guards(c, s);
+}
+
+pm_status pm_attach_ids(pm_ctx *c, uint32_t *ids)
+{
+    if (!c) return fail(PM_ERR_ARG, "ctx is NULL");
+    if (ids && c->nkeys == 0) return fail(PM_ERR_STATE, "ids need a configuration that supports tile sorting");
+    c->ids = ids;
+    return PM_OK;
+}
+
+pm_status pm_segment_tags(pm_ctx *c, uint8_t *tags, void *stream)
+{
+    if (!c || !tags) return fail(PM_ERR_ARG, "NULL argument to pm_segment_tags");
+    hipStream_t s = S(stream);
+    if (c->permuted)
+        LAUNCH(pm::K_COPY, hipMemcpyAsync(tags, c->ws.tags[c->cur_tag], (size_t)c->P, hipMemcpyDeviceToDevice, s));
+    else
+        LAUNCH(pm::K_COPY, pm::launch_tags_canonical(tags, c->P, c->nseg, c->ws.seg_off, s));
+    return PM_OK;
+}
+
+pm_status pm_reset_order(pm_ctx *c)
+{
+    if (!c) return fail(PM_ERR_ARG, "ctx is NULL");
+    c->permuted = false;
+    return PM_OK;
 }
 
 pm_status pm_power(pm_ctx *c, const float *x, int32_t a_lo, int32_t a_hi, int32_t b_lo, int32_t b_hi,
@@ -453,24 +671,24 @@ pm_status pm_power(pm_ctx *c, const float *x, int32_t a_lo, int32_t a_hi, int32_
         for (int g = lo; g < hi; g++) tot += (double)(c->seg_off[g + 1] - c->seg_off[g]) * (double)c->seg_q[g];
         return (double)M / tot;
     };
-    HIPCHK(pm::launch_fill_i64(c->ws.q, M, s));
-    pm_status st = pm_paint(c, x, a_lo, a_hi, c->ws.q, stream);
+    LAUNCH(pm::K_FILL, pm::launch_fill_i64(c->ws.q, M, s));
+    pm_status st = paint_atomic(c, x, a_lo, a_hi, c->ws.q, s);
     if (st == PM_OK) st = forward_density(c, c->ws.q, scale_of(a_lo, a_hi), s);
     if (st != PM_OK) return st;
     const float2 *A = reinterpret_cast<const float2 *>(c->ws.q), *B = A;
     if (a_lo != b_lo || a_hi != b_hi) {
         int64_t *qb = reinterpret_cast<int64_t *>(c->ws.f);
-        HIPCHK(pm::launch_fill_i64(qb, M, s));
-        st = pm_paint(c, x, b_lo, b_hi, qb, stream);
+        LAUNCH(pm::K_FILL, pm::launch_fill_i64(qb, M, s));
+        st = paint_atomic(c, x, b_lo, b_hi, qb, s);
         if (st == PM_OK) st = forward_density(c, qb, scale_of(b_lo, b_hi), s);
         if (st != PM_OK) return st;
         B = reinterpret_cast<const float2 *>(qb);
     }
     const double V = pow(c->cfg.box, 3);
     double *out = c->ws.partial + (size_t)pm::POWER_BLOCKS * 3 * pm::MAX_BINS;
-    HIPCHK(pm::launch_power_bin(A, B, n, n, nbins, compensate, V / ((double)M * (double)M), 2.0 * M_PI / c->cfg.box,
+    LAUNCH(pm::K_POWER_BIN, pm::launch_power_bin(A, B, n, n, nbins, compensate, V / ((double)M * (double)M), 2.0 * M_PI / c->cfg.box,
                                 c->ws.partial, s));
-    HIPCHK(pm::launch_power_reduce(c->ws.partial, nbins, out, s));
+    LAUNCH(pm::K_POWER_REDUCE, pm::launch_power_reduce(c->ws.partial, nbins, out, s));
     std::vector<double> h(3 * (size_t)nbins);
     HIPCHK(hipMemcpyAsync(h.data(), out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

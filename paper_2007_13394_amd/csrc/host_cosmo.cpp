@@ -59,13 +59,16 @@ double asimp_rec(const std::function<double(double)> &f, double a, double b, dou
            asimp_rec(f, m, b, fm, frm, fb, right, 0.5 * eps, depth - 1);
 }
 
-// Adaptive Simpson to absolute tolerance eps.
-double asimpson(const std::function<double(double)> &f, double a, double b, double eps)
+// Adaptive Simpson to a relative tolerance `rel` of the integral (the scale
+// comes from a 64-panel composite estimate), at most 2^30 subdivisions deep.
+double asimpson(const std::function<double(double)> &f, double a, double b, double rel)
 {
     if (b <= a) return 0.0;
+    const double scale = fabs(simpson(f, a, b, 64));
+    const double eps = rel * scale + 1e-300;
     const double fa = f(a), fb = f(b), fm = f(0.5 * (a + b));
     const double whole = (b - a) / 6.0 * (fa + 4 * fm + fb);
-    return asimp_rec(f, a, b, fa, fm, fb, whole, eps, 48);
+    return asimp_rec(f, a, b, fa, fm, fb, whole, eps, 30);
 }
 
 struct FTable {
@@ -278,10 +281,10 @@ void cosmo_setup(Ctx &c)
         const double qmax = 30.0 / amin;
         auto gq = [&](double q) { return q * ftilde(alpha, q); };
         // cumulative of g on a fine grid, then bisection inside the bracketing cell
-        const int ng = 20000;
+        const int ng = 4096;
         const double hq = qmax / ng;
         std::vector<double> cum(ng + 1, 0.0);
-        for (int i = 0; i < ng; i++) cum[i + 1] = cum[i] + asimpson(gq, i * hq, (i + 1) * hq, 1e-17);
+        for (int i = 0; i < ng; i++) cum[i + 1] = cum[i] + simpson(gq, i * hq, (i + 1) * hq, 16);
         const double gtot = cum[ng];
         const int ns = g.n_shell;
         c.edges.assign(ns + 1, 0.0);
@@ -292,7 +295,7 @@ void cosmo_setup(Ctx &c)
             double lo = i * hq, hi = (i + 1) * hq;
             for (int it = 0; it < 100; it++) {
                 const double mid = 0.5 * (lo + hi);
-                const double v = cum[i] + asimpson(gq, i * hq, mid, 1e-17);
+                const double v = cum[i] + asimpson(gq, i * hq, mid, 1e-14);
                 (v < target ? lo : hi) = mid;
             }
             c.edges[s] = 0.5 * (lo + hi);
@@ -302,8 +305,8 @@ void cosmo_setup(Ctx &c)
         for (int s = 0; s < ns; s++) {
             auto f2 = [&](double q) { return q * q * ftilde(alpha, q); };
             auto f4 = [&](double q) { return q * q * q * q * ftilde(alpha, q); };
-            m2[s] = asimpson(f2, c.edges[s], c.edges[s + 1], 1e-16);
-            m4[s] = asimpson(f4, c.edges[s], c.edges[s + 1], 1e-15);
+            m2[s] = asimpson(f2, c.edges[s], c.edges[s + 1], 1e-14);
+            m4[s] = asimpson(f4, c.edges[s], c.edges[s + 1], 1e-14);
             ntot += m2[s];
         }
         for (int s = 0; s < ns; s++) {

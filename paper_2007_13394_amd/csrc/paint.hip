@@ -15,48 +15,138 @@
 namespace pm {
 namespace {
 
+// Cells and integer quanta of one particle's eight corners (corner order:
+// axis 2 fastest).  Every kernel that paints uses this, so a particle's
+// split is identical whichever kernel or workgroup computes it.
+__device__ __forceinline__ void cic_quanta(float u0, float u1, float u2, long long quantum, int mask,
+                                           int c[3][2], long long q[8])
+{
+    const float u[3] = {u0, u1, u2};
+    double w[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const float f = floorf(u[d]);
+        const int id = (int)f;
+        const double dd = (double)(u[d] - f);
+        w[d][0] = 1.0 - dd;
+        w[d][1] = dd;
+        c[d][0] = id & mask;
+        c[d][1] = (id + 1) & mask;
+    }
+    const double qd = (double)quantum;
+    long long acc = 0;
+    int corner = 0;
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int e = 0; e < 2; e++, corner++) {
+                if (corner < 7) {
+                    const double wq = ((w[0][a] * w[1][b]) * w[2][e]) * qd;
+                    q[corner] = (long long)__builtin_rint(wq);
+                    acc += q[corner];
+                } else {
+                    q[corner] = quantum - acc;
+                }
+            }
+}
+
+__device__ __forceinline__ void add_corners(const int c[3][2], const long long q[8], int n, unsigned long long *mesh)
+{
+    int corner = 0;
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int e = 0; e < 2; e++, corner++) {
+                const int64_t idx = ((int64_t)c[0][a] * n + c[1][b]) * n + c[2][e];
+                __hip_atomic_fetch_add(mesh + idx, (unsigned long long)q[corner], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+}
+
 __global__ __launch_bounds__(256) void k_paint(const float *__restrict__ x, int64_t stride, int64_t first,
                                                int64_t count, long long quantum, int n,
                                                unsigned long long *mesh)
 {
-    const double qd = (double)quantum;
-    const int mask = n - 1;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = first + t;
         int c[3][2];
-        double w[3][2];
+        long long q[8];
+        cic_quanta(x[i], x[stride + i], x[2 * stride + i], quantum, n - 1, c, q);
+        add_corners(c, q, n, mesh);
+    }
+}
+
+// Particles in any order, each with its segment tag; segments [lo, hi) only.
+__global__ __launch_bounds__(256) void k_paint_tagged(const float *__restrict__ x, int64_t P,
+                                                      const uint8_t *__restrict__ tags, int lo, int hi,
+                                                      const int64_t *__restrict__ quanta, int n,
+                                                      unsigned long long *mesh)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = tags[i];
+        if (g < lo || g >= hi) continue;
+        int c[3][2];
+        long long q[8];
+        cic_quanta(x[i], x[P + i], x[2 * P + i], (long long)quanta[g], n - 1, c, q);
+        add_corners(c, q, n, mesh);
+    }
+}
+
+// One workgroup per TILE^3 tile of the mesh, particles sorted by tile and
+// face flags (koff: offsets per key 8 * tile + flags).  The tile's cells get
+// corners from its own particles and from particles of the seven lower
+// neighbour tiles whose flags say a +1 corner crosses into this tile.  The
+// sums are formed with LDS atomics and the tile is written once with plain
+// stores, so the mesh needs no zero fill and no global atomics.
+__global__ __launch_bounds__(256) void k_paint_tiles(const float *__restrict__ xs, const uint8_t *__restrict__ tags,
+                                                     int64_t P, const int *__restrict__ koff,
+                                                     const int64_t *__restrict__ quanta, int nseg, int lo, int hi,
+                                                     int n, unsigned long long *mesh)
+{
+    __shared__ unsigned long long acc[TILE * TILE * TILE];
+    __shared__ long long qtab[MAX_SEG];
+    const int nt = n / TILE, mask = n - 1;
+    const int t = blockIdx.x;
+    const int t0 = t / (nt * nt), t1 = (t / nt) % nt, t2 = t % nt;
+    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += blockDim.x) acc[i] = 0;
+    for (int i = threadIdx.x; i < nseg; i += blockDim.x) qtab[i] = quanta[i];
+    __syncthreads();
+    for (int e = 0; e < 8; e++) {
+        const int s0 = (t0 - (e & 1) + nt) % nt, s1 = (t1 - ((e >> 1) & 1) + nt) % nt,
+                  s2 = (t2 - ((e >> 2) & 1) + nt) % nt;
+        const int tn = (s0 * nt + s1) * nt + s2;
+        for (int f = 0; f < 8; f++) {
+            if ((f & e) != e) continue;
+            const int beg = koff[tn * 8 + f], end = koff[tn * 8 + f + 1];
+            for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+                const int g = tags[i];
+                if (g < lo || g >= hi) continue;
+                int c[3][2];
+                long long q[8];
+                cic_quanta(xs[i], xs[P + i], xs[2 * P + i], (long long)qtab[g], mask, c, q);
+                int corner = 0;
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-            const float u = x[d * stride + i];
-            const float f = floorf(u);
-            const int id = (int)f;
-            const double dd = (double)(u - f);
-            w[d][0] = 1.0 - dd;
-            w[d][1] = dd;
-            c[d][0] = id & mask;
-            c[d][1] = (id + 1) & mask;
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int b = 0; b < 2; b++)
+#pragma unroll
+                        for (int d = 0; d < 2; d++, corner++) {
+                            const int l0 = c[0][a] - t0 * TILE, l1 = c[1][b] - t1 * TILE, l2 = c[2][d] - t2 * TILE;
+                            if ((unsigned)l0 < TILE && (unsigned)l1 < TILE && (unsigned)l2 < TILE)
+                                atomicAdd(&acc[(l0 * TILE + l1) * TILE + l2], (unsigned long long)q[corner]);
+                        }
+            }
         }
-        long long acc = 0;
-        int corner = 0;
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-            for (int b = 0; b < 2; b++)
-#pragma unroll
-                for (int e = 0; e < 2; e++, corner++) {
-                    long long q;
-                    if (corner < 7) {
-                        const double wq = ((w[0][a] * w[1][b]) * w[2][e]) * qd;
-                        q = (long long)__builtin_rint(wq);
-                        acc += q;
-                    } else {
-                        q = quantum - acc;
-                    }
-                    const int64_t idx = ((int64_t)c[0][a] * n + c[1][b]) * n + c[2][e];
-                    __hip_atomic_fetch_add(mesh + idx, (unsigned long long)q, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += blockDim.x) {
+        const int l0 = i / (TILE * TILE), l1 = (i / TILE) % TILE, l2 = i % TILE;
+        mesh[((int64_t)(t0 * TILE + l0) * n + (t1 * TILE + l1)) * n + (t2 * TILE + l2)] = acc[i];
     }
 }
 
@@ -70,6 +160,28 @@ hipError_t launch_paint(const float *x, int64_t stride, int64_t first, int64_t c
     if (blocks > 65536 * 8) blocks = 65536 * 8;
     hipLaunchKernelGGL(k_paint, dim3((unsigned)blocks), dim3(256), 0, s, x, stride, first, count,
                        (long long)quantum, n, reinterpret_cast<unsigned long long *>(mesh));
+    return hipGetLastError();
+}
+
+hipError_t launch_paint_tagged(const float *x, int64_t P, const uint8_t *tags, int seg_lo, int seg_hi,
+                               const int64_t *quanta, int n, int64_t *mesh, hipStream_t s)
+{
+    int64_t blocks = (P + 255) / 256;
+    if (blocks > 65536 * 8) blocks = 65536 * 8;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_paint_tagged, dim3((unsigned)blocks), dim3(256), 0, s, x, P, tags, seg_lo, seg_hi, quanta,
+                       n, reinterpret_cast<unsigned long long *>(mesh));
+    return hipGetLastError();
+}
+
+hipError_t launch_paint_tiles(const float *xs, const uint8_t *tags, int64_t P, const int *koff,
+                              const int64_t *quanta, int nseg, int seg_lo, int seg_hi, int n, int64_t *mesh,
+                              hipStream_t s)
+{
+    const int nt = n / TILE;
+    if (nt < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_paint_tiles, dim3((unsigned)(nt * nt * nt)), dim3(256), 0, s, xs, tags, P, koff, quanta,
+                       nseg, seg_lo, seg_hi, n, reinterpret_cast<unsigned long long *>(mesh));
     return hipGetLastError();
 }
 

@@ -103,6 +103,93 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(float *x, float *p, 
     if (bad) atomicOr(flag, FLAG_NAN);
 }
 
+// One workgroup per TILE^3 tile: the three force meshes over the tile and its
+// +1 halo are staged in LDS, then every particle sorted into the tile is read
+// out from LDS, kicked and drifted; results go to the caller's arrays at the
+// particle's sorted index (with its id, when ids are attached).
+__global__ __launch_bounds__(256) void k_readout_kd_tiles(const float *__restrict__ xs, const float *__restrict__ ps,
+                                                          int64_t P, const int *__restrict__ koff,
+                                                          const float *__restrict__ F, int64_t rs, int64_t cs, int n,
+                                                          float kick, float drift, float *x, float *p,
+                                                          const uint32_t *__restrict__ ids_tmp, uint32_t *ids,
+                                                          int *flag)
+{
+    constexpr int H = TILE + 1, H3 = H * H * H;
+    __shared__ float fl[3 * H3];
+    const int nt = n / TILE, mask = n - 1;
+    const int t = blockIdx.x;
+    const int o0 = (t / (nt * nt)) * TILE, o1 = ((t / nt) % nt) * TILE, o2 = (t % nt) * TILE;
+    for (int i = threadIdx.x; i < H3; i += blockDim.x) {
+        const int a = i / (H * H), b = (i / H) % H, c = i % H;
+        const int64_t idx = ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + ((o2 + c) & mask);
+        fl[i] = F[idx];
+        fl[H3 + i] = F[cs + idx];
+        fl[2 * H3 + i] = F[2 * cs + idx];
+    }
+    __syncthreads();
+    const float nf = (float)n;
+    bool bad = false;
+    const int beg = koff[t * 8], end = koff[t * 8 + 8];
+    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        const float u0 = xs[i], u1 = xs[P + i], u2 = xs[2 * P + i];
+        const float f0 = floorf(u0), f1 = floorf(u1), f2 = floorf(u2);
+        const float d0 = u0 - f0, d1 = u1 - f1, d2 = u2 - f2;
+        const int a0 = ((int)f0 - o0) & mask, a1 = ((int)f1 - o1) & mask, a2 = ((int)f2 - o2) & mask;
+        const float w0[2] = {1.f - d0, d0}, w1[2] = {1.f - d1, d1}, w2[2] = {1.f - d2, d2};
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                const int row = ((a0 + a) * H + (a1 + b)) * H + a2;
+                const float wab = w0[a] * w1[b];
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    const float w = wab * w2[c];
+                    s0 += w * fl[row + c];
+                    s1 += w * fl[H3 + row + c];
+                    s2 += w * fl[2 * H3 + row + c];
+                }
+            }
+        const float p0 = ps[i] + kick * s0;
+        const float p1 = ps[P + i] + kick * s1;
+        const float p2 = ps[2 * P + i] + kick * s2;
+        const float x0 = wrapf(u0 + drift * p0, nf);
+        const float x1 = wrapf(u1 + drift * p1, nf);
+        const float x2 = wrapf(u2 + drift * p2, nf);
+        bad |= !(isfinite(p0) && isfinite(p1) && isfinite(p2) && isfinite(x0) && isfinite(x1) && isfinite(x2));
+        p[i] = p0;
+        p[P + i] = p1;
+        p[2 * P + i] = p2;
+        x[i] = x0;
+        x[P + i] = x1;
+        x[2 * P + i] = x2;
+        if (ids) ids[i] = ids_tmp[i];
+    }
+    if (bad) atomicOr(flag, FLAG_NAN);
+}
+
+__global__ void k_fill_i32(int *p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_add_i64(const int64_t *src, int64_t *dst, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] += src[i];
+}
+
+__global__ void k_tags_canonical(uint8_t *tags, int64_t P, int nseg, const int64_t *seg_off)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t t = 0;
+        for (int g = 1; g < nseg; g++) t += (i >= seg_off[g]) ? 1 : 0;
+        tags[i] = t;
+    }
+}
+
 __global__ void k_copy_real(const float *src, int64_t rs, int n, float *dst)
 {
     const int64_t m = (int64_t)n * n * n;
@@ -269,6 +356,36 @@ hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2
 {
     hipLaunchKernelGGL(k_readout_kick_drift, dim3(grid_for(P, 256)), dim3(256), 0, s, x, p, P,
                        reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout_kd_tiles(const float *xs, const float *ps, int64_t P, const int *koff, const float2 *f,
+                                   int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
+                                   float *p, const uint32_t *ids_tmp, uint32_t *ids, int *flag, hipStream_t s)
+{
+    const int nt = n / TILE;
+    if (nt < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_readout_kd_tiles, dim3((unsigned)(nt * nt * nt)), dim3(256), 0, s, xs, ps, P, koff,
+                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, x, p, ids_tmp,
+                       ids, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *p, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_i64(const int64_t *src, int64_t *dst, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_i64, dim3(grid_for(count, 256)), dim3(256), 0, s, src, dst, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_tags_canonical(uint8_t *tags, int64_t P, int nseg, const int64_t *seg_off, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tags_canonical, dim3(grid_for(P, 256)), dim3(256), 0, s, tags, P, nseg, seg_off);
     return hipGetLastError();
 }
 

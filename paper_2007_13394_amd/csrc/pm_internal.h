@@ -17,6 +17,10 @@ constexpr int TILE_W = 8;
 // column tiles.
 constexpr int64_t half_pad(int n) { return ((n / 2 + 1 + TILE_W - 1) / TILE_W) * TILE_W; }
 
+// Particles are sorted by TILE^3-cell blocks of the mesh for the tiled paint
+// and readout (meshes of at least 2 TILE cells per side).
+constexpr int TILE = 16;
+
 constexpr int MAX_SEG = 65;
 constexpr int MAX_BINS = 2048;
 constexpr int POWER_BLOCKS = 512;
@@ -33,6 +37,29 @@ struct Workspace {
     int *flag = nullptr;         // guard bits
     double *partial = nullptr;   // power-spectrum block partials
     float *tables = nullptr;     // small per-run tables (IC directions, shells)
+    int64_t *seg_off = nullptr;  // device copy of the segment offsets (MAX_SEG + 1)
+    int64_t *quanta = nullptr;   // device copy of the segment mass quanta (MAX_SEG)
+    float *xs = nullptr;         // tile-sorted positions [3][P]
+    float *ps = nullptr;         // tile-sorted momenta [3][P]
+    uint8_t *tags[2] = {nullptr, nullptr};  // per-particle segment tags (ping-pong)
+    uint32_t *ids_tmp = nullptr; // tile-sorted ids [P]
+    int *key = nullptr;          // sort key per particle (aliases the F region)
+    int *rank = nullptr;         // rank within key
+    int *cnt = nullptr;          // counts per key (K + 1)
+    int *koff = nullptr;         // exclusive offsets per key (K + 1)
+    int *bsum = nullptr;         // scan block sums
+};
+
+// Kernel kinds recorded by the launch trace (pm_trace_begin / pm_trace_end).
+enum KernelKind {
+    K_FILL = 0, K_PAINT, K_R2C, K_COLS_FWD, K_AXIS0, K_COLS_INV, K_C2R, K_READOUT_KD, K_READOUT,
+    K_POWER_BIN, K_POWER_REDUCE, K_IC_PARTICLES, K_COPY, K_SORT_COUNT, K_SORT_SCAN, K_SORT_SCATTER,
+    K_COUNT
+};
+
+struct TraceRec {
+    int kind;
+    hipEvent_t a, b;
 };
 
 struct Ctx {
@@ -53,6 +80,18 @@ struct Ctx {
     std::vector<float> dirs;      // (2 n_fib + 1) x 3
     Workspace ws;
     std::vector<float2> tw_host;
+    // particle order: canonical (segments at seg_off) or permuted by the last
+    // tile sort (segment of particle i = tags[cur_tag][i])
+    bool permuted = false;
+    int cur_tag = 0;
+    int64_t nkeys = 0;            // 8 x tiles when tile sorting is available, else 0
+    std::vector<int64_t> segtab_host;
+    uint32_t *ids = nullptr;      // caller's id array, permuted along with the particles
+    // launch trace
+    bool tracing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<TraceRec> trace;
 };
 
 // ---- host numerics (host_cosmo.cpp)
@@ -91,6 +130,19 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
 // ---- launchers (paint.hip)
 hipError_t launch_paint(const float *x, int64_t stride, int64_t first, int64_t count, int64_t quantum,
                         int n, int64_t *mesh, hipStream_t s);
+hipError_t launch_paint_tagged(const float *x, int64_t P, const uint8_t *tags, int seg_lo, int seg_hi,
+                               const int64_t *quanta, int n, int64_t *mesh, hipStream_t s);
+hipError_t launch_paint_tiles(const float *xs, const uint8_t *tags, int64_t P, const int *koff,
+                              const int64_t *quanta, int nseg, int seg_lo, int seg_hi, int n, int64_t *mesh,
+                              hipStream_t s);
+
+// ---- launchers (sort.hip)
+hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, int *key, int *rank, hipStream_t s);
+hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipStream_t s);
+hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
+                               const int64_t *seg_off, const int *key, const int *rank, const int *off, float *xs,
+                               float *ps, uint8_t *tag_out, const uint32_t *ids_in, uint32_t *ids_out,
+                               hipStream_t s);
 
 // ---- launchers (particles.hip)
 hipError_t launch_fill_i64(int64_t *p, int64_t count, hipStream_t s);
@@ -99,6 +151,12 @@ hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs
 hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f,
                                      int64_t comp_stride, int n, float kick, float drift, int *flag,
                                      hipStream_t s);
+hipError_t launch_readout_kd_tiles(const float *xs, const float *ps, int64_t P, const int *koff, const float2 *f,
+                                   int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
+                                   float *p, const uint32_t *ids_tmp, uint32_t *ids, int *flag, hipStream_t s);
+hipError_t launch_fill_i32(int *p, int64_t count, hipStream_t s);
+hipError_t launch_add_i64(const int64_t *src, int64_t *dst, int64_t count, hipStream_t s);
+hipError_t launch_tags_canonical(uint8_t *tags, int64_t P, int nseg, const int64_t *seg_off, hipStream_t s);
 hipError_t launch_copy_real(const float *src, int64_t rs, int n, float *dst, hipStream_t s);
 hipError_t launch_copy_half(const float2 *src, int64_t rs, int n, float2 *dst, hipStream_t s);
 hipError_t launch_load_half(const float2 *src, int n, float2 *dst, int64_t rs, hipStream_t s);

@@ -1,0 +1,192 @@
+// Counting sort of particles by mesh tile, done at the start of every step
+// so that the paint and the readout can work tile by tile out of LDS.
+//
+// Key of a particle = 8 * tile + face flags: tile is the TILE^3-cell block
+// holding floor(u); bit d of the flags is set when floor(u_d) is the last
+// cell of the tile along axis d (its +1 cloud-in-cell corner then lies in the
+// next tile).  Counting: one atomic per distinct key per wavefront (lanes
+// sharing a key are ranked by ballot), so lattice-ordered CDM, where most of
+// a wavefront falls in one tile, costs few atomics.  Offsets come from an
+// exclusive scan of the counts; the scatter writes position, momentum,
+// segment tag and optional id of particle i to offset[key_i] + rank_i.
+#include "pm_internal.h"
+
+namespace pm {
+namespace {
+
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536LL * 16)
+{
+    int64_t b = (n + block - 1) / block;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+__device__ __forceinline__ int tile_key(float u0, float u1, float u2, int n)
+{
+    const int mask = n - 1, nt = n / TILE;
+    const int c0 = (int)floorf(u0) & mask, c1 = (int)floorf(u1) & mask, c2 = (int)floorf(u2) & mask;
+    const int t = ((c0 / TILE) * nt + (c1 / TILE)) * nt + (c2 / TILE);
+    const int f = ((c0 % TILE) == TILE - 1 ? 1 : 0) | ((c1 % TILE) == TILE - 1 ? 2 : 0) |
+                  ((c2 % TILE) == TILE - 1 ? 4 : 0);
+    return t * 8 + f;
+}
+
+__global__ __launch_bounds__(256) void k_sort_count(const float *__restrict__ x, int64_t P, int n, int *cnt,
+                                                    int *key, int *rank)
+{
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < P; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool live = i < P;
+        const int k = live ? tile_key(x[i], x[P + i], x[2 * P + i], n) : -1;
+        // rank lanes with equal keys: one atomic per distinct key in the wavefront
+        uint64_t todo = __ballot(live);
+        int r = 0;
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int lk = __shfl(k, leader);
+            const uint64_t same = __ballot(live && k == lk);
+            int b = 0;
+            if (lane == leader) b = atomicAdd(cnt + lk, __popcll(same));
+            b = __shfl(b, leader);
+            if (live && k == lk) r = b + __popcll(same & ((1ull << lane) - 1));
+            todo &= ~same;
+        }
+        if (live) {
+            key[i] = k;
+            rank[i] = r;
+        }
+    }
+}
+
+// Exclusive scan in blocks of SCAN_B = 2048 values (256 threads x 8).
+constexpr int SCAN_T = 256, SCAN_PER = 8, SCAN_B = SCAN_T * SCAN_PER;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *sh)
+{
+    // sh: SCAN_T ints; returns the exclusive prefix of v over the block, total in sh[SCAN_T - 1] + last v
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        const int t = tid >= off ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    const int incl = sh[tid];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(const int *in, int *out, int64_t n, int *block_sums)
+{
+    __shared__ int sh[SCAN_T];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_PER;
+    int v[SCAN_PER], s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        v[j] = base + j < n ? in[base + j] : 0;
+        s += v[j];
+    }
+    const int pre = block_exclusive_scan(s, sh);
+    int run = pre;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == SCAN_T - 1) block_sums[blockIdx.x] = run;
+}
+
+// Single block: exclusive scan of up to SCAN_B * 4 block sums, in place.
+__global__ __launch_bounds__(SCAN_T) void k_scan_sums(int *sums, int nb)
+{
+    __shared__ int sh[SCAN_T];
+    int carry = 0;
+    for (int start = 0; start < nb; start += SCAN_B) {
+        const int base = start + threadIdx.x * SCAN_PER;
+        int v[SCAN_PER], s = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_PER; j++) {
+            v[j] = base + j < nb ? sums[base + j] : 0;
+            s += v[j];
+        }
+        const int pre = block_exclusive_scan(s, sh);
+        int run = carry + pre;
+#pragma unroll
+        for (int j = 0; j < SCAN_PER; j++) {
+            if (base + j < nb) sums[base + j] = run;
+            run += v[j];
+        }
+        // total of this chunk = inclusive value of the last thread
+        if (threadIdx.x == SCAN_T - 1) sh[0] = run;
+        __syncthreads();
+        carry = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_add(int *out, int64_t n, const int *sums)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] += sums[i / SCAN_B];
+}
+
+__global__ __launch_bounds__(256) void k_sort_scatter(const float *__restrict__ x, const float *__restrict__ p,
+                                                      const uint8_t *__restrict__ tag_in, int64_t P, int nseg,
+                                                      const int64_t *__restrict__ seg_off, const int *key,
+                                                      const int *rank, const int *off, float *xs, float *ps,
+                                                      uint8_t *tag_out, const uint32_t *ids_in, uint32_t *ids_out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = (int64_t)off[key[i]] + rank[i];
+        xs[d] = x[i];
+        xs[P + d] = x[P + i];
+        xs[2 * P + d] = x[2 * P + i];
+        if (p) {
+            ps[d] = p[i];
+            ps[P + d] = p[P + i];
+            ps[2 * P + d] = p[2 * P + i];
+        }
+        uint8_t t;
+        if (tag_in) {
+            t = tag_in[i];
+        } else {   // canonical order: segment from the offsets
+            t = 0;
+            for (int g = 1; g < nseg; g++) t += (i >= seg_off[g]) ? 1 : 0;
+        }
+        tag_out[d] = t;
+        if (ids_in) ids_out[d] = ids_in[i];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, int *key, int *rank, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sort_count, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P, n, cnt, key, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipStream_t s)
+{
+    const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    if (nb > (int64_t)SCAN_B * 4096) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, block_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, s, block_sums, (int)nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n, 256)), dim3(256), 0, s, out, n, block_sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
+                               const int64_t *seg_off, const int *key, const int *rank, const int *off, float *xs,
+                               float *ps, uint8_t *tag_out, const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sort_scatter, dim3(grid_for(P, 256)), dim3(256), 0, s, x, p, tag_in, P, nseg, seg_off, key,
+                       rank, off, xs, ps, tag_out, ids_in, ids_out);
+    return hipGetLastError();
+}
+
+}  // namespace pm

@@ -17,7 +17,7 @@ if not os.path.exists(_SO):
 _lib = C.CDLL(_SO)
 
 PM_OK, PM_ERR_ARG, PM_ERR_SIZE, PM_ERR_DEVICE, PM_ERR_OVERFLOW, PM_ERR_NAN, PM_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
-PM_FLAG_NO_FLIP, PM_FLAG_NO_GUARDS = 1, 2
+PM_FLAG_NO_FLIP, PM_FLAG_NO_GUARDS, PM_FLAG_NO_SORT = 1, 2, 4
 
 
 class PMError(RuntimeError):
@@ -80,10 +80,18 @@ _sig("pm_force_mesh", [_vp, _vp, _vp, _vp])
 _sig("pm_force", [_vp, _vp, _vp, _vp])
 _sig("pm_step", [_vp, _vp, _vp, _dbl, _dbl, _dbl, _dbl, _vp])
 _sig("pm_power", [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp])
+_sig("pm_trace_begin", [_vp, _i32])
+_sig("pm_attach_ids", [_vp, _vp])
+_sig("pm_segment_tags", [_vp, _vp, _vp])
+_sig("pm_reset_order", [_vp])
+_sig("pm_trace_end", [_vp, _i32, _vp, _vp, C.POINTER(_i32)])
+_lib.pm_kernel_name.restype = C.c_char_p
+_lib.pm_kernel_name.argtypes = [_i32]
 
 EXPORTS = ["pm_sizes", "pm_init", "pm_free", "pm_last_error", "pm_segments", "pm_shells", "pm_growth",
            "pm_kdk_factors", "pm_ic", "pm_paint_q", "pm_paint", "pm_fft_r2c", "pm_fft_c2r", "pm_force_mesh",
-           "pm_force", "pm_step", "pm_power"]
+           "pm_force", "pm_step", "pm_power", "pm_trace_begin", "pm_trace_end", "pm_kernel_name", "pm_attach_ids",
+           "pm_segment_tags", "pm_reset_order"]
 
 
 def _check(st):
@@ -228,3 +236,41 @@ def pm_power(ctx, x, a_lo, a_hi, b_lo=None, b_hi=None, nbins=None, compensate=Fa
     _check(_lib.pm_power(ctx.h, _dev(x, torch.float32, 3 * ctx.P, "x"), a_lo, a_hi, b_lo, b_hi, nbins,
                          int(bool(compensate)), k.ctypes.data, pk.ctypes.data, nm.ctypes.data, _stream(stream)))
     return k, pk, nm
+
+
+def pm_trace_begin(ctx, capacity=4096):
+    _check(_lib.pm_trace_begin(ctx.h, capacity))
+
+
+def pm_trace_end(ctx, max_records=65536):
+    """[(kernel name, milliseconds)] of the launches recorded since pm_trace_begin."""
+    kind = np.zeros(max_records, dtype=np.int32)
+    ms = np.zeros(max_records, dtype=np.float32)
+    cnt = _i32()
+    _check(_lib.pm_trace_end(ctx.h, max_records, kind.ctypes.data, ms.ctypes.data, C.byref(cnt)))
+    m = min(cnt.value, max_records)
+    return [(pm_kernel_name(int(kind[i])), float(ms[i])) for i in range(m)]
+
+
+def pm_kernel_name(kind):
+    return _lib.pm_kernel_name(kind).decode()
+
+
+def pm_attach_ids(ctx, ids):
+    """Attach a uint32 (stored as int32) device tensor of P ids, or None."""
+    if ids is None:
+        _check(_lib.pm_attach_ids(ctx.h, None))
+        ctx._ids = None
+        return
+    _check(_lib.pm_attach_ids(ctx.h, _dev(ids, torch.int32, ctx.P, "ids")))
+    ctx._ids = ids   # keep the tensor alive while attached
+
+
+def pm_segment_tags(ctx, out=None, stream=None):
+    out = torch.empty(ctx.P, dtype=torch.uint8, device=ctx.workspace.device) if out is None else out
+    _check(_lib.pm_segment_tags(ctx.h, _dev(out, torch.uint8, ctx.P, "tags"), _stream(stream)))
+    return out
+
+
+def pm_reset_order(ctx):
+    _check(_lib.pm_reset_order(ctx.h))

@@ -62,6 +62,20 @@ def test_segments_and_shells_match_oracle(c1):
     assert np.allclose(D, oD, rtol=1e-8) and np.allclose(G, oG, rtol=1e-8)
 
 
+def test_shells_normal_hierarchy_match_oracle():
+    # the effective distribution of three unequal masses (cut-off q = 30 / alpha_min)
+    pm = _pm()
+    cfg = I.config("C1", m_nu=I.NH_006)
+    ctx = pm.Ctx(pm.make_config(cfg))
+    e, qs, ms = pm.pm_shells(ctx)
+    alpha = np.array(I.NH_006) / I.NH_006[0]
+    oe, oq, om = O.fd_shells(alpha, 10)
+    assert np.allclose(e, oe, rtol=1e-9) and np.allclose(qs, oq, rtol=1e-9) and np.allclose(ms, om, rtol=1e-9)
+    off, mass, q = pm.pm_segments(ctx)
+    _, o_mass, _ = O.segments(O.make_sim(cfg))
+    assert np.allclose(mass, o_mass, rtol=1e-9)
+
+
 def test_paint_bit_exact_synthetic_and_adversarial(c1, dev):
     pm = _pm()
     cfg, ctx = c1
@@ -154,15 +168,11 @@ def test_force_on_particles_vs_oracle(c1, dev):
     assert rel_l2(got[:, :nc], ref[:, :nc]) < 1e-5 and rel_l2(got[:, nc:], ref[:, nc:]) < 1e-5
 
 
-@pytest.mark.parametrize("call", [(0.01, 0.01, 0.0595, 0.109), (0.604, 0.5545, 0.6535, 0.703), (1.0, 0.9505, 1.0, 1.0)])
-def test_one_step_vs_oracle(c1, dev, call):
-    pm = _pm()
-    cfg, ctx = c1
+CALLS = [(0.01, 0.01, 0.0595, 0.109), (0.604, 0.5545, 0.6535, 0.703), (1.0, 0.9505, 1.0, 1.0)]
+
+
+def _step_compare(cfg, gx, gp, x, p, call):
     n = cfg["n_mesh"]
-    x, p = I.synthetic_state(cfg, seed=13)
-    xd, pd = torch.from_numpy(x).to(dev), torch.from_numpy(p).to(dev)
-    pm.pm_step(ctx, xd, pd, *call)
-    gx, gp = xd.cpu().numpy(), pd.cpu().numpy()
     s = O.make_sim(cfg)
     kick, drift = O.kdk_factors(s.cosmo, *[[v] for v in call])
     ox, op = x.astype(np.float64), p.astype(np.float64)
@@ -180,6 +190,74 @@ def test_one_step_vs_oracle(c1, dev, call):
         else:
             assert np.array_equal(gx[:, sl], x[:, sl])
     assert np.all((gx >= 0) & (gx < n))
+
+
+@pytest.mark.parametrize("call", CALLS)
+def test_one_step_sorted_vs_oracle(c1, dev, call):
+    """Default step: particles are tile-sorted; ids map them back."""
+    pm = _pm()
+    cfg, ctx = c1
+    x, p = I.synthetic_state(cfg, seed=13)
+    pm.pm_reset_order(ctx)
+    ids = torch.arange(ctx.P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(ctx, ids)
+    xd, pd = torch.from_numpy(x).to(dev), torch.from_numpy(p).to(dev)
+    pm.pm_step(ctx, xd, pd, *call)
+    order = np.argsort(ids.cpu().numpy())
+    assert np.array_equal(np.sort(ids.cpu().numpy()), np.arange(ctx.P))
+    gx, gp = xd.cpu().numpy()[:, order], pd.cpu().numpy()[:, order]
+    tags = pm.pm_segment_tags(ctx).cpu().numpy()[order]
+    off, _, _ = pm.pm_segments(ctx)
+    assert np.array_equal(tags, np.repeat(np.arange(ctx.nseg), np.diff(off)))
+    pm.pm_attach_ids(ctx, None)
+    pm.pm_reset_order(ctx)
+    _step_compare(cfg, gx, gp, x, p, call)
+
+
+@pytest.mark.parametrize("call", CALLS[:2])
+def test_one_step_unsorted_vs_oracle(dev, call):
+    pm = _pm()
+    cfg = I.config("C1")
+    ctx = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_NO_SORT))
+    x, p = I.synthetic_state(cfg, seed=13)
+    xd, pd = torch.from_numpy(x).to(dev), torch.from_numpy(p).to(dev)
+    pm.pm_step(ctx, xd, pd, *call)
+    _step_compare(cfg, xd.cpu().numpy(), pd.cpu().numpy(), x, p, call)
+
+
+def test_sorted_state_paint_and_force_are_order_independent(dev):
+    # after sorted steps the particle arrays are permuted; painting and forces
+    # through the segment tags must match the same particles in canonical order
+    pm = _pm()
+    cfg = I.config("C1")
+    ctx = pm.Ctx(pm.make_config(cfg))
+    n = cfg["n_mesh"]
+    x, p = I.synthetic_state(cfg, seed=31)
+    ids = torch.arange(ctx.P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(ctx, ids)
+    xd, pd = torch.from_numpy(x).to(dev), torch.from_numpy(p).to(dev)
+    for c in CALLS[:2]:
+        pm.pm_step(ctx, xd, pd, *c)
+    order = torch.argsort(ids.long())
+    xc = xd[:, order].contiguous()
+    m_perm = torch.zeros(n ** 3, dtype=torch.int64, device=dev)
+    pm.pm_paint(ctx, xd, 0, ctx.nseg, m_perm)
+    m_nu = torch.zeros_like(m_perm)
+    pm.pm_paint(ctx, xd, 1, ctx.nseg, m_nu)
+    acc_perm = torch.empty_like(xd)
+    pm.pm_force(ctx, xd, acc_perm)
+    k1, pk1, _ = pm.pm_power(ctx, xd, 0, 1, 1, ctx.nseg, nbins=16)
+    ctx2 = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_NO_SORT))
+    m_can = torch.zeros_like(m_perm)
+    pm.pm_paint(ctx2, xc, 0, ctx2.nseg, m_can)
+    m_nu2 = torch.zeros_like(m_perm)
+    pm.pm_paint(ctx2, xc, 1, ctx2.nseg, m_nu2)
+    assert torch.equal(m_perm, m_can) and torch.equal(m_nu, m_nu2)
+    acc_can = torch.empty_like(xc)
+    pm.pm_force(ctx2, xc, acc_can)
+    assert torch.allclose(acc_perm[:, order], acc_can, rtol=0, atol=1e-6 * float(acc_can.abs().max()))
+    k2, pk2, _ = pm.pm_power(ctx2, xc, 0, 1, 1, ctx2.nseg, nbins=16)
+    assert np.allclose(pk1, pk2, rtol=1e-5, atol=0)
 
 
 def test_initial_conditions_vs_oracle(c1, dev):
