@@ -39,9 +39,14 @@ def model_bytes(P, n):
         "r2c_rows": 8 * M + 8 * Mc,       # int64 density in, half spectrum out
         "cols_fwd": 16 * Mc,
         "axis0": 8 * Mc + 24 * Mc,        # spectrum in, three force spectra out
+        "x0_fwd": 16 * Mc,                # 16-point axis-0 pass, one field
+        "x0_green": 8 * Mc + 24 * Mc,     # spectrum in, three force spectra out
+        "x0_inv": 48 * Mc,                # inverse 16-point pass, three fields
         "cols_inv": 16 * Mc,
         "c2r_rows": 8 * Mc + 4 * M,
         "readout_kick_drift": 12 * M + 48 * P,
+        "sort_count": 20 * P,             # positions in, key and rank out
+        "sort_scatter": 58 * P,           # x, p, key, rank, tag in; sorted x, p, tag out
     }
     paint_step = 12 * P + 8 * M           # positions in, int64 mesh written once
     step = 60 * P + 40 * M + 128 * Mc

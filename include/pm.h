@@ -178,7 +178,9 @@ pm_status pm_fft_c2r(pm_ctx *ctx, const float *spec, float *real, void *stream);
 
 /* Force meshes from a fixed-point density: delta = Q 2^-shift - 1, F_d(k) =
  * 1.5 Omega_m i k_d / k^2 delta(k) (zero at k = 0 and on the Nyquist plane of
- * component d).  mesh_q: device int64 [N]^3; out: device float32 [3][N]^3. */
+ * component d).  mesh_q: device int64 [N]^3; out: device float32 [3][N]^3.
+ * mesh_q is consumed completely before out is written, so it may lie inside
+ * out's memory (a caller short of memory can build the density there). */
 pm_status pm_force_mesh(pm_ctx *ctx, const int64_t *mesh_q, float *out, void *stream);
 
 /* Force on every particle at positions x: paint all segments, solve, read

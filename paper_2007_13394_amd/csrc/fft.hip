@@ -12,7 +12,10 @@
 //     a per-mode multiplier (the gradient of the inverse Laplacian, or the
 //     initial-condition transfer function) and an inverse transform, so the
 //     forward spectrum is read once and the k-space multiply never touches
-//     HBM on its own.
+//     HBM on its own.  For the force solve at N >= 256, where a 64-byte
+//     column tile would touch a different 2 MiB page on every row, axis 0 is
+//     instead split into a 16-point pass over strided planes and an N/16-point
+//     pass over consecutive planes fused with the multiplier (see below).
 // Transforms inside LDS are Stockham autosort stages of radix 2..16 held in
 // registers (two barriers per stage, in place), twiddles from an FP64-derived
 // table.  Consecutive workgroups are spread over the eight XCDs by the
@@ -35,43 +38,49 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
-// cos(2 pi j / 16)
-constexpr float c16(int j)
+// cos(2 pi j / 64), exact quarter-wave symmetry
+constexpr float c64q(int j)
 {
-    switch (j & 15) {
+    switch (j) {
     case 0: return 1.0f;
-    case 1: return 0.92387953251128674f;
-    case 2: return 0.70710678118654752f;
-    case 3: return 0.38268343236508977f;
-    case 4: return 0.0f;
-    case 5: return -0.38268343236508977f;
-    case 6: return -0.70710678118654752f;
-    case 7: return -0.92387953251128674f;
-    case 8: return -1.0f;
-    case 9: return -0.92387953251128674f;
-    case 10: return -0.70710678118654752f;
-    case 11: return -0.38268343236508977f;
-    case 12: return 0.0f;
-    case 13: return 0.38268343236508977f;
-    case 14: return 0.70710678118654752f;
-    default: return 0.92387953251128674f;
+    case 1: return 0.99518472667219693f;
+    case 2: return 0.98078528040323043f;
+    case 3: return 0.95694033573220882f;
+    case 4: return 0.92387953251128674f;
+    case 5: return 0.88192126434835505f;
+    case 6: return 0.83146961230254524f;
+    case 7: return 0.77301045336273699f;
+    case 8: return 0.70710678118654757f;
+    case 9: return 0.63439328416364549f;
+    case 10: return 0.55557023301960229f;
+    case 11: return 0.47139673682599781f;
+    case 12: return 0.38268343236508984f;
+    case 13: return 0.29028467725446233f;
+    case 14: return 0.19509032201612833f;
+    case 15: return 0.09801714032956077f;
+    default: return 0.0f;
     }
 }
-
-// a * exp(-/+ 2 pi i j / 16) (minus for the forward transform)
-template <bool INV>
-__device__ __forceinline__ float2 rot16(float2 a, int j)
+constexpr float c64(int j)
 {
-    j &= 15;
+    j &= 63;
+    return j <= 16 ? c64q(j) : (j <= 32 ? -c64q(32 - j) : (j <= 48 ? -c64q(j - 32) : c64q(64 - j)));
+}
+
+// a * exp(-/+ 2 pi i j / 64) (minus for the forward transform)
+template <bool INV>
+__device__ __forceinline__ float2 rot64(float2 a, int j)
+{
+    j &= 63;
     if (j == 0) return a;
-    if (j == 8) return make_float2(-a.x, -a.y);
-    if (j == 4) return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
-    if (j == 12) return INV ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
-    const float c = c16(j), s = INV ? c16(j - 4) : -c16(j - 4);
+    if (j == 32) return make_float2(-a.x, -a.y);
+    if (j == 16) return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+    if (j == 48) return INV ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+    const float c = c64(j), s = INV ? c64(j - 16) : -c64(j - 16);
     return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
 }
 
-// In-register DFT of size R (natural order in and out), radix-2 recursion.
+// In-register DFT of size R <= 64 (natural order in and out), radix-2 recursion.
 template <int R, bool INV>
 struct Dft {
     __device__ __forceinline__ static void run(float2 *v)
@@ -86,7 +95,7 @@ struct Dft {
         Dft<R / 2, INV>::run(o);
 #pragma unroll
         for (int k = 0; k < R / 2; k++) {
-            const float2 t = rot16<INV>(o[k], k * (16 / R));
+            const float2 t = rot64<INV>(o[k], k * (64 / R));
             v[k] = cadd(e[k], t);
             v[k + R / 2] = csub(e[k], t);
         }
@@ -435,6 +444,175 @@ __global__ __launch_bounds__(Ax0Cfg<LOGN>::T) void k_axis0(const float2 *src, in
     }
 }
 
+
+// ---------------------------------------------------------------- axis 0 in two passes
+// At N >= 256 one plane of the half spectrum (N x nhp complex, contiguous)
+// spans several 2 MiB pages, and a column tile that reads 64 bytes from each
+// of N planes takes an address-translation miss on nearly every access.  The
+// axis-0 transform is therefore split as N = 16 x N2 (four-step FFT) into two
+// passes whose wavefronts each read 512 contiguous bytes of one plane:
+//   pass A: for every j1 < N2, a 16-point DFT over the planes j1 + N2 j2
+//           (j2 < 16) and the twiddle w_N^(j1 m); Y_m[j1] is stored in place,
+//           in plane j1 + N2 m;
+//   pass B: for every m < 16, an N2-point DFT over the consecutive planes
+//           N2 m + j1, which leaves frequency k0 = m + 16 k in plane N2 m + k
+//           (digit-reversed along axis 0).
+// The force kernel fuses pass B with the gradient of the inverse Laplacian and
+// the inverse of pass B for two fields; the inverse of pass A then restores
+// natural order on all three outputs.  Plane offsets e (0 <= e < N nhp) index
+// (k1, k2) = (e / nhp, e % nhp).
+
+// Pass A (or its inverse) over nf fields: grid (N nhp / 256, N2, nf).
+template <int N, bool INV>
+__global__ __launch_bounds__(256) void k_x0_pass16(float2 *base, int64_t field_stride, int64_t plane,
+                                                   const float2 *__restrict__ tw)
+{
+    constexpr int N2 = N / 16;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int j1 = blockIdx.y;
+    float2 *p = base + (int64_t)blockIdx.z * field_stride + e + (int64_t)j1 * plane;
+    const int64_t pstep = (int64_t)N2 * plane;
+    const float2 *twN = tw + N;
+    float2 v[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) v[j] = p[j * pstep];
+    if constexpr (!INV) {
+        Dft<16, false>::run(v);
+#pragma unroll
+        for (int m = 1; m < 16; m++) v[m] = cmul(v[m], twN[j1 * m]);
+    } else {
+#pragma unroll
+        for (int m = 1; m < 16; m++) v[m] = cmul(v[m], cconj(twN[j1 * m]));
+        Dft<16, true>::run(v);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j++) p[j * pstep] = v[j];
+}
+
+// Pass B of the force solve: grid (N nhp / 64, 16), 64 R2 threads with
+// R2 = N2 / 16, each thread one of 64 consecutive plane offsets.  The N2-point
+// DFT is itself split as N2 = R2 x 16: step 1 (thread (c, g), g < R2) takes a
+// 16-point DFT over j1 = g + R2 i and the twiddle w_N2^(g a), step 2 (thread
+// (c, q), after an LDS exchange) the R2-point DFTs over g for a = q + R2 s,
+// giving k = a + 16 l.  T = coef i S / k^2 is kept in registers; k0 T and T
+// go through the inverse steps; outputs k0 T -> out0 (which may alias src),
+// k1 T -> out1, k2 T -> out2, each zero at k = 0 and on its own Nyquist plane.
+template <int N>
+struct X0Cfg {
+    static constexpr int N2 = N / 16, R2 = N2 / 16, C = 64, T = C * R2, SPT = 16 / R2;
+    static_assert(N >= 256 && R2 >= 1, "two-pass axis-0 transform needs N >= 256");
+};
+
+// Inverse of pass B on one thread's 16 values (step-2 slots in, j1 = g + R2 i
+// out); the caller's LDS tile is free on entry and on return.
+template <int N>
+__device__ __forceinline__ void x0_inverse_b(float2 (&w)[16], float2 *lds, int c, int g,
+                                             const float2 *__restrict__ twN2)
+{
+    using X = X0Cfg<N>;
+    constexpr int R2 = X::R2, C = X::C, SPT = X::SPT;
+#pragma unroll
+    for (int s = 0; s < SPT; s++) {
+        Dft<R2, true>::run(w + s * R2);
+        const int a = g + R2 * s;
+#pragma unroll
+        for (int l = 0; l < R2; l++) lds[(a * R2 + l) * C + c] = w[s * R2 + l];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 16; a++) w[a] = lds[(a * R2 + g) * C + c];
+    __syncthreads();
+    if constexpr (R2 > 1) {
+#pragma unroll
+        for (int a = 1; a < 16; a++) w[a] = cmul(w[a], cconj(twN2[g * a]));
+    }
+    Dft<16, true>::run(w);
+}
+
+template <int N>
+__global__ __launch_bounds__(X0Cfg<N>::T, 4) void k_x0_green(const float2 *src, float2 *out0, float2 *out1,
+                                                          float2 *out2, int64_t plane, int nhp, float coef,
+                                                          const float2 *__restrict__ tw)
+{
+    using X = X0Cfg<N>;
+    constexpr int N2 = X::N2, R2 = X::R2, C = X::C, SPT = X::SPT;
+    __shared__ float2 lds[16 * R2 * C];
+    const int m = blockIdx.y;
+    const int c = threadIdx.x % C, g = threadIdx.x / C;   // step 1: g; step 2: q = g
+    const int64_t e = (int64_t)blockIdx.x * C + c;
+    const int64_t pbase = (int64_t)(N2 * m + g) * plane + e;
+    const int64_t pstep = (int64_t)R2 * plane;
+    const float2 *twN2 = tw + N2;
+    float2 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) v[i] = src[pbase + i * pstep];
+    Dft<16, false>::run(v);
+    if constexpr (R2 > 1) {
+#pragma unroll
+        for (int a = 1; a < 16; a++) v[a] = cmul(v[a], twN2[g * a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 16; a++) lds[(a * R2 + g) * C + c] = v[a];
+    __syncthreads();
+    // step 2: slot s R2 + l holds frequency k = q + R2 s + 16 l
+#pragma unroll
+    for (int s = 0; s < SPT; s++) {
+        const int a = g + R2 * s;
+#pragma unroll
+        for (int l = 0; l < R2; l++) v[s * R2 + l] = lds[(a * R2 + l) * C + c];
+        Dft<R2, false>::run(v + s * R2);
+    }
+    __syncthreads();
+    const float sc = 6.28318530717958648f / (float)N;
+    const int k1i = (int)(e / nhp), k2 = (int)(e % nhp);
+    const int n1 = signed_mode(k1i, N);
+    const float k1 = sc * n1, kz = sc * k2, kperp = k1 * k1 + kz * kz;
+    float2 keep[16];
+#pragma unroll
+    for (int s = 0; s < SPT; s++)
+#pragma unroll
+        for (int l = 0; l < R2; l++) {
+            const int k = g + R2 * s + 16 * l;
+            const int n0 = signed_mode(m + 16 * k, N);
+            const float k0 = sc * n0, kk = k0 * k0 + kperp;
+            const float gr = (k2 > N / 2 || kk == 0.f) ? 0.f : coef / kk;
+            const float2 x = v[s * R2 + l];
+            const float2 t = make_float2(-gr * x.y, gr * x.x);                 // T = i g S
+            keep[s * R2 + l] = t;
+            const float g0 = (n0 == N / 2 || n0 == -N / 2) ? 0.f : k0;
+            v[s * R2 + l] = make_float2(g0 * t.x, g0 * t.y);                  // k0 T
+        }
+    // walking output pointers; the empty asm keeps the compiler from
+    // materialising all sixteen 64-bit addresses while T is live
+    x0_inverse_b<N>(v, lds, c, g, twN2);
+    {
+        float2 *q = out0 + pbase;
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            asm volatile("" : "+v"(q));
+            *q = v[i];
+            q += pstep;
+        }
+    }
+    x0_inverse_b<N>(keep, lds, c, g, twN2);
+    {
+        // k1, k2 multipliers recomputed here rather than kept live
+        const int64_t e2 = (int64_t)blockIdx.x * C + threadIdx.x % C;
+        const int r1 = signed_mode((int)(e2 / nhp), N), r2 = (int)(e2 % nhp);
+        const float f1 = (r1 == N / 2 || r1 == -N / 2) ? 0.f : sc * r1;
+        const float f2 = (r2 >= N / 2) ? 0.f : sc * r2;
+        float2 *q1 = out1 + pbase, *q2 = out2 + pbase;
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            asm volatile("" : "+v"(q1), "+v"(q2));
+            *q1 = make_float2(f1 * keep[i].x, f1 * keep[i].y);
+            *q2 = make_float2(f2 * keep[i].x, f2 * keep[i].y);
+            q1 += pstep;
+            q2 += pstep;
+        }
+    }
+}
+
 }  // namespace
 
 #define PM_DISPATCH_LOGN(logn, MACRO) \
@@ -515,6 +693,7 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
     const int n = 1 << logn;
     if (mode == MULT_FORCE && n < 16) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)n * (unsigned)n_cb;
+    if (mode == MULT_FORCE && logn >= 8) return hipErrorInvalidValue;   // two-pass path (launch_x0_*)
     IcParams icp{};
     if (ic) icp = *ic;
     const float fc = (float)coef;
@@ -532,6 +711,48 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
                                out2, o_l, o_o, n_cb, fc, icp, tw);                                  \
     }
     PM_DISPATCH_LOGN(logn, AX0)
+    return hipGetLastError();
+}
+
+hipError_t launch_x0_pass16(int logn, bool inverse, float2 *base, int64_t field_stride, int64_t plane, int nf,
+                            const float2 *tw, hipStream_t s)
+{
+    if (logn < 8 || logn > 11 || plane % 256 || nf < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(plane / 256), (unsigned)(1 << (logn - 4)), (unsigned)nf);
+#define X0A(NN)                                                                                      \
+    {                                                                                                \
+        if (inverse)                                                                                 \
+            hipLaunchKernelGGL((k_x0_pass16<NN, true>), grid, dim3(256), 0, s, base, field_stride,   \
+                               plane, tw);                                                           \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_x0_pass16<NN, false>), grid, dim3(256), 0, s, base, field_stride,  \
+                               plane, tw);                                                           \
+    }
+    switch (logn) {
+    case 8: X0A(256); break;
+    case 9: X0A(512); break;
+    case 10: X0A(1024); break;
+    default: X0A(2048); break;
+    }
+#undef X0A
+    return hipGetLastError();
+}
+
+hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, float2 *out2, int64_t plane,
+                           int nhp, double coef, const float2 *tw, hipStream_t s)
+{
+    if (logn < 8 || logn > 11 || plane % 64 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(plane / 64), 16);
+    const float fc = (float)coef;
+#define X0B(NN)                                                                                      \
+    hipLaunchKernelGGL((k_x0_green<NN>), grid, dim3(X0Cfg<NN>::T), 0, s, src, out0, out1, out2, plane, nhp, fc, tw)
+    switch (logn) {
+    case 8: X0B(256); break;
+    case 9: X0B(512); break;
+    case 10: X0B(1024); break;
+    default: X0B(2048); break;
+    }
+#undef X0B
     return hipGetLastError();
 }
 

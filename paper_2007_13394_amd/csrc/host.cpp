@@ -224,28 +224,37 @@ pm_status paint_all(pm_ctx *c, const float *x, hipStream_t s)
 }
 
 // From the int64 density at `src` (row stride n int64) to the three real
-// force meshes in the F region (row stride 2 Nhp floats).
+// force meshes in the F region (row stride 2 Nhp floats).  The forward
+// spectrum is written into F0 (row stride Nhp, not a power of two, so strided
+// passes do not camp on a few HBM channels) and the axis-0 pass works in
+// place on it.
 pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s)
 {
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
     const int ncb = (int)(nhp / pm::TILE_W);
-    float2 *S = reinterpret_cast<float2 *>(c->ws.q);
     float2 *F = c->ws.f;
     const int64_t cs = n2 * nhp;
     const double scale = ldexp(1.0, -c->cfg.shift);
-    // axis 2: density contrast, real-to-complex rows (in place when src is Q)
-    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, src, n, S, n, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
+    // axis 2: density contrast, real-to-complex rows
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, src, n, F, nhp, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
     // axis 1
-    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
-    // axis 0 forward, gradient of the inverse Laplacian, axis 0 inverse x 3
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    // axis 0 forward, gradient of the inverse Laplacian, axis 0 inverses (in place on F0)
     const double coef = 1.5 * c->cfg.omega_m / ((double)n2 * n);
-    LAUNCH(pm::K_AXIS0, pm::launch_axis0(lg, pm::MULT_FORCE, S, n2, n, F, F + cs, F + 2 * cs, n * nhp, nhp, ncb, coef, nullptr,
-                            c->ws.tw, s));
+    if (lg >= 8) {
+        const int64_t plane = (int64_t)n * nhp;
+        LAUNCH(pm::K_X0_FWD, pm::launch_x0_pass16(lg, false, F, cs, plane, 1, c->ws.tw, s));
+        LAUNCH(pm::K_X0_GREEN, pm::launch_x0_green(lg, F, F, F + cs, F + 2 * cs, plane, (int)nhp, coef, c->ws.tw, s));
+        LAUNCH(pm::K_X0_INV, pm::launch_x0_pass16(lg, true, F, cs, plane, 3, c->ws.tw, s));
+    } else {
+        LAUNCH(pm::K_AXIS0, pm::launch_axis0(lg, pm::MULT_FORCE, F, n * nhp, nhp, F, F + cs, F + 2 * cs, n * nhp,
+                                             nhp, ncb, coef, nullptr, c->ws.tw, s));
+    }
     for (int d = 0; d < 3; d++) {
         LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + d * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
-        LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp, n2,
-                                   c->ws.tw, s));
+        LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp,
+                                              n2, c->ws.tw, s));
     }
     return PM_OK;
 }
@@ -372,7 +381,7 @@ void pm_free(pm_ctx *ctx)
 static const char *kKernelNames[pm::K_COUNT] = {
     "fill",      "paint",        "r2c_rows",     "cols_fwd",   "axis0",      "cols_inv",   "c2r_rows",
     "readout_kick_drift", "readout", "power_bin", "power_reduce", "ic_particles", "copy", "sort_count",
-    "sort_scan", "sort_scatter"};
+    "sort_scan", "sort_scatter", "x0_fwd", "x0_green", "x0_inv"};
 
 const char *pm_kernel_name(int32_t kind)
 {

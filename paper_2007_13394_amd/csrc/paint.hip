@@ -110,37 +110,48 @@ __global__ __launch_bounds__(256) void k_paint_tiles(const float *__restrict__ x
 {
     __shared__ unsigned long long acc[TILE * TILE * TILE];
     __shared__ long long qtab[MAX_SEG];
+    __shared__ int rng[27][2];   // particle ranges contributing to this tile
     const int nt = n / TILE, mask = n - 1;
     const int t = blockIdx.x;
     const int t0 = t / (nt * nt), t1 = (t / nt) % nt, t2 = t % nt;
     for (int i = threadIdx.x; i < TILE * TILE * TILE; i += blockDim.x) acc[i] = 0;
     for (int i = threadIdx.x; i < nseg; i += blockDim.x) qtab[i] = quanta[i];
+    // the 27 (neighbour e, flags f) ranges with f containing e: own tile (e = 0,
+    // all flags) and the lower neighbours' particles whose +1 corner crosses
+    // into this tile; their offsets are fetched in parallel, once
+    if (threadIdx.x < 64) {
+        const int e = threadIdx.x >> 3, f = threadIdx.x & 7;
+        if ((f & e) == e) {
+            int slot = 0;   // index of (e, f) among the valid pairs, in (e, f) order
+            for (int ee = 0; ee < e; ee++) slot += 1 << (3 - __popc(ee));
+            for (int ff = 0; ff < f; ff++) slot += ((ff & e) == e) ? 1 : 0;
+            const int s0 = (t0 - (e & 1) + nt) % nt, s1 = (t1 - ((e >> 1) & 1) + nt) % nt,
+                      s2 = (t2 - ((e >> 2) & 1) + nt) % nt;
+            const int tn = (s0 * nt + s1) * nt + s2;
+            rng[slot][0] = koff[tn * 8 + f];
+            rng[slot][1] = koff[tn * 8 + f + 1];
+        }
+    }
     __syncthreads();
-    for (int e = 0; e < 8; e++) {
-        const int s0 = (t0 - (e & 1) + nt) % nt, s1 = (t1 - ((e >> 1) & 1) + nt) % nt,
-                  s2 = (t2 - ((e >> 2) & 1) + nt) % nt;
-        const int tn = (s0 * nt + s1) * nt + s2;
-        for (int f = 0; f < 8; f++) {
-            if ((f & e) != e) continue;
-            const int beg = koff[tn * 8 + f], end = koff[tn * 8 + f + 1];
-            for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-                const int g = tags[i];
-                if (g < lo || g >= hi) continue;
-                int c[3][2];
-                long long q[8];
-                cic_quanta(xs[i], xs[P + i], xs[2 * P + i], (long long)qtab[g], mask, c, q);
-                int corner = 0;
+    for (int r = 0; r < 27; r++) {
+        const int beg = rng[r][0], end = rng[r][1];
+        for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+            const int g = tags[i];
+            if (g < lo || g >= hi) continue;
+            int c[3][2];
+            long long q[8];
+            cic_quanta(xs[i], xs[P + i], xs[2 * P + i], (long long)qtab[g], mask, c, q);
+            int corner = 0;
 #pragma unroll
-                for (int a = 0; a < 2; a++)
+            for (int a = 0; a < 2; a++)
 #pragma unroll
-                    for (int b = 0; b < 2; b++)
+                for (int b = 0; b < 2; b++)
 #pragma unroll
-                        for (int d = 0; d < 2; d++, corner++) {
-                            const int l0 = c[0][a] - t0 * TILE, l1 = c[1][b] - t1 * TILE, l2 = c[2][d] - t2 * TILE;
-                            if ((unsigned)l0 < TILE && (unsigned)l1 < TILE && (unsigned)l2 < TILE)
-                                atomicAdd(&acc[(l0 * TILE + l1) * TILE + l2], (unsigned long long)q[corner]);
-                        }
-            }
+                    for (int d = 0; d < 2; d++, corner++) {
+                        const int l0 = c[0][a] - t0 * TILE, l1 = c[1][b] - t1 * TILE, l2 = c[2][d] - t2 * TILE;
+                        if ((unsigned)l0 < TILE && (unsigned)l1 < TILE && (unsigned)l2 < TILE)
+                            atomicAdd(&acc[(l0 * TILE + l1) * TILE + l2], (unsigned long long)q[corner]);
+                    }
         }
     }
     __syncthreads();

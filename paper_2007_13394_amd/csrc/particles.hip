@@ -114,17 +114,22 @@ __global__ __launch_bounds__(256) void k_readout_kd_tiles(const float *__restric
                                                           const uint32_t *__restrict__ ids_tmp, uint32_t *ids,
                                                           int *flag)
 {
-    constexpr int H = TILE + 1, H3 = H * H * H;
+    // LDS rows of TILE + 1 floats (tile row and its +1 halo) padded to RS
+    constexpr int H = TILE + 1, RS = TILE + 4, ROWS = H * H, H3 = ROWS * RS;
     __shared__ float fl[3 * H3];
     const int nt = n / TILE, mask = n - 1;
     const int t = blockIdx.x;
     const int o0 = (t / (nt * nt)) * TILE, o1 = ((t / nt) % nt) * TILE, o2 = (t % nt) * TILE;
-    for (int i = threadIdx.x; i < H3; i += blockDim.x) {
-        const int a = i / (H * H), b = (i / H) % H, c = i % H;
-        const int64_t idx = ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + ((o2 + c) & mask);
-        fl[i] = F[idx];
-        fl[H3 + i] = F[cs + idx];
-        fl[2 * H3 + i] = F[2 * cs + idx];
+    // one thread per (component, row): four 16-byte loads (rows start 64-byte
+    // aligned) and the halo float
+    for (int r = threadIdx.x; r < 3 * ROWS; r += blockDim.x) {
+        const int d = r / ROWS, rr = r % ROWS, a = rr / H, b = rr % H;
+        const float *src = F + d * cs + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs;
+        const float4 *s4 = reinterpret_cast<const float4 *>(src + o2);
+        float *dst = fl + d * H3 + rr * RS;
+#pragma unroll
+        for (int j = 0; j < TILE / 4; j++) reinterpret_cast<float4 *>(dst)[j] = s4[j];
+        dst[TILE] = src[(o2 + TILE) & mask];
     }
     __syncthreads();
     const float nf = (float)n;
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(256) void k_readout_kd_tiles(const float *__restric
         for (int a = 0; a < 2; a++)
 #pragma unroll
             for (int b = 0; b < 2; b++) {
-                const int row = ((a0 + a) * H + (a1 + b)) * H + a2;
+                const int row = ((a0 + a) * H + (a1 + b)) * RS + a2;
                 const float wab = w0[a] * w1[b];
 #pragma unroll
                 for (int c = 0; c < 2; c++) {

@@ -54,7 +54,7 @@ struct Workspace {
 enum KernelKind {
     K_FILL = 0, K_PAINT, K_R2C, K_COLS_FWD, K_AXIS0, K_COLS_INV, K_C2R, K_READOUT_KD, K_READOUT,
     K_POWER_BIN, K_POWER_REDUCE, K_IC_PARTICLES, K_COPY, K_SORT_COUNT, K_SORT_SCAN, K_SORT_SCATTER,
-    K_COUNT
+    K_X0_FWD, K_X0_GREEN, K_X0_INV, K_COUNT
 };
 
 struct TraceRec {
@@ -126,6 +126,16 @@ enum { MULT_FORCE = 0, MULT_IC = 1, MULT_NONE = 2 };
 hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int64_t s_o, float2 *out0,
                         float2 *out1, float2 *out2, int64_t o_l, int64_t o_o, int n_cb, double coef,
                         const IcParams *ic, const float2 *tw, hipStream_t s);
+// Axis 0 of the force solve at N >= 256 as two passes (N = 16 x N/16), on
+// fields of nhp-padded half spectra whose planes hold `plane` = N nhp complex:
+// pass A (16-point DFTs over planes N/16 apart, twiddled; or its inverse) on
+// nf fields field_stride apart, and pass B fused with the gradient of the
+// inverse Laplacian (src may alias out0; outputs digit-reversed until the
+// inverse of pass A).
+hipError_t launch_x0_pass16(int logn, bool inverse, float2 *base, int64_t field_stride, int64_t plane, int nf,
+                            const float2 *tw, hipStream_t s);
+hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, float2 *out2, int64_t plane,
+                           int nhp, double coef, const float2 *tw, hipStream_t s);
 
 // ---- launchers (paint.hip)
 hipError_t launch_paint(const float *x, int64_t stride, int64_t first, int64_t count, int64_t quantum,

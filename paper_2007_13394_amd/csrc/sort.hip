@@ -40,19 +40,25 @@ __global__ __launch_bounds__(256) void k_sort_count(const float *__restrict__ x,
         const int64_t i = base + threadIdx.x;
         const bool live = i < P;
         const int k = live ? tile_key(x[i], x[P + i], x[2 * P + i], n) : -1;
-        // rank lanes with equal keys: one atomic per distinct key in the wavefront
+        // group lanes with equal keys (ballot loop: no memory traffic), then
+        // the leader of every group issues its atomic in one instruction
         uint64_t todo = __ballot(live);
-        int r = 0;
+        uint64_t group = 0;
+        int leader = 0;
         while (todo) {
-            const int leader = __ffsll((unsigned long long)todo) - 1;
-            const int lk = __shfl(k, leader);
+            const int l = __ffsll((unsigned long long)todo) - 1;
+            const int lk = __shfl(k, l);
             const uint64_t same = __ballot(live && k == lk);
-            int b = 0;
-            if (lane == leader) b = atomicAdd(cnt + lk, __popcll(same));
-            b = __shfl(b, leader);
-            if (live && k == lk) r = b + __popcll(same & ((1ull << lane) - 1));
+            if (live && k == lk) {
+                group = same;
+                leader = l;
+            }
             todo &= ~same;
         }
+        int b = 0;
+        if (live && lane == leader) b = atomicAdd(cnt + k, __popcll(group));
+        b = __shfl(b, leader);
+        const int r = b + __popcll(group & ((1ull << lane) - 1));
         if (live) {
             key[i] = k;
             rank[i] = r;

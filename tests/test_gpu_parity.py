@@ -122,7 +122,7 @@ def test_paint_segments_and_order_independence(c1, dev):
     assert torch.equal(mesh, mesh2)
 
 
-@pytest.mark.parametrize("n", [16, 64, 128])
+@pytest.mark.parametrize("n", [16, 64, 128, 256, 512])
 def test_fft_r2c_and_c2r_vs_oracle(dev, n):
     pm = _pm()
     cfg = I.config("C1", n_mesh=n, n_cdm=16, n_sites=2)
@@ -140,10 +140,11 @@ def test_fft_r2c_and_c2r_vs_oracle(dev, n):
     assert rel_l2(back.cpu().numpy().reshape(n, n, n), refb) < 1e-6
 
 
-def test_force_mesh_vs_oracle(c1, dev):
+@pytest.mark.parametrize("n", [64, 256])
+def test_force_mesh_vs_oracle(dev, n):
     pm = _pm()
-    cfg, ctx = c1
-    n = cfg["n_mesh"]
+    cfg = I.config("C1", n_mesh=n, n_cdm=32, n_sites=8)
+    ctx = pm.Ctx(pm.make_config(cfg))
     q = I.synthetic_density_q(n, seed=9)
     out = torch.empty(3 * n ** 3, dtype=torch.float32, device=dev)
     pm.pm_force_mesh(ctx, torch.from_numpy(q).to(dev), out)
@@ -302,3 +303,18 @@ def test_power_spectrum_vs_oracle(c1, dev):
             err = np.abs(pk[sel] - opk[sel]) / np.abs(opk[sel]).max()
             say("power", alo, ahi, blo, bhi, comp, err.max())
             assert err.max() < 1e-5
+
+
+def test_one_step_C5_vs_oracle(dev):
+    # 256^3 mesh: column and axis-0 passes on the register six-step transform
+    pm = _pm()
+    cfg = I.config("C5")
+    ctx = pm.Ctx(pm.make_config(cfg))
+    x, p = I.synthetic_state(cfg, seed=41)
+    ids = torch.arange(ctx.P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(ctx, ids)
+    xd, pd = torch.from_numpy(x).to(dev), torch.from_numpy(p).to(dev)
+    call = (0.406, 0.3565, 0.4555, 0.505)
+    pm.pm_step(ctx, xd, pd, *call)
+    order = np.argsort(ids.cpu().numpy())
+    _step_compare(cfg, xd.cpu().numpy()[:, order], pd.cpu().numpy()[:, order], x, p, call)
