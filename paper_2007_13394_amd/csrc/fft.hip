@@ -171,13 +171,6 @@ __device__ __forceinline__ void fft_from(float2 *buf, const float2 *__restrict__
     }
 }
 
-// Renumber workgroups so that each XCD (b mod 8) owns a contiguous tile range.
-__device__ __forceinline__ int xcd_tile(int b, int nb)
-{
-    const int q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
-    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
 template <int LOGN>
 struct RowCfg {
     static constexpr int N = 1 << LOGN, L = N / 2;

@@ -102,45 +102,91 @@ __global__ __launch_bounds__(256) void k_paint_tagged(const float *__restrict__ 
 // corners from its own particles and from particles of the seven lower
 // neighbour tiles whose flags say a +1 corner crosses into this tile.  The
 // sums are formed with LDS atomics and the tile is written once with plain
-// stores, so the mesh needs no zero fill and no global atomics.
-__global__ __launch_bounds__(256) void k_paint_tiles(const float *__restrict__ xs, const uint8_t *__restrict__ tags,
-                                                     int64_t P, const int *__restrict__ koff,
-                                                     const int64_t *__restrict__ quanta, int nseg, int lo, int hi,
-                                                     int n, unsigned long long *mesh)
+// stores, so the mesh needs no zero fill and no global atomics.  The own
+// tile's particles (one contiguous range) and the 19 neighbour ranges are
+// walked as one flat index space, two particles per thread per round, so
+// that the global loads of a thread are independent of each other.
+constexpr int PAINT_T = 256, NRANGE = 20;
+
+__global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float *__restrict__ xs,
+                                                         const uint8_t *__restrict__ tags, int64_t P,
+                                                         const int *__restrict__ koff,
+                                                         const int64_t *__restrict__ quanta, int nseg, int lo,
+                                                         int hi, int n, unsigned long long *mesh)
 {
     __shared__ unsigned long long acc[TILE * TILE * TILE];
     __shared__ long long qtab[MAX_SEG];
-    __shared__ int rng[27][2];   // particle ranges contributing to this tile
+    __shared__ int rbeg[NRANGE], rpre[NRANGE + 1];
     const int nt = n / TILE, mask = n - 1;
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int t0 = t / (nt * nt), t1 = (t / nt) % nt, t2 = t % nt;
-    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += blockDim.x) acc[i] = 0;
-    for (int i = threadIdx.x; i < nseg; i += blockDim.x) qtab[i] = quanta[i];
-    // the 27 (neighbour e, flags f) ranges with f containing e: own tile (e = 0,
-    // all flags) and the lower neighbours' particles whose +1 corner crosses
-    // into this tile; their offsets are fetched in parallel, once
+    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PAINT_T) acc[i] = 0;
+    for (int i = threadIdx.x; i < nseg; i += PAINT_T) qtab[i] = quanta[i];
+    // range 0: the own tile (all flags); ranges 1..19: lower neighbour e != 0,
+    // flags f containing e, in (e, f) order
     if (threadIdx.x < 64) {
         const int e = threadIdx.x >> 3, f = threadIdx.x & 7;
-        if ((f & e) == e) {
-            int slot = 0;   // index of (e, f) among the valid pairs, in (e, f) order
-            for (int ee = 0; ee < e; ee++) slot += 1 << (3 - __popc(ee));
+        int slot = -1, b = 0, len = 0;
+        if (e == 0 && f == 0) {
+            slot = 0;
+            b = koff[t * 8];
+            len = koff[t * 8 + 8] - b;
+        } else if (e != 0 && (f & e) == e) {
+            slot = 1;
+            for (int ee = 1; ee < e; ee++) slot += 1 << (3 - __popc(ee));
             for (int ff = 0; ff < f; ff++) slot += ((ff & e) == e) ? 1 : 0;
             const int s0 = (t0 - (e & 1) + nt) % nt, s1 = (t1 - ((e >> 1) & 1) + nt) % nt,
                       s2 = (t2 - ((e >> 2) & 1) + nt) % nt;
             const int tn = (s0 * nt + s1) * nt + s2;
-            rng[slot][0] = koff[tn * 8 + f];
-            rng[slot][1] = koff[tn * 8 + f + 1];
+            b = koff[tn * 8 + f];
+            len = koff[tn * 8 + f + 1] - b;
+        }
+        if (slot >= 0) {
+            rbeg[slot] = b;
+            rpre[slot + 1] = len;
         }
     }
     __syncthreads();
-    for (int r = 0; r < 27; r++) {
-        const int beg = rng[r][0], end = rng[r][1];
-        for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-            const int g = tags[i];
-            if (g < lo || g >= hi) continue;
+    if (threadIdx.x == 0) {
+        rpre[0] = 0;
+        for (int r = 1; r <= NRANGE; r++) rpre[r] += rpre[r - 1];
+    }
+    __syncthreads();
+    const int total = rpre[NRANGE];
+    const int ox = t0 * TILE, oy = t1 * TILE, oz = t2 * TILE;
+    for (int k0 = threadIdx.x; k0 < total; k0 += 2 * PAINT_T) {
+        int idx[2];
+        bool ok[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int k = k0 + u * PAINT_T;
+            ok[u] = k < total;
+            int r = 0;   // last range whose prefix is <= k
+#pragma unroll
+            for (int step = 16; step >= 1; step >>= 1)
+                if (r + step < NRANGE && rpre[r + step] <= k) r += step;
+            idx[u] = ok[u] ? rbeg[r] + (k - rpre[r]) : 0;
+        }
+        float u0[2], u1[2], u2[2];
+        int g[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            if (ok[u]) {
+                u0[u] = xs[idx[u]];
+                u1[u] = xs[P + idx[u]];
+                u2[u] = xs[2 * P + idx[u]];
+                g[u] = tags[idx[u]];
+            } else {
+                u0[u] = u1[u] = u2[u] = 0.f;
+                g[u] = -1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            if (!ok[u] || g[u] < lo || g[u] >= hi) continue;
             int c[3][2];
             long long q[8];
-            cic_quanta(xs[i], xs[P + i], xs[2 * P + i], (long long)qtab[g], mask, c, q);
+            cic_quanta(u0[u], u1[u], u2[u], (long long)qtab[g[u]], mask, c, q);
             int corner = 0;
 #pragma unroll
             for (int a = 0; a < 2; a++)
@@ -148,16 +194,16 @@ __global__ __launch_bounds__(256) void k_paint_tiles(const float *__restrict__ x
                 for (int b = 0; b < 2; b++)
 #pragma unroll
                     for (int d = 0; d < 2; d++, corner++) {
-                        const int l0 = c[0][a] - t0 * TILE, l1 = c[1][b] - t1 * TILE, l2 = c[2][d] - t2 * TILE;
+                        const int l0 = c[0][a] - ox, l1 = c[1][b] - oy, l2 = c[2][d] - oz;
                         if ((unsigned)l0 < TILE && (unsigned)l1 < TILE && (unsigned)l2 < TILE)
                             atomicAdd(&acc[(l0 * TILE + l1) * TILE + l2], (unsigned long long)q[corner]);
                     }
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += blockDim.x) {
+    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PAINT_T) {
         const int l0 = i / (TILE * TILE), l1 = (i / TILE) % TILE, l2 = i % TILE;
-        mesh[((int64_t)(t0 * TILE + l0) * n + (t1 * TILE + l1)) * n + (t2 * TILE + l2)] = acc[i];
+        mesh[((int64_t)(ox + l0) * n + (oy + l1)) * n + (oz + l2)] = acc[i];
     }
 }
 
@@ -191,7 +237,7 @@ hipError_t launch_paint_tiles(const float *xs, const uint8_t *tags, int64_t P, c
 {
     const int nt = n / TILE;
     if (nt < 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_paint_tiles, dim3((unsigned)(nt * nt * nt)), dim3(256), 0, s, xs, tags, P, koff, quanta,
+    hipLaunchKernelGGL(k_paint_tiles, dim3((unsigned)(nt * nt * nt)), dim3(PAINT_T), 0, s, xs, tags, P, koff, quanta,
                        nseg, seg_lo, seg_hi, n, reinterpret_cast<unsigned long long *>(mesh));
     return hipGetLastError();
 }

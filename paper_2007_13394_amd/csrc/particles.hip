@@ -107,36 +107,55 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(float *x, float *p, 
 // +1 halo are staged in LDS, then every particle sorted into the tile is read
 // out from LDS, kicked and drifted; results go to the caller's arrays at the
 // particle's sorted index (with its id, when ids are attached).
-__global__ __launch_bounds__(256) void k_readout_kd_tiles(const float *__restrict__ xs, const float *__restrict__ ps,
-                                                          int64_t P, const int *__restrict__ koff,
-                                                          const float *__restrict__ F, int64_t rs, int64_t cs, int n,
-                                                          float kick, float drift, float *x, float *p,
-                                                          const uint32_t *__restrict__ ids_tmp, uint32_t *ids,
-                                                          int *flag)
+// 512 threads: the 69 KB LDS tile allows two workgroups per CU, so the
+// workgroup itself must carry enough waves to hide memory latency.  The
+// particle range and each thread's first particle are loaded before the LDS
+// fill, and the next particle is loaded before the current one is stored.
+constexpr int READOUT_T = 512;
+
+__global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__restrict__ xs,
+                                                                const float *__restrict__ ps, int64_t P,
+                                                                const int *__restrict__ koff,
+                                                                const float *__restrict__ F, int64_t rs,
+                                                                int64_t cs, int n, float kick, float drift,
+                                                                float *x, float *p,
+                                                                const uint32_t *__restrict__ ids_tmp,
+                                                                uint32_t *ids, int *flag)
 {
     // LDS rows of TILE + 1 floats (tile row and its +1 halo) padded to RS
     constexpr int H = TILE + 1, RS = TILE + 4, ROWS = H * H, H3 = ROWS * RS;
-    __shared__ float fl[3 * H3];
+    __shared__ __align__(16) float fl[3 * H3];
     const int nt = n / TILE, mask = n - 1;
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int o0 = (t / (nt * nt)) * TILE, o1 = ((t / nt) % nt) * TILE, o2 = (t % nt) * TILE;
-    // one thread per (component, row): four 16-byte loads (rows start 64-byte
-    // aligned) and the halo float
-    for (int r = threadIdx.x; r < 3 * ROWS; r += blockDim.x) {
+    const int beg = koff[t * 8], end = koff[t * 8 + 8];
+    int i = beg + threadIdx.x;
+    float u0 = 0.f, u1 = 0.f, u2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
+    if (i < end) {
+        u0 = xs[i];
+        u1 = xs[P + i];
+        u2 = xs[2 * P + i];
+        v0 = ps[i];
+        v1 = ps[P + i];
+        v2 = ps[2 * P + i];
+    }
+    // four lanes per (component, row), one 16-byte load each (rows start
+    // 64-byte aligned), then one lane per row for the halo float
+    for (int e = threadIdx.x; e < 3 * ROWS * 4; e += READOUT_T) {
+        const int r = e >> 2, j = e & 3;
+        const int d = r / ROWS, rr = r % ROWS, a = rr / H, b = rr % H;
+        const float *src = F + d * cs + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + o2;
+        reinterpret_cast<float4 *>(fl + d * H3 + rr * RS)[j] = reinterpret_cast<const float4 *>(src)[j];
+    }
+    for (int r = threadIdx.x; r < 3 * ROWS; r += READOUT_T) {
         const int d = r / ROWS, rr = r % ROWS, a = rr / H, b = rr % H;
         const float *src = F + d * cs + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs;
-        const float4 *s4 = reinterpret_cast<const float4 *>(src + o2);
-        float *dst = fl + d * H3 + rr * RS;
-#pragma unroll
-        for (int j = 0; j < TILE / 4; j++) reinterpret_cast<float4 *>(dst)[j] = s4[j];
-        dst[TILE] = src[(o2 + TILE) & mask];
+        fl[d * H3 + rr * RS + TILE] = src[(o2 + TILE) & mask];
     }
     __syncthreads();
     const float nf = (float)n;
     bool bad = false;
-    const int beg = koff[t * 8], end = koff[t * 8 + 8];
-    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        const float u0 = xs[i], u1 = xs[P + i], u2 = xs[2 * P + i];
+    while (i < end) {
         const float f0 = floorf(u0), f1 = floorf(u1), f2 = floorf(u2);
         const float d0 = u0 - f0, d1 = u1 - f1, d2 = u2 - f2;
         const int a0 = ((int)f0 - o0) & mask, a1 = ((int)f1 - o1) & mask, a2 = ((int)f2 - o2) & mask;
@@ -156,13 +175,22 @@ __global__ __launch_bounds__(256) void k_readout_kd_tiles(const float *__restric
                     s2 += w * fl[2 * H3 + row + c];
                 }
             }
-        const float p0 = ps[i] + kick * s0;
-        const float p1 = ps[P + i] + kick * s1;
-        const float p2 = ps[2 * P + i] + kick * s2;
+        const float p0 = v0 + kick * s0;
+        const float p1 = v1 + kick * s1;
+        const float p2 = v2 + kick * s2;
         const float x0 = wrapf(u0 + drift * p0, nf);
         const float x1 = wrapf(u1 + drift * p1, nf);
         const float x2 = wrapf(u2 + drift * p2, nf);
         bad |= !(isfinite(p0) && isfinite(p1) && isfinite(p2) && isfinite(x0) && isfinite(x1) && isfinite(x2));
+        const int inext = i + READOUT_T;
+        if (inext < end) {
+            u0 = xs[inext];
+            u1 = xs[P + inext];
+            u2 = xs[2 * P + inext];
+            v0 = ps[inext];
+            v1 = ps[P + inext];
+            v2 = ps[2 * P + inext];
+        }
         p[i] = p0;
         p[P + i] = p1;
         p[2 * P + i] = p2;
@@ -170,6 +198,7 @@ __global__ __launch_bounds__(256) void k_readout_kd_tiles(const float *__restric
         x[P + i] = x1;
         x[2 * P + i] = x2;
         if (ids) ids[i] = ids_tmp[i];
+        i = inext;
     }
     if (bad) atomicOr(flag, FLAG_NAN);
 }
@@ -370,7 +399,7 @@ hipError_t launch_readout_kd_tiles(const float *xs, const float *ps, int64_t P, 
 {
     const int nt = n / TILE;
     if (nt < 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_readout_kd_tiles, dim3((unsigned)(nt * nt * nt)), dim3(256), 0, s, xs, ps, P, koff,
+    hipLaunchKernelGGL(k_readout_kd_tiles, dim3((unsigned)(nt * nt * nt)), dim3(READOUT_T), 0, s, xs, ps, P, koff,
                        reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, x, p, ids_tmp,
                        ids, flag);
     return hipGetLastError();

@@ -25,6 +25,15 @@ constexpr int MAX_SEG = 65;
 constexpr int MAX_BINS = 2048;
 constexpr int POWER_BLOCKS = 512;
 
+// Workgroups are dispatched round-robin over the eight XCDs (b mod 8), each
+// with its own L2.  Renumbering them so that each XCD owns a contiguous range
+// of tiles lets neighbouring tiles share cache lines in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Device-side guard bits (workspace flag word).
 enum { FLAG_OVERFLOW = 1, FLAG_NAN = 2 };
 

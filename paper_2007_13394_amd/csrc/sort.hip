@@ -32,11 +32,17 @@ __device__ __forceinline__ int tile_key(float u0, float u1, float u2, int n)
     return t * 8 + f;
 }
 
-__global__ __launch_bounds__(256) void k_sort_count(const float *__restrict__ x, int64_t P, int n, int *cnt,
-                                                    int *key, int *rank)
+// Each workgroup takes SORT_CH consecutive particles, workgroups numbered so
+// that each XCD owns a contiguous run of chunks (the scatter of a nearly
+// sorted state then writes whole cache lines from one L2).
+constexpr int SORT_T = 256, SORT_CH = SORT_T * 8;
+
+__global__ __launch_bounds__(SORT_T) void k_sort_count(const float *__restrict__ x, int64_t P, int n, int *cnt,
+                                                       int *key, int *rank)
 {
     const int lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < P; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * SORT_CH;
+    for (int64_t base = c0; base < c0 + SORT_CH && base < P; base += SORT_T) {
         const int64_t i = base + threadIdx.x;
         const bool live = i < P;
         const int k = live ? tile_key(x[i], x[P + i], x[2 * P + i], n) : -1;
@@ -140,13 +146,15 @@ __global__ void k_scan_add(int *out, int64_t n, const int *sums)
         out[i] += sums[i / SCAN_B];
 }
 
-__global__ __launch_bounds__(256) void k_sort_scatter(const float *__restrict__ x, const float *__restrict__ p,
+__global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict__ x, const float *__restrict__ p,
                                                       const uint8_t *__restrict__ tag_in, int64_t P, int nseg,
                                                       const int64_t *__restrict__ seg_off, const int *key,
                                                       const int *rank, const int *off, float *xs, float *ps,
                                                       uint8_t *tag_out, const uint32_t *ids_in, uint32_t *ids_out)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * SORT_CH;
+    const int64_t c1 = c0 + SORT_CH < P ? c0 + SORT_CH : P;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += SORT_T) {
         const int64_t d = (int64_t)off[key[i]] + rank[i];
         xs[d] = x[i];
         xs[P + d] = x[P + i];
@@ -172,7 +180,9 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const float *__restrict__ 
 
 hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, int *key, int *rank, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_count, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P, n, cnt, key, rank);
+    const int64_t nb = (P + SORT_CH - 1) / SORT_CH;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sort_count, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SORT_T), 0, s, x, P, n, cnt, key, rank);
     return hipGetLastError();
 }
 
@@ -190,7 +200,9 @@ hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *ta
                                const int64_t *seg_off, const int *key, const int *rank, const int *off, float *xs,
                                float *ps, uint8_t *tag_out, const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_scatter, dim3(grid_for(P, 256)), dim3(256), 0, s, x, p, tag_in, P, nseg, seg_off, key,
+    const int64_t nb = (P + SORT_CH - 1) / SORT_CH;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SORT_T), 0, s, x, p, tag_in, P, nseg, seg_off, key,
                        rank, off, xs, ps, tag_out, ids_in, ids_out);
     return hipGetLastError();
 }

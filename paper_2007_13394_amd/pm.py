@@ -136,11 +136,16 @@ class Ctx:
         h = _vp()
         _check(_lib.pm_init(C.byref(cfg), C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), _stream(stream), C.byref(h)))
         self.h = h
+        self._free = _lib.pm_free   # held here: module globals may be gone at interpreter exit
+
+    def close(self):
+        """Release the context (the workspace tensor is freed with the object)."""
+        if getattr(self, "h", None) is not None and self.h.value:
+            self._free(self.h)
+            self.h = None
 
     def __del__(self):
-        if getattr(self, "h", None) is not None and self.h.value:
-            _lib.pm_free(self.h)
-            self.h = None
+        self.close()
 
     def particles(self):
         """Fresh (x, p) float32 [3, P] device tensors."""
