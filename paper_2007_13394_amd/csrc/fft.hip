@@ -106,11 +106,21 @@ struct Dft<1, INV> {
     __device__ __forceinline__ static void run(float2 *) {}
 };
 
+// LDS index with one pad slot per 2^PS elements (PS = 0: none).  A Stockham
+// stage writes its outputs R elements apart; with 8-byte elements and a
+// stride of 16 every lane of a wavefront would hit the same bank pair.
+template <int PS>
+__device__ __forceinline__ int pad(int i)
+{
+    return PS ? i + (i >> PS) : i;
+}
+constexpr int padded(int n, int ps) { return ps ? n + (n >> ps) + 1 : n; }
+
 // One Stockham stage of radix R over NC independent transforms of length L
 // held in LDS: element (c, l) at buf[c * SC + l * SL].  NS = product of the
 // radices already applied.  All butterflies of a thread are read before the
 // barrier and written after it, so the stage runs in place.
-template <int L, int R, int NS, int NC, int T, bool COLMAJ, int SL, int SC, bool INV>
+template <int L, int R, int NS, int NC, int T, bool COLMAJ, int SL, int SC, bool INV, int PS = 0>
 __device__ __forceinline__ void stage(float2 *buf, const float2 *__restrict__ twL)
 {
     constexpr int NB = NC * (L / R);
@@ -132,7 +142,7 @@ __device__ __forceinline__ void stage(float2 *buf, const float2 *__restrict__ tw
             }
             const int k = j & (NS - 1);
 #pragma unroll
-            for (int r = 0; r < R; r++) v[b][r] = buf[c * SC + (j + r * (L / R)) * SL];
+            for (int r = 0; r < R; r++) v[b][r] = buf[pad<PS>(c * SC + (j + r * (L / R)) * SL)];
             if (NS > 1) {
 #pragma unroll
                 for (int r = 1; r < R; r++) {
@@ -151,14 +161,14 @@ __device__ __forceinline__ void stage(float2 *buf, const float2 *__restrict__ tw
         const int bf = tid + b * T;
         if ((NB % T == 0) || bf < NB) {
 #pragma unroll
-            for (int r = 0; r < R; r++) buf[dst[b] + r * NS * SL] = v[b][r];
+            for (int r = 0; r < R; r++) buf[pad<PS>(dst[b] + r * NS * SL)] = v[b][r];
         }
     }
     __syncthreads();
 }
 
 // Full transform: stages of at most 2^MAXB, bits split as evenly as possible.
-template <int L, int NS, int NC, int T, bool COLMAJ, int SL, int SC, bool INV, int MAXB>
+template <int L, int NS, int NC, int T, bool COLMAJ, int SL, int SC, bool INV, int MAXB, int PS = 0>
 __device__ __forceinline__ void fft_from(float2 *buf, const float2 *__restrict__ twL)
 {
     if constexpr (NS < L) {
@@ -166,8 +176,8 @@ __device__ __forceinline__ void fft_from(float2 *buf, const float2 *__restrict__
         constexpr int nst = (rem + MAXB - 1) / MAXB;
         constexpr int bits = (rem + nst - 1) / nst;
         constexpr int R = 1 << bits;
-        stage<L, R, NS, NC, T, COLMAJ, SL, SC, INV>(buf, twL);
-        fft_from<L, NS * R, NC, T, COLMAJ, SL, SC, INV, MAXB>(buf, twL);
+        stage<L, R, NS, NC, T, COLMAJ, SL, SC, INV, PS>(buf, twL);
+        fft_from<L, NS * R, NC, T, COLMAJ, SL, SC, INV, MAXB, PS>(buf, twL);
     }
 }
 
@@ -178,9 +188,9 @@ struct RowCfg {
     static constexpr int T = 256;
 };
 
-template <int LOGN>
+template <int LOGN, int WW = TILE_W>
 struct ColCfg {
-    static constexpr int N = 1 << LOGN, W = TILE_W, E = N * W;
+    static constexpr int N = 1 << LOGN, W = WW, E = N * W;
     // 16 elements per thread (at least one wavefront): keeps a tile's
     // register footprint below the 128-VGPR budget of 16 waves per CU.
     static constexpr int T = (E / 16) > 64 ? ((E / 16) < 1024 ? (E / 16) : 1024) : 64;
@@ -280,11 +290,11 @@ __global__ __launch_bounds__(256) void k_c2r_rows(const float2 *src, int64_t src
 }
 
 // ---------------------------------------------------------------- columns
-template <int LOGN, bool INV>
-__global__ __launch_bounds__(ColCfg<LOGN>::T) void k_cols(float2 *base, int64_t stride_l, int64_t stride_o,
-                                                          int n_cb, const float2 *__restrict__ tw)
+template <int LOGN, bool INV, int WW>
+__global__ __launch_bounds__((ColCfg<LOGN, WW>::T)) void k_cols(float2 *base, int64_t stride_l, int64_t stride_o,
+                                                              int n_cb, const float2 *__restrict__ tw)
 {
-    using C = ColCfg<LOGN>;
+    using C = ColCfg<LOGN, WW>;
     constexpr int N = C::N, W = C::W, E = C::E, T = C::T;
     __shared__ float2 buf[E];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -606,6 +616,119 @@ __global__ __launch_bounds__(X0Cfg<N>::T, 4) void k_x0_green(const float2 *src, 
     }
 }
 
+// Rows fused with pass A: one workgroup takes the 16 rows (plane j1 + N2 j,
+// row x1), j < 16, of a field, so the 16-point axis-0 DFT across them costs
+// no HBM pass of its own.  Forward: real-to-complex of the 16 int64 rows,
+// then for every column k the DFT over j and the twiddle w_N^(j1 m), stored
+// in plane j1 + N2 m.  Inverse: for every column the twiddle conj(w_N^(j1 m))
+// and the inverse DFT over m, then the 16 complex-to-real rows.  The x1
+// transform commutes with both, so it may run before or after.  L = N/2
+// threads, 16 rows of L complex in LDS (128 KiB at N = 2048).
+template <int LOGN>
+__global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const int64_t *src, float2 *dst, int nhp, int64_t plane,
+                                                            double scale, double offset,
+                                                            const float2 *__restrict__ tw, int *flag)
+{
+    constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, PS = 4;
+    __shared__ float2 buf[padded(RB * L, PS)];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int j1 = tile / N, x1 = tile % N;
+    const int tid = threadIdx.x;
+    bool bad = false;
+#pragma unroll 4
+    for (int e = tid; e < RB * L; e += T) {
+        const int r = e / L, m = e % L;
+        const longlong2 q =
+            *reinterpret_cast<const longlong2 *>(src + ((int64_t)(j1 + N2 * r) * N + x1) * N + 2 * m);
+        bad |= (q.x < -(1LL << 40)) | (q.y < -(1LL << 40));
+        buf[pad<PS>(e)] = make_float2((float)((double)q.x * scale + offset), (float)((double)q.y * scale + offset));
+    }
+    if (bad) atomicOr(flag, FLAG_OVERFLOW);
+    __syncthreads();
+    fft_from<L, 1, RB, T, false, 1, L, false, 4, PS>(buf, tw + L);
+    const float2 *twN = tw + N;
+    float2 *d0 = dst + (int64_t)j1 * plane + (int64_t)x1 * nhp;
+    const int64_t pstep = (int64_t)N2 * plane;
+    for (int k = tid; k <= L; k += T) {
+        const float2 w = twN[k];
+        float2 v[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            // X_k = (Z_k + conj Z_{L-k}) / 2 - i w^k (Z_k - conj Z_{L-k}) / 2
+            const float2 zk = buf[pad<PS>(r * L + (k & (L - 1)))];
+            const float2 zc = cconj(buf[pad<PS>(r * L + ((L - k) & (L - 1)))]);
+            const float2 sum = cadd(zk, zc), t = cmul(w, csub(zk, zc));
+            v[r] = make_float2(0.5f * (sum.x + t.y), 0.5f * (sum.y - t.x));
+        }
+        Dft<16, false>::run(v);
+#pragma unroll
+        for (int m = 1; m < 16; m++) v[m] = cmul(v[m], twN[j1 * m]);
+#pragma unroll
+        for (int m = 0; m < 16; m++) d0[m * pstep + k] = v[m];
+    }
+    const int padc = nhp - (L + 1);
+    for (int e = tid; e < 16 * padc; e += T) {
+        const int m = e / padc, k = L + 1 + e % padc;
+        d0[m * pstep + k] = make_float2(0.f, 0.f);
+    }
+}
+
+template <int LOGN>
+__global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, float *dst, int64_t dst_stride,
+                                                            int nhp, int64_t plane, const float2 *__restrict__ tw)
+{
+    constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, LS = L + 1, PS = 4;
+    __shared__ float2 buf[padded(RB * LS, PS)];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int j1 = tile / N, x1 = tile % N;
+    const int tid = threadIdx.x;
+    const float2 *twN = tw + N;
+    const float2 *s0 = src + (int64_t)j1 * plane + (int64_t)x1 * nhp;
+    const int64_t pstep = (int64_t)N2 * plane;
+    {
+        // column k = tid, and the Nyquist column k = L on thread 0, whose
+        // loads are issued with the others (a second round would leave the
+        // whole workgroup waiting on one thread's loads)
+        float2 v[16], vn[16];
+#pragma unroll
+        for (int m = 0; m < 16; m++) v[m] = s0[m * pstep + tid];
+        if (tid == 0) {
+#pragma unroll
+            for (int m = 0; m < 16; m++) vn[m] = s0[m * pstep + L];
+        }
+#pragma unroll
+        for (int m = 1; m < 16; m++) v[m] = cmul(v[m], cconj(twN[j1 * m]));
+        Dft<16, true>::run(v);
+#pragma unroll
+        for (int r = 0; r < 16; r++) buf[pad<PS>(r * LS + tid)] = v[r];
+        if (tid == 0) {
+#pragma unroll
+            for (int m = 1; m < 16; m++) vn[m] = cmul(vn[m], cconj(twN[j1 * m]));
+            Dft<16, true>::run(vn);
+#pragma unroll
+            for (int r = 0; r < 16; r++) buf[pad<PS>(r * LS + L)] = vn[r];
+        }
+    }
+    __syncthreads();
+    // Z_k = A + i B, A = X_k + conj X_{L-k}, B = (X_k - conj X_{L-k}) exp(+2 pi i k / N);
+    // Z_{L-k} = conj A + i conj B.
+    for (int e = tid; e < RB * (L / 2 + 1); e += T) {
+        const int r = e / (L / 2 + 1), k = e % (L / 2 + 1);
+        const float2 X = buf[pad<PS>(r * LS + k)], Y = cconj(buf[pad<PS>(r * LS + L - k)]);
+        const float2 A = cadd(X, Y), B = cmul(cconj(twN[k]), csub(X, Y));
+        buf[pad<PS>(r * LS + k)] = make_float2(A.x - B.y, A.y + B.x);
+        if (k != 0 && k != L / 2) buf[pad<PS>(r * LS + L - k)] = make_float2(A.x + B.y, B.x - A.y);
+    }
+    __syncthreads();
+    fft_from<L, 1, RB, T, false, 1, LS, true, 4, PS>(buf, tw + L);
+#pragma unroll 4
+    for (int e = tid; e < RB * L; e += T) {
+        const int r = e / L, m = e % L;
+        *reinterpret_cast<float2 *>(dst + ((int64_t)(j1 + N2 * r) * N + x1) * dst_stride + 2 * m) =
+            buf[pad<PS>(r * LS + m)];
+    }
+}
+
 }  // namespace
 
 #define PM_DISPATCH_LOGN(logn, MACRO) \
@@ -669,10 +792,10 @@ hipError_t launch_cols(int logn, bool inverse, float2 *base, int64_t stride_l, i
 #define COLS(LG)                                                                                     \
     {                                                                                                \
         if (inverse)                                                                                 \
-            hipLaunchKernelGGL((k_cols<LG, true>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base,        \
+            hipLaunchKernelGGL((k_cols<LG, true, TILE_W>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base,  \
                                stride_l, stride_o, n_cb, tw);                                       \
         else                                                                                         \
-            hipLaunchKernelGGL((k_cols<LG, false>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base,       \
+            hipLaunchKernelGGL((k_cols<LG, false, TILE_W>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base, \
                                stride_l, stride_o, n_cb, tw);                                       \
     }
     PM_DISPATCH_LOGN(logn, COLS)
@@ -746,6 +869,41 @@ hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *ou
     default: X0B(2048); break;
     }
 #undef X0B
+    return hipGetLastError();
+}
+
+hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int64_t plane, double scale,
+                         double offset, const float2 *tw, int *flag, hipStream_t s)
+{
+    if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
+#define R2CX(LG)                                                                                     \
+    hipLaunchKernelGGL((k_r2c_x0<LG>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, nhp, plane, scale, offset, \
+                       tw, flag)
+    switch (logn) {
+    case 8: R2CX(8); break;
+    case 9: R2CX(9); break;
+    case 10: R2CX(10); break;
+    default: R2CX(11); break;
+    }
+#undef R2CX
+    return hipGetLastError();
+}
+
+hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int nhp, int64_t plane,
+                         const float2 *tw, hipStream_t s)
+{
+    if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
+#define C2RX(LG)                                                                                     \
+    hipLaunchKernelGGL((k_c2r_x0<LG>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, dst_stride, nhp, plane, tw)
+    switch (logn) {
+    case 8: C2RX(8); break;
+    case 9: C2RX(9); break;
+    case 10: C2RX(10); break;
+    default: C2RX(11); break;
+    }
+#undef C2RX
     return hipGetLastError();
 }
 

@@ -236,21 +236,29 @@ pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s)
     float2 *F = c->ws.f;
     const int64_t cs = n2 * nhp;
     const double scale = ldexp(1.0, -c->cfg.shift);
+    const double coef = 1.5 * c->cfg.omega_m / ((double)n2 * n);
+    if (lg >= 8) {
+        // axis 0 as 16 x N/16 (four-step): the 16-point pass rides on the row
+        // transforms, the N/16-point pass on the gradient of the inverse
+        // Laplacian; the spectrum stays digit-reversed along axis 0 in between
+        const int64_t plane = (int64_t)n * nhp;
+        LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0(lg, src, F, (int)nhp, plane, scale, -1.0, c->ws.tw, c->ws.flag, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_X0_GREEN, pm::launch_x0_green(lg, F, F, F + cs, F + 2 * cs, plane, (int)nhp, coef, c->ws.tw, s));
+        for (int d = 0; d < 3; d++) {
+            LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + d * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
+            LAUNCH(pm::K_C2R_X0, pm::launch_c2r_x0(lg, F + d * cs, reinterpret_cast<float *>(F + d * cs), 2 * nhp,
+                                                   (int)nhp, plane, c->ws.tw, s));
+        }
+        return PM_OK;
+    }
     // axis 2: density contrast, real-to-complex rows
     LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, src, n, F, nhp, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
     // axis 1
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
     // axis 0 forward, gradient of the inverse Laplacian, axis 0 inverses (in place on F0)
-    const double coef = 1.5 * c->cfg.omega_m / ((double)n2 * n);
-    if (lg >= 8) {
-        const int64_t plane = (int64_t)n * nhp;
-        LAUNCH(pm::K_X0_FWD, pm::launch_x0_pass16(lg, false, F, cs, plane, 1, c->ws.tw, s));
-        LAUNCH(pm::K_X0_GREEN, pm::launch_x0_green(lg, F, F, F + cs, F + 2 * cs, plane, (int)nhp, coef, c->ws.tw, s));
-        LAUNCH(pm::K_X0_INV, pm::launch_x0_pass16(lg, true, F, cs, plane, 3, c->ws.tw, s));
-    } else {
-        LAUNCH(pm::K_AXIS0, pm::launch_axis0(lg, pm::MULT_FORCE, F, n * nhp, nhp, F, F + cs, F + 2 * cs, n * nhp,
-                                             nhp, ncb, coef, nullptr, c->ws.tw, s));
-    }
+    LAUNCH(pm::K_AXIS0, pm::launch_axis0(lg, pm::MULT_FORCE, F, n * nhp, nhp, F, F + cs, F + 2 * cs, n * nhp, nhp,
+                                         ncb, coef, nullptr, c->ws.tw, s));
     for (int d = 0; d < 3; d++) {
         LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + d * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
         LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + d * cs, nhp, reinterpret_cast<float *>(F + d * cs), 2 * nhp,
@@ -381,7 +389,7 @@ void pm_free(pm_ctx *ctx)
 static const char *kKernelNames[pm::K_COUNT] = {
     "fill",      "paint",        "r2c_rows",     "cols_fwd",   "axis0",      "cols_inv",   "c2r_rows",
     "readout_kick_drift", "readout", "power_bin", "power_reduce", "ic_particles", "copy", "sort_count",
-    "sort_scan", "sort_scatter", "x0_fwd", "x0_green", "x0_inv"};
+    "sort_scan", "sort_scatter", "x0_fwd", "x0_green", "x0_inv", "r2c_x0", "c2r_x0"};
 
 const char *pm_kernel_name(int32_t kind)
 {

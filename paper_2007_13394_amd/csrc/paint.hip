@@ -118,8 +118,11 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float *__restrict
     __shared__ long long qtab[MAX_SEG];
     __shared__ int rbeg[NRANGE], rpre[NRANGE + 1];
     const int nt = n / TILE, mask = n - 1;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int t0 = t / (nt * nt), t1 = (t / nt) % nt, t2 = t % nt;
+    // workgroups walk the tiles in row-major order (consecutive tiles share
+    // rows of the mesh); particle ranges are looked up by Morton index
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int t0 = b / (nt * nt), t1 = (b / nt) % nt, t2 = b % nt;
+    const int t = tile_index(t0, t1, t2);
     for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PAINT_T) acc[i] = 0;
     for (int i = threadIdx.x; i < nseg; i += PAINT_T) qtab[i] = quanta[i];
     // range 0: the own tile (all flags); ranges 1..19: lower neighbour e != 0,
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float *__restrict
             for (int ff = 0; ff < f; ff++) slot += ((ff & e) == e) ? 1 : 0;
             const int s0 = (t0 - (e & 1) + nt) % nt, s1 = (t1 - ((e >> 1) & 1) + nt) % nt,
                       s2 = (t2 - ((e >> 2) & 1) + nt) % nt;
-            const int tn = (s0 * nt + s1) * nt + s2;
+            const int tn = tile_index(s0, s1, s2);
             b = koff[tn * 8 + f];
             len = koff[tn * 8 + f + 1] - b;
         }

@@ -122,12 +122,17 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__r
                                                                 const uint32_t *__restrict__ ids_tmp,
                                                                 uint32_t *ids, int *flag)
 {
-    // LDS rows of TILE + 1 floats (tile row and its +1 halo) padded to RS
-    constexpr int H = TILE + 1, RS = TILE + 4, ROWS = H * H, H3 = ROWS * RS;
-    __shared__ __align__(16) float fl[3 * H3];
+    // LDS: the (TILE + 1)^3 cells of the tile and its +1 halo, the three
+    // force components of a cell interleaved in one float4
+    constexpr int H = TILE + 1, ROWS = H * H;
+    __shared__ float4 fl[ROWS * H];
     const int nt = n / TILE, mask = n - 1;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int o0 = (t / (nt * nt)) * TILE, o1 = ((t / nt) % nt) * TILE, o2 = (t % nt) * TILE;
+    // workgroups walk the tiles in row-major order (consecutive tiles share
+    // rows of the force mesh); particle ranges are looked up by Morton index
+    const int bt = xcd_tile(blockIdx.x, gridDim.x);
+    const int t0 = bt / (nt * nt), t1 = (bt / nt) % nt, t2 = bt % nt;
+    const int t = tile_index(t0, t1, t2);
+    const int o0 = t0 * TILE, o1 = t1 * TILE, o2 = t2 * TILE;
     const int beg = koff[t * 8], end = koff[t * 8 + 8];
     int i = beg + threadIdx.x;
     float u0 = 0.f, u1 = 0.f, u2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
@@ -139,18 +144,24 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__r
         v1 = ps[P + i];
         v2 = ps[2 * P + i];
     }
-    // four lanes per (component, row), one 16-byte load each (rows start
-    // 64-byte aligned), then one lane per row for the halo float
-    for (int e = threadIdx.x; e < 3 * ROWS * 4; e += READOUT_T) {
-        const int r = e >> 2, j = e & 3;
-        const int d = r / ROWS, rr = r % ROWS, a = rr / H, b = rr % H;
-        const float *src = F + d * cs + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + o2;
-        reinterpret_cast<float4 *>(fl + d * H3 + rr * RS)[j] = reinterpret_cast<const float4 *>(src)[j];
+    // (row, quad) tasks: one 16-byte load per component (rows start 64-byte
+    // aligned), four cells written; then one task per row for the halo cell
+    for (int e = threadIdx.x; e < ROWS * 4; e += READOUT_T) {
+        const int rr = e >> 2, j = e & 3, a = rr / H, b = rr % H;
+        const float *src = F + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + o2 + 4 * j;
+        const float4 fx = *reinterpret_cast<const float4 *>(src);
+        const float4 fy = *reinterpret_cast<const float4 *>(src + cs);
+        const float4 fz = *reinterpret_cast<const float4 *>(src + 2 * cs);
+        float4 *dst = fl + rr * H + 4 * j;
+        dst[0] = make_float4(fx.x, fy.x, fz.x, 0.f);
+        dst[1] = make_float4(fx.y, fy.y, fz.y, 0.f);
+        dst[2] = make_float4(fx.z, fy.z, fz.z, 0.f);
+        dst[3] = make_float4(fx.w, fy.w, fz.w, 0.f);
     }
-    for (int r = threadIdx.x; r < 3 * ROWS; r += READOUT_T) {
-        const int d = r / ROWS, rr = r % ROWS, a = rr / H, b = rr % H;
-        const float *src = F + d * cs + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs;
-        fl[d * H3 + rr * RS + TILE] = src[(o2 + TILE) & mask];
+    for (int rr = threadIdx.x; rr < ROWS; rr += READOUT_T) {
+        const int a = rr / H, b = rr % H;
+        const float *src = F + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + ((o2 + TILE) & mask);
+        fl[rr * H + TILE] = make_float4(src[0], src[cs], src[2 * cs], 0.f);
     }
     __syncthreads();
     const float nf = (float)n;
@@ -165,14 +176,15 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__r
         for (int a = 0; a < 2; a++)
 #pragma unroll
             for (int b = 0; b < 2; b++) {
-                const int row = ((a0 + a) * H + (a1 + b)) * RS + a2;
+                const int row = ((a0 + a) * H + (a1 + b)) * H + a2;
                 const float wab = w0[a] * w1[b];
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
                     const float w = wab * w2[c];
-                    s0 += w * fl[row + c];
-                    s1 += w * fl[H3 + row + c];
-                    s2 += w * fl[2 * H3 + row + c];
+                    const float4 f = fl[row + c];
+                    s0 += w * f.x;
+                    s1 += w * f.y;
+                    s2 += w * f.z;
                 }
             }
         const float p0 = v0 + kick * s0;

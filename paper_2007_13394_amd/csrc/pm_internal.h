@@ -34,6 +34,24 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Sort keys number the tiles in Morton (Z) order, bits of (t0, t1, t2)
+// interleaved with t2 fastest: a particle that crosses a tile face then
+// usually lands a few tiles away in the sorted arrays.  Tile counts per side
+// are powers of two up to 2^10.
+__device__ __forceinline__ unsigned morton_spread(unsigned v)
+{
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__device__ __forceinline__ int tile_index(int t0, int t1, int t2)
+{
+    return (int)(morton_spread((unsigned)t2) | (morton_spread((unsigned)t1) << 1) |
+                 (morton_spread((unsigned)t0) << 2));
+}
+
 // Device-side guard bits (workspace flag word).
 enum { FLAG_OVERFLOW = 1, FLAG_NAN = 2 };
 
@@ -63,7 +81,7 @@ struct Workspace {
 enum KernelKind {
     K_FILL = 0, K_PAINT, K_R2C, K_COLS_FWD, K_AXIS0, K_COLS_INV, K_C2R, K_READOUT_KD, K_READOUT,
     K_POWER_BIN, K_POWER_REDUCE, K_IC_PARTICLES, K_COPY, K_SORT_COUNT, K_SORT_SCAN, K_SORT_SCATTER,
-    K_X0_FWD, K_X0_GREEN, K_X0_INV, K_COUNT
+    K_X0_FWD, K_X0_GREEN, K_X0_INV, K_R2C_X0, K_C2R_X0, K_COUNT
 };
 
 struct TraceRec {
@@ -145,6 +163,12 @@ hipError_t launch_x0_pass16(int logn, bool inverse, float2 *base, int64_t field_
                             const float2 *tw, hipStream_t s);
 hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, float2 *out2, int64_t plane,
                            int nhp, double coef, const float2 *tw, hipStream_t s);
+// Row transforms fused with pass A (forward: int64 density rows -> twiddled
+// pass-A output; inverse: pass-A inverse -> real rows, in place allowed).
+hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int64_t plane, double scale,
+                         double offset, const float2 *tw, int *flag, hipStream_t s);
+hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int nhp, int64_t plane,
+                         const float2 *tw, hipStream_t s);
 
 // ---- launchers (paint.hip)
 hipError_t launch_paint(const float *x, int64_t stride, int64_t first, int64_t count, int64_t quantum,

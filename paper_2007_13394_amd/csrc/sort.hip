@@ -1,8 +1,8 @@
 // Counting sort of particles by mesh tile, done at the start of every step
 // so that the paint and the readout can work tile by tile out of LDS.
 //
-// Key of a particle = 8 * tile + face flags: tile is the TILE^3-cell block
-// holding floor(u); bit d of the flags is set when floor(u_d) is the last
+// Key of a particle = 8 * tile + face flags: tile is the Morton index of the
+// TILE^3-cell block holding floor(u); bit d of the flags is set when floor(u_d) is the last
 // cell of the tile along axis d (its +1 cloud-in-cell corner then lies in the
 // next tile).  Counting: one atomic per distinct key per wavefront (lanes
 // sharing a key are ranked by ballot), so lattice-ordered CDM, where most of
@@ -24,9 +24,9 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536LL * 16)
 
 __device__ __forceinline__ int tile_key(float u0, float u1, float u2, int n)
 {
-    const int mask = n - 1, nt = n / TILE;
+    const int mask = n - 1;
     const int c0 = (int)floorf(u0) & mask, c1 = (int)floorf(u1) & mask, c2 = (int)floorf(u2) & mask;
-    const int t = ((c0 / TILE) * nt + (c1 / TILE)) * nt + (c2 / TILE);
+    const int t = tile_index(c0 / TILE, c1 / TILE, c2 / TILE);
     const int f = ((c0 % TILE) == TILE - 1 ? 1 : 0) | ((c1 % TILE) == TILE - 1 ? 2 : 0) |
                   ((c2 % TILE) == TILE - 1 ? 4 : 0);
     return t * 8 + f;
