@@ -39,9 +39,9 @@ def model_bytes(P, n):
         "r2c_rows": 8 * M + 8 * Mc,       # int64 density in, half spectrum out
         "cols_fwd": 16 * Mc,
         "axis0": 8 * Mc + 24 * Mc,        # spectrum in, three force spectra out
-        "x0_fwd": 16 * Mc,                # 16-point axis-0 pass, one field
+        "r2c_x0": 8 * M + 8 * Mc,         # int64 density in, half spectrum out (16-point axis-0 pass fused)
         "x0_green": 8 * Mc + 24 * Mc,     # spectrum in, three force spectra out
-        "x0_inv": 48 * Mc,                # inverse 16-point pass, three fields
+        "c2r_x0": 8 * Mc + 4 * M,         # half spectrum in, real force mesh out (16-point pass fused)
         "cols_inv": 16 * Mc,
         "c2r_rows": 8 * Mc + 4 * M,
         "readout_kick_drift": 12 * M + 48 * P,

@@ -460,37 +460,12 @@ __global__ __launch_bounds__(Ax0Cfg<LOGN>::T) void k_axis0(const float2 *src, in
 //   pass B: for every m < 16, an N2-point DFT over the consecutive planes
 //           N2 m + j1, which leaves frequency k0 = m + 16 k in plane N2 m + k
 //           (digit-reversed along axis 0).
-// The force kernel fuses pass B with the gradient of the inverse Laplacian and
-// the inverse of pass B for two fields; the inverse of pass A then restores
+// Pass A rides on the row transforms (k_r2c_x0, k_c2r_x0 below, which hold
+// the 16 rows j2 < 16 of one x1 in LDS).  The force kernel fuses pass B with
+// the gradient of the inverse Laplacian and the inverse of pass B for two
+// fields; the inverse of pass A, inside the complex-to-real rows, restores
 // natural order on all three outputs.  Plane offsets e (0 <= e < N nhp) index
 // (k1, k2) = (e / nhp, e % nhp).
-
-// Pass A (or its inverse) over nf fields: grid (N nhp / 256, N2, nf).
-template <int N, bool INV>
-__global__ __launch_bounds__(256) void k_x0_pass16(float2 *base, int64_t field_stride, int64_t plane,
-                                                   const float2 *__restrict__ tw)
-{
-    constexpr int N2 = N / 16;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int j1 = blockIdx.y;
-    float2 *p = base + (int64_t)blockIdx.z * field_stride + e + (int64_t)j1 * plane;
-    const int64_t pstep = (int64_t)N2 * plane;
-    const float2 *twN = tw + N;
-    float2 v[16];
-#pragma unroll
-    for (int j = 0; j < 16; j++) v[j] = p[j * pstep];
-    if constexpr (!INV) {
-        Dft<16, false>::run(v);
-#pragma unroll
-        for (int m = 1; m < 16; m++) v[m] = cmul(v[m], twN[j1 * m]);
-    } else {
-#pragma unroll
-        for (int m = 1; m < 16; m++) v[m] = cmul(v[m], cconj(twN[j1 * m]));
-        Dft<16, true>::run(v);
-    }
-#pragma unroll
-    for (int j = 0; j < 16; j++) p[j * pstep] = v[j];
-}
 
 // Pass B of the force solve: grid (N nhp / 64, 16), 64 R2 threads with
 // R2 = N2 / 16, each thread one of 64 consecutive plane offsets.  The N2-point
@@ -827,30 +802,6 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
                                out2, o_l, o_o, n_cb, fc, icp, tw);                                  \
     }
     PM_DISPATCH_LOGN(logn, AX0)
-    return hipGetLastError();
-}
-
-hipError_t launch_x0_pass16(int logn, bool inverse, float2 *base, int64_t field_stride, int64_t plane, int nf,
-                            const float2 *tw, hipStream_t s)
-{
-    if (logn < 8 || logn > 11 || plane % 256 || nf < 1) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(plane / 256), (unsigned)(1 << (logn - 4)), (unsigned)nf);
-#define X0A(NN)                                                                                      \
-    {                                                                                                \
-        if (inverse)                                                                                 \
-            hipLaunchKernelGGL((k_x0_pass16<NN, true>), grid, dim3(256), 0, s, base, field_stride,   \
-                               plane, tw);                                                           \
-        else                                                                                         \
-            hipLaunchKernelGGL((k_x0_pass16<NN, false>), grid, dim3(256), 0, s, base, field_stride,  \
-                               plane, tw);                                                           \
-    }
-    switch (logn) {
-    case 8: X0A(256); break;
-    case 9: X0A(512); break;
-    case 10: X0A(1024); break;
-    default: X0A(2048); break;
-    }
-#undef X0A
     return hipGetLastError();
 }
 

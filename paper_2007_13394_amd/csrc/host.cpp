@@ -62,7 +62,7 @@ int ilog2i(int v)
 }
 
 struct Layout {
-    size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags0, tags1, ids, koff, key, rank, cnt, bsum, total;
+    size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags, ids, koff, key, rank, cnt, bsum, total;
     int64_t nkeys;
 };
 
@@ -95,16 +95,14 @@ Layout layout(const pm_config &c)
     off = align256(off + (size_t)(3 * (2 * c.n_fib + 1) + 2 * c.n_shell) * 4);
     L.segtab = off;
     off = align256(off + (size_t)(2 * pm::MAX_SEG + 1) * 8);
-    L.xs = L.ps = L.tags0 = L.tags1 = L.ids = L.koff = L.key = L.rank = L.cnt = L.bsum = 0;
+    L.xs = L.ps = L.tags = L.ids = L.koff = L.key = L.rank = L.cnt = L.bsum = 0;
     if (L.nkeys > 0) {
-        // tile-sorted particle copies and tags survive the whole step
+        // tile-sorted particle records and the tags survive the whole step
         L.xs = off;
-        off = align256(off + (size_t)(12 * P));
+        off = align256(off + (size_t)(16 * P));
         L.ps = off;
-        off = align256(off + (size_t)(12 * P));
-        L.tags0 = off;
-        off = align256(off + (size_t)P);
-        L.tags1 = off;
+        off = align256(off + (size_t)(16 * P));
+        L.tags = off;
         off = align256(off + (size_t)P);
         L.ids = off;
         off = align256(off + (size_t)(4 * P));
@@ -189,8 +187,7 @@ bool sorting_on(const pm_ctx *c) { return c->nkeys > 0 && !(c->cfg.flags & PM_FL
 pm_status paint_atomic(pm_ctx *c, const float *x, int lo, int hi, int64_t *mesh, hipStream_t s)
 {
     if (c->permuted) {
-        LAUNCH(pm::K_PAINT, pm::launch_paint_tagged(x, c->P, c->ws.tags[c->cur_tag], lo, hi, c->ws.quanta, c->n,
-                                                    mesh, s));
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tagged(x, c->P, c->ws.tags, lo, hi, c->ws.quanta, c->n, mesh, s));
     } else {
         for (int g = lo; g < hi; g++)
             LAUNCH(pm::K_PAINT, pm::launch_paint(x, c->P, c->seg_off[g], c->seg_off[g + 1] - c->seg_off[g],
@@ -199,19 +196,20 @@ pm_status paint_atomic(pm_ctx *c, const float *x, int lo, int hi, int64_t *mesh,
     return PM_OK;
 }
 
-// Counting sort of (x, p, tags, ids) by tile key into the workspace copies
-// xs, ps, tags[1 - cur_tag], ids_tmp and the key offsets koff.  p may be NULL.
+// Counting sort of (x, p, tags, ids) by tile key into the workspace records
+// xs (position and tag), ps, ids_tmp and the key offsets koff.  p may be
+// NULL.  The tag array itself keeps the caller's order until a readout
+// writes the particles back in sorted order.
 pm_status tile_sort(pm_ctx *c, const float *x, const float *p, hipStream_t s)
 {
     const int64_t K = c->nkeys;
     LAUNCH(pm::K_FILL, pm::launch_fill_i32(c->ws.cnt, K + 1, s));
     LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, c->ws.cnt, c->ws.key, c->ws.rank, s));
     LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt, c->ws.koff, K + 1, c->ws.bsum, s));
-    const uint8_t *tin = c->permuted ? c->ws.tags[c->cur_tag] : nullptr;
+    const uint8_t *tin = c->permuted ? c->ws.tags : nullptr;
     LAUNCH(pm::K_SORT_SCATTER,
            pm::launch_sort_scatter(x, p, tin, c->P, c->nseg, c->ws.seg_off, c->ws.key, c->ws.rank, c->ws.koff,
-                                   c->ws.xs, p ? c->ws.ps : nullptr, c->ws.tags[1 - c->cur_tag],
-                                   c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
+                                   c->ws.xs, p ? c->ws.ps : nullptr, c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
     return PM_OK;
 }
 
@@ -331,10 +329,9 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
     c->ws.quanta = c->ws.seg_off + (pm::MAX_SEG + 1);
     c->nkeys = L.nkeys;
     if (L.nkeys > 0) {
-        c->ws.xs = reinterpret_cast<float *>(b + L.xs);
-        c->ws.ps = reinterpret_cast<float *>(b + L.ps);
-        c->ws.tags[0] = reinterpret_cast<uint8_t *>(b + L.tags0);
-        c->ws.tags[1] = reinterpret_cast<uint8_t *>(b + L.tags1);
+        c->ws.xs = reinterpret_cast<float4 *>(b + L.xs);
+        c->ws.ps = reinterpret_cast<float4 *>(b + L.ps);
+        c->ws.tags = reinterpret_cast<uint8_t *>(b + L.tags);
         c->ws.ids_tmp = reinterpret_cast<uint32_t *>(b + L.ids);
         c->ws.koff = reinterpret_cast<int *>(b + L.koff);
         c->ws.key = reinterpret_cast<int *>(b + L.key);
@@ -389,7 +386,7 @@ void pm_free(pm_ctx *ctx)
 static const char *kKernelNames[pm::K_COUNT] = {
     "fill",      "paint",        "r2c_rows",     "cols_fwd",   "axis0",      "cols_inv",   "c2r_rows",
     "readout_kick_drift", "readout", "power_bin", "power_reduce", "ic_particles", "copy", "sort_count",
-    "sort_scan", "sort_scatter", "x0_fwd", "x0_green", "x0_inv", "r2c_x0", "c2r_x0"};
+    "sort_scan", "sort_scatter", "x0_green", "r2c_x0", "c2r_x0"};
 
 const char *pm_kernel_name(int32_t kind)
 {
@@ -549,8 +546,8 @@ pm_status pm_paint(pm_ctx *c, const float *x, int32_t seg_lo, int32_t seg_hi, in
         pm_status st = tile_sort(c, x, nullptr, s);
         if (st != PM_OK) return st;
         const int64_t n = c->n;
-        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, c->ws.tags[1 - c->cur_tag], c->P, c->ws.koff,
-                                                   c->ws.quanta, c->nseg, seg_lo, seg_hi, c->n, c->ws.q, s));
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, seg_lo, seg_hi,
+                                                   c->n, c->ws.q, s));
         LAUNCH(pm::K_COPY, pm::launch_add_i64(c->ws.q, mesh_q, n * n * n, s));
         return PM_OK;
     }
@@ -627,15 +624,14 @@ pm_status pm_step(pm_ctx *c, float *x, float *p, double a_force, double a_kick0,
         // the caller's arrays, which then hold the particles in sorted order
         st = tile_sort(c, x, p, s);
         if (st != PM_OK) return st;
-        const uint8_t *tags = c->ws.tags[1 - c->cur_tag];
-        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, tags, c->P, c->ws.koff, c->ws.quanta, c->nseg, 0,
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, 0,
                                                    c->nseg, c->n, c->ws.q, s));
         st = solve(c, c->ws.q, s);
         if (st != PM_OK) return st;
         LAUNCH(pm::K_READOUT_KD,
                pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * n * nhp, c->n,
-                                           (float)kick, (float)drift, x, p, c->ws.ids_tmp, c->ids, c->ws.flag, s));
-        c->cur_tag = 1 - c->cur_tag;
+                                           (float)kick, (float)drift, x, p, c->ws.tags, c->ws.ids_tmp, c->ids,
+                                           c->ws.flag, s));
         c->permuted = true;
         return check_guards(c, s);
     }
@@ -660,7 +656,7 @@ pm_status pm_segment_tags(pm_ctx *c, uint8_t *tags, void *stream)
     if (!c || !tags) return fail(PM_ERR_ARG, "NULL argument to pm_segment_tags");
     hipStream_t s = S(stream);
     if (c->permuted)
-        LAUNCH(pm::K_COPY, hipMemcpyAsync(tags, c->ws.tags[c->cur_tag], (size_t)c->P, hipMemcpyDeviceToDevice, s));
+        LAUNCH(pm::K_COPY, hipMemcpyAsync(tags, c->ws.tags, (size_t)c->P, hipMemcpyDeviceToDevice, s));
     else
         LAUNCH(pm::K_COPY, pm::launch_tags_canonical(tags, c->P, c->nseg, c->ws.seg_off, s));
     return PM_OK;

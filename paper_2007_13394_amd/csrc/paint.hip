@@ -108,8 +108,7 @@ __global__ __launch_bounds__(256) void k_paint_tagged(const float *__restrict__ 
 // that the global loads of a thread are independent of each other.
 constexpr int PAINT_T = 256, NRANGE = 20;
 
-__global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float *__restrict__ xs,
-                                                         const uint8_t *__restrict__ tags, int64_t P,
+__global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restrict__ xs,
                                                          const int *__restrict__ koff,
                                                          const int64_t *__restrict__ quanta, int nseg, int lo,
                                                          int hi, int n, unsigned long long *mesh)
@@ -175,10 +174,11 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float *__restrict
 #pragma unroll
         for (int u = 0; u < 2; u++) {
             if (ok[u]) {
-                u0[u] = xs[idx[u]];
-                u1[u] = xs[P + idx[u]];
-                u2[u] = xs[2 * P + idx[u]];
-                g[u] = tags[idx[u]];
+                const float4 r = xs[idx[u]];   // position and segment tag
+                u0[u] = r.x;
+                u1[u] = r.y;
+                u2[u] = r.z;
+                g[u] = __float_as_int(r.w);
             } else {
                 u0[u] = u1[u] = u2[u] = 0.f;
                 g[u] = -1;
@@ -234,14 +234,13 @@ hipError_t launch_paint_tagged(const float *x, int64_t P, const uint8_t *tags, i
     return hipGetLastError();
 }
 
-hipError_t launch_paint_tiles(const float *xs, const uint8_t *tags, int64_t P, const int *koff,
-                              const int64_t *quanta, int nseg, int seg_lo, int seg_hi, int n, int64_t *mesh,
-                              hipStream_t s)
+hipError_t launch_paint_tiles(const float4 *xs, const int *koff, const int64_t *quanta, int nseg, int seg_lo,
+                              int seg_hi, int n, int64_t *mesh, hipStream_t s)
 {
     const int nt = n / TILE;
     if (nt < 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_paint_tiles, dim3((unsigned)(nt * nt * nt)), dim3(PAINT_T), 0, s, xs, tags, P, koff, quanta,
-                       nseg, seg_lo, seg_hi, n, reinterpret_cast<unsigned long long *>(mesh));
+    hipLaunchKernelGGL(k_paint_tiles, dim3((unsigned)(nt * nt * nt)), dim3(PAINT_T), 0, s, xs, koff, quanta, nseg,
+                       seg_lo, seg_hi, n, reinterpret_cast<unsigned long long *>(mesh));
     return hipGetLastError();
 }
 

@@ -107,18 +107,18 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(float *x, float *p, 
 // +1 halo are staged in LDS, then every particle sorted into the tile is read
 // out from LDS, kicked and drifted; results go to the caller's arrays at the
 // particle's sorted index (with its id, when ids are attached).
-// 512 threads: the 69 KB LDS tile allows two workgroups per CU, so the
+// 512 threads: the 77 KB LDS tile allows two workgroups per CU, so the
 // workgroup itself must carry enough waves to hide memory latency.  The
 // particle range and each thread's first particle are loaded before the LDS
 // fill, and the next particle is loaded before the current one is stored.
 constexpr int READOUT_T = 512;
 
-__global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__restrict__ xs,
-                                                                const float *__restrict__ ps, int64_t P,
+__global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__restrict__ xs,
+                                                                const float4 *__restrict__ ps, int64_t P,
                                                                 const int *__restrict__ koff,
                                                                 const float *__restrict__ F, int64_t rs,
                                                                 int64_t cs, int n, float kick, float drift,
-                                                                float *x, float *p,
+                                                                float *x, float *p, uint8_t *tags,
                                                                 const uint32_t *__restrict__ ids_tmp,
                                                                 uint32_t *ids, int *flag)
 {
@@ -135,14 +135,10 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__r
     const int o0 = t0 * TILE, o1 = t1 * TILE, o2 = t2 * TILE;
     const int beg = koff[t * 8], end = koff[t * 8 + 8];
     int i = beg + threadIdx.x;
-    float u0 = 0.f, u1 = 0.f, u2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
+    float4 ur = make_float4(0.f, 0.f, 0.f, 0.f), vr = ur;
     if (i < end) {
-        u0 = xs[i];
-        u1 = xs[P + i];
-        u2 = xs[2 * P + i];
-        v0 = ps[i];
-        v1 = ps[P + i];
-        v2 = ps[2 * P + i];
+        ur = xs[i];
+        vr = ps[i];
     }
     // (row, quad) tasks: one 16-byte load per component (rows start 64-byte
     // aligned), four cells written; then one task per row for the halo cell
@@ -167,6 +163,8 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__r
     const float nf = (float)n;
     bool bad = false;
     while (i < end) {
+        const float u0 = ur.x, u1 = ur.y, u2 = ur.z;
+        const int tag = __float_as_int(ur.w);
         const float f0 = floorf(u0), f1 = floorf(u1), f2 = floorf(u2);
         const float d0 = u0 - f0, d1 = u1 - f1, d2 = u2 - f2;
         const int a0 = ((int)f0 - o0) & mask, a1 = ((int)f1 - o1) & mask, a2 = ((int)f2 - o2) & mask;
@@ -187,21 +185,17 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__r
                     s2 += w * f.z;
                 }
             }
-        const float p0 = v0 + kick * s0;
-        const float p1 = v1 + kick * s1;
-        const float p2 = v2 + kick * s2;
+        const float p0 = vr.x + kick * s0;
+        const float p1 = vr.y + kick * s1;
+        const float p2 = vr.z + kick * s2;
         const float x0 = wrapf(u0 + drift * p0, nf);
         const float x1 = wrapf(u1 + drift * p1, nf);
         const float x2 = wrapf(u2 + drift * p2, nf);
         bad |= !(isfinite(p0) && isfinite(p1) && isfinite(p2) && isfinite(x0) && isfinite(x1) && isfinite(x2));
         const int inext = i + READOUT_T;
         if (inext < end) {
-            u0 = xs[inext];
-            u1 = xs[P + inext];
-            u2 = xs[2 * P + inext];
-            v0 = ps[inext];
-            v1 = ps[P + inext];
-            v2 = ps[2 * P + inext];
+            ur = xs[inext];
+            vr = ps[inext];
         }
         p[i] = p0;
         p[P + i] = p1;
@@ -209,6 +203,7 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float *__r
         x[i] = x0;
         x[P + i] = x1;
         x[2 * P + i] = x2;
+        tags[i] = (uint8_t)tag;
         if (ids) ids[i] = ids_tmp[i];
         i = inext;
     }
@@ -405,15 +400,16 @@ hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2
     return hipGetLastError();
 }
 
-hipError_t launch_readout_kd_tiles(const float *xs, const float *ps, int64_t P, const int *koff, const float2 *f,
+hipError_t launch_readout_kd_tiles(const float4 *xs, const float4 *ps, int64_t P, const int *koff, const float2 *f,
                                    int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
-                                   float *p, const uint32_t *ids_tmp, uint32_t *ids, int *flag, hipStream_t s)
+                                   float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag,
+                                   hipStream_t s)
 {
     const int nt = n / TILE;
     if (nt < 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_readout_kd_tiles, dim3((unsigned)(nt * nt * nt)), dim3(READOUT_T), 0, s, xs, ps, P, koff,
-                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, x, p, ids_tmp,
-                       ids, flag);
+                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, x, p, tags,
+                       ids_tmp, ids, flag);
     return hipGetLastError();
 }
 

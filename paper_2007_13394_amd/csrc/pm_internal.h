@@ -66,9 +66,9 @@ struct Workspace {
     float *tables = nullptr;     // small per-run tables (IC directions, shells)
     int64_t *seg_off = nullptr;  // device copy of the segment offsets (MAX_SEG + 1)
     int64_t *quanta = nullptr;   // device copy of the segment mass quanta (MAX_SEG)
-    float *xs = nullptr;         // tile-sorted positions [3][P]
-    float *ps = nullptr;         // tile-sorted momenta [3][P]
-    uint8_t *tags[2] = {nullptr, nullptr};  // per-particle segment tags (ping-pong)
+    float4 *xs = nullptr;        // tile-sorted records (u0, u1, u2, segment tag as int bits) [P]
+    float4 *ps = nullptr;        // tile-sorted momenta (p0, p1, p2, 0) [P]
+    uint8_t *tags = nullptr;     // segment tag per particle in the caller's current order [P]
     uint32_t *ids_tmp = nullptr; // tile-sorted ids [P]
     int *key = nullptr;          // sort key per particle (aliases the F region)
     int *rank = nullptr;         // rank within key
@@ -81,7 +81,7 @@ struct Workspace {
 enum KernelKind {
     K_FILL = 0, K_PAINT, K_R2C, K_COLS_FWD, K_AXIS0, K_COLS_INV, K_C2R, K_READOUT_KD, K_READOUT,
     K_POWER_BIN, K_POWER_REDUCE, K_IC_PARTICLES, K_COPY, K_SORT_COUNT, K_SORT_SCAN, K_SORT_SCATTER,
-    K_X0_FWD, K_X0_GREEN, K_X0_INV, K_R2C_X0, K_C2R_X0, K_COUNT
+    K_X0_GREEN, K_R2C_X0, K_C2R_X0, K_COUNT
 };
 
 struct TraceRec {
@@ -108,9 +108,8 @@ struct Ctx {
     Workspace ws;
     std::vector<float2> tw_host;
     // particle order: canonical (segments at seg_off) or permuted by the last
-    // tile sort (segment of particle i = tags[cur_tag][i])
+    // tile-sorted step (segment of particle i = tags[i])
     bool permuted = false;
-    int cur_tag = 0;
     int64_t nkeys = 0;            // 8 x tiles when tile sorting is available, else 0
     std::vector<int64_t> segtab_host;
     uint32_t *ids = nullptr;      // caller's id array, permuted along with the particles
@@ -159,8 +158,6 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
 // nf fields field_stride apart, and pass B fused with the gradient of the
 // inverse Laplacian (src may alias out0; outputs digit-reversed until the
 // inverse of pass A).
-hipError_t launch_x0_pass16(int logn, bool inverse, float2 *base, int64_t field_stride, int64_t plane, int nf,
-                            const float2 *tw, hipStream_t s);
 hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, float2 *out2, int64_t plane,
                            int nhp, double coef, const float2 *tw, hipStream_t s);
 // Row transforms fused with pass A (forward: int64 density rows -> twiddled
@@ -175,17 +172,15 @@ hipError_t launch_paint(const float *x, int64_t stride, int64_t first, int64_t c
                         int n, int64_t *mesh, hipStream_t s);
 hipError_t launch_paint_tagged(const float *x, int64_t P, const uint8_t *tags, int seg_lo, int seg_hi,
                                const int64_t *quanta, int n, int64_t *mesh, hipStream_t s);
-hipError_t launch_paint_tiles(const float *xs, const uint8_t *tags, int64_t P, const int *koff,
-                              const int64_t *quanta, int nseg, int seg_lo, int seg_hi, int n, int64_t *mesh,
-                              hipStream_t s);
+hipError_t launch_paint_tiles(const float4 *xs, const int *koff, const int64_t *quanta, int nseg, int seg_lo,
+                              int seg_hi, int n, int64_t *mesh, hipStream_t s);
 
 // ---- launchers (sort.hip)
 hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, int *key, int *rank, hipStream_t s);
 hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipStream_t s);
 hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
-                               const int64_t *seg_off, const int *key, const int *rank, const int *off, float *xs,
-                               float *ps, uint8_t *tag_out, const uint32_t *ids_in, uint32_t *ids_out,
-                               hipStream_t s);
+                               const int64_t *seg_off, const int *key, const int *rank, const int *off, float4 *xs,
+                               float4 *ps, const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s);
 
 // ---- launchers (particles.hip)
 hipError_t launch_fill_i64(int64_t *p, int64_t count, hipStream_t s);
@@ -194,9 +189,10 @@ hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs
 hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f,
                                      int64_t comp_stride, int n, float kick, float drift, int *flag,
                                      hipStream_t s);
-hipError_t launch_readout_kd_tiles(const float *xs, const float *ps, int64_t P, const int *koff, const float2 *f,
+hipError_t launch_readout_kd_tiles(const float4 *xs, const float4 *ps, int64_t P, const int *koff, const float2 *f,
                                    int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
-                                   float *p, const uint32_t *ids_tmp, uint32_t *ids, int *flag, hipStream_t s);
+                                   float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag,
+                                   hipStream_t s);
 hipError_t launch_fill_i32(int *p, int64_t count, hipStream_t s);
 hipError_t launch_add_i64(const int64_t *src, int64_t *dst, int64_t count, hipStream_t s);
 hipError_t launch_tags_canonical(uint8_t *tags, int64_t P, int nseg, const int64_t *seg_off, hipStream_t s);

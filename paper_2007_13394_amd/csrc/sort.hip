@@ -7,8 +7,9 @@
 // next tile).  Counting: one atomic per distinct key per wavefront (lanes
 // sharing a key are ranked by ballot), so lattice-ordered CDM, where most of
 // a wavefront falls in one tile, costs few atomics.  Offsets come from an
-// exclusive scan of the counts; the scatter writes position, momentum,
-// segment tag and optional id of particle i to offset[key_i] + rank_i.
+// exclusive scan of the counts; the scatter writes the position record (with
+// the segment tag), the momentum and the optional id of particle i to
+// offset[key_i] + rank_i.
 #include "pm_internal.h"
 
 namespace pm {
@@ -146,32 +147,28 @@ __global__ void k_scan_add(int *out, int64_t n, const int *sums)
         out[i] += sums[i / SCAN_B];
 }
 
+// Scatter into float4 records: one 16-byte store for the position and the
+// segment tag, one for the momentum, so a particle that moves far in the
+// order costs two stores instead of seven partial ones.
 __global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict__ x, const float *__restrict__ p,
-                                                      const uint8_t *__restrict__ tag_in, int64_t P, int nseg,
-                                                      const int64_t *__restrict__ seg_off, const int *key,
-                                                      const int *rank, const int *off, float *xs, float *ps,
-                                                      uint8_t *tag_out, const uint32_t *ids_in, uint32_t *ids_out)
+                                                         const uint8_t *__restrict__ tag_in, int64_t P, int nseg,
+                                                         const int64_t *__restrict__ seg_off, const int *key,
+                                                         const int *rank, const int *off, float4 *xs, float4 *ps,
+                                                         const uint32_t *ids_in, uint32_t *ids_out)
 {
     const int64_t c0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * SORT_CH;
     const int64_t c1 = c0 + SORT_CH < P ? c0 + SORT_CH : P;
     for (int64_t i = c0 + threadIdx.x; i < c1; i += SORT_T) {
         const int64_t d = (int64_t)off[key[i]] + rank[i];
-        xs[d] = x[i];
-        xs[P + d] = x[P + i];
-        xs[2 * P + d] = x[2 * P + i];
-        if (p) {
-            ps[d] = p[i];
-            ps[P + d] = p[P + i];
-            ps[2 * P + d] = p[2 * P + i];
-        }
-        uint8_t t;
+        int t;
         if (tag_in) {
             t = tag_in[i];
         } else {   // canonical order: segment from the offsets
             t = 0;
             for (int g = 1; g < nseg; g++) t += (i >= seg_off[g]) ? 1 : 0;
         }
-        tag_out[d] = t;
+        xs[d] = make_float4(x[i], x[P + i], x[2 * P + i], __int_as_float(t));
+        if (p) ps[d] = make_float4(p[i], p[P + i], p[2 * P + i], 0.f);
         if (ids_in) ids_out[d] = ids_in[i];
     }
 }
@@ -197,13 +194,13 @@ hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipS
 }
 
 hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
-                               const int64_t *seg_off, const int *key, const int *rank, const int *off, float *xs,
-                               float *ps, uint8_t *tag_out, const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s)
+                               const int64_t *seg_off, const int *key, const int *rank, const int *off, float4 *xs,
+                               float4 *ps, const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s)
 {
     const int64_t nb = (P + SORT_CH - 1) / SORT_CH;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SORT_T), 0, s, x, p, tag_in, P, nseg, seg_off, key,
-                       rank, off, xs, ps, tag_out, ids_in, ids_out);
+                       rank, off, xs, ps, ids_in, ids_out);
     return hipGetLastError();
 }
 
