@@ -25,9 +25,49 @@ import time
 METRIC = "particle-steps/s at 1024^3 CDM; learned vs plain PM at equal 1% P(k) error"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# on this workload, each scaled by what the counter reads for a plain device
+# copy of known size (profiles/ has the summaries and the commands).  A figure
+# is reported only while the kernel's source file still has the hash it had
+# when the counters were taken.
+MEASURED_TRAFFIC = {
+    # profiles/c3_step_hbm_counters.md
+    "c2r_x0": {"bytes_per_launch": 69484220363, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "252159e40514f3c1"},
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel):
+    """Calibrated HBM bytes per launch of `kernel`, or None when no counter
+    figure exists or its source changed since the counters were taken."""
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if rec is None:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), rec["source"])
+    with open(path, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_16"]:
+            return None
+    return rec["bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain device-to-device copy of exactly 1 GiB (reads 1 GiB, writes
+    1 GiB): the reference against which FETCH_SIZE and WRITE_SIZE are scaled
+    when this command runs under rocprofv3 --pmc."""
+    import torch
+    a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
 
 
 def model_bytes(P, n):
@@ -100,6 +140,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU slab "
@@ -113,6 +155,9 @@ def main():
     from paper_2007_13394_amd import pm
     from paper_2007_13394_amd import run as R
 
+    if args.copy_calibration:
+        copy_calibration()
+        log("[bench] copy calibration: 1 GiB device-to-device copy done")
     cfg = I.config(args.config)
     n = cfg["n_mesh"]
     log(f"[bench] config {args.config}: mesh {n}^3, CDM {cfg['n_cdm']}^3, sites {cfg['n_sites']}^3")
@@ -191,7 +236,8 @@ def main():
                                f"{cfg['n_log']} log + {cfg['n_lin']} linear steps from z=99, int64 fixed-point paint",
                    "particles": P, "mesh": n},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom) if args.config == "C3" else None},
         "step_roofline": {"model_bytes_per_step": step_bytes,
                           "frac": round(step_bytes / (HBM_PEAK_GBS * 1e9) / (ms_per_step * 1e-3), 4)},
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
