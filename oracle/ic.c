@@ -136,38 +136,45 @@ static double wrap(double u, double n)
 
 static long sgn_mode(long k, long n) { return k <= n / 2 ? k : k - n; }
 
-/* Displacement (Mpc/h) of one component from the white-noise spectrum W.
- * kind 0: CDM at lattice points; kind 1: neutrinos, free-streaming suppressed
- * and evaluated half a cell off the lattice. */
+/* Multiplier of mode t (full n^3 spectrum) that turns the white-noise spectrum
+ * into displacement component d (Mpc/h): i k_d / k^2 sqrt(A P(k) / V_cell),
+ * zero at k = 0 and on every Nyquist plane.  kind 0: CDM at lattice points;
+ * kind 1: neutrinos, free-streaming suppressed and evaluated half a cell off
+ * the lattice (phase exp(i k.h)). */
+static cplx ic_mult(const orc_sim *s, long t, long n, int d, int kind, double amp, double kfs)
+{
+    double L = s->box, vcell = pow(L / n, 3);
+    long k[3] = {sgn_mode(t / (n * n), n), sgn_mode((t / n) % n, n), sgn_mode(t % n, n)};
+    for (int e = 0; e < 3; e++) if (labs(k[e]) == n / 2) return 0;
+    double kv[3], k2 = 0;
+    for (int e = 0; e < 3; e++) { kv[e] = 2.0 * M_PI * k[e] / L; k2 += kv[e] * kv[e]; }
+    if (k2 == 0) return 0;
+    double kk = sqrt(k2);
+    cplx mult = sqrt(amp * orc_pk_unnorm(s, kk) / vcell);
+    if (kind == 1) {
+        double r = kk / kfs;
+        mult /= (1.0 + r * r);
+        double ph = 0.5 * (L / n) * (kv[0] + kv[1] + kv[2]);
+        mult *= cos(ph) + I * sin(ph);
+    }
+    return I * kv[d] / k2 * mult;
+}
+
+/* Displacement (Mpc/h) of one component from the white-noise spectrum W:
+ * inverse transform of the multiplied spectrum, normalised by 1/n^3. */
 static void displacement(const orc_sim *s, const cplx *W, long n, int d, int kind, double amp,
                          double kfs, cplx *out)
 {
-    double L = s->box, vcell = pow(L / n, 3);
     long m = n * n * n;
-    for (long t = 0; t < m; t++) {
-        long k[3] = {sgn_mode(t / (n * n), n), sgn_mode((t / n) % n, n), sgn_mode(t % n, n)};
-        int nyq = 0;
-        for (int e = 0; e < 3; e++) if (labs(k[e]) == n / 2) nyq = 1;
-        double kv[3], k2 = 0;
-        for (int e = 0; e < 3; e++) { kv[e] = 2.0 * M_PI * k[e] / L; k2 += kv[e] * kv[e]; }
-        if (nyq || k2 == 0) { out[t] = 0; continue; }
-        double kk = sqrt(k2);
-        cplx delta = W[t] * sqrt(amp * orc_pk_unnorm(s, kk) / vcell);
-        if (kind == 1) {
-            double r = kk / kfs;
-            delta /= (1.0 + r * r);
-            double ph = 0.5 * (L / n) * (kv[0] + kv[1] + kv[2]);
-            delta *= cos(ph) + I * sin(ph);
-        }
-        out[t] = I * kv[d] / k2 * delta;
-    }
+    for (long t = 0; t < m; t++) out[t] = ic_mult(s, t, n, d, kind, amp, kfs) * W[t];
     orc_fft3d((double *)out, n, +1);
     for (long t = 0; t < m; t++) out[t] /= (double)m;
 }
 
 /* x, p: [3][P] in mesh units.  disp_cdm [3][N_c], disp_nu [3][N_sites] (mesh
  * units) are optional outputs of the displacement fields used. */
-int orc_ic(const orc_sim *s, const float *white, double *x, double *p, double *disp_cdm, double *disp_nu)
+static int ic_impl(const orc_sim *s, const float *white32, const double *white64, double *x, double *p,
+                   double *disp_cdm, double *disp_nu)
 {
     long n = s->n_cdm, m = n * n * n, nc, nn;
     long P = orc_num_particles(s, &nc, &nn);
@@ -180,7 +187,7 @@ int orc_ic(const orc_sim *s, const float *white, double *x, double *p, double *d
     double dc = (double)s->n_mesh / n;
 
     cplx *W = malloc(sizeof(cplx) * m), *S = malloc(sizeof(cplx) * m);
-    for (long t = 0; t < m; t++) W[t] = white[t];
+    for (long t = 0; t < m; t++) W[t] = white32 ? (double)white32[t] : white64[t];
     orc_fft3d((double *)W, n, -1);
 
     for (int d = 0; d < 3; d++) {
@@ -242,3 +249,70 @@ int orc_ic(const orc_sim *s, const float *white, double *x, double *p, double *d
     free(S);
     return 0;
 }
+
+int orc_ic(const orc_sim *s, const float *white, double *x, double *p, double *disp_cdm, double *disp_nu)
+{
+    return ic_impl(s, white, NULL, x, p, disp_cdm, disp_nu);
+}
+
+/* The same initial conditions from FP64 white noise (for derivative checks). */
+int orc_ic_w64(const orc_sim *s, const double *white, double *x, double *p)
+{
+    return ic_impl(s, NULL, white, x, p, NULL, NULL);
+}
+
+/* Vector-Jacobian product of the initial conditions with respect to the white
+ * noise: wbar = (d(x, p)/dw)^T (xbar, pbar).  Positions and momenta are linear
+ * in the displacement fields (x = q + s, p = (G/D) s; a neutrino site's 70
+ * particles share its displacement), and each field is A w with
+ * A = F^-1 diag(M) F for the unnormalised forward transform F; its transpose is
+ * F^-1 diag(conj M) F, the same transforms with the multiplier conjugated. */
+int orc_ic_vjp(const orc_sim *s, const double *xbar, const double *pbar, double *wbar)
+{
+    long n = s->n_cdm, m = n * n * n, nc, nn;
+    long P = orc_num_particles(s, &nc, &nn);
+    const orc_cosmo *c = &s->cosmo;
+    double a2[2] = {s->a0, 1.0}, D[2], G[2];
+    if (orc_growth(c, 2, a2, D, G, 1e-3)) return -1;
+    double amp = orc_pk_amplitude(s) * pow(D[0] / D[1], 2);
+    double vfac = G[0] / D[0];
+    double to_mesh = s->n_mesh / s->box;
+    cplx *acc = calloc(m, sizeof(cplx)), *F = malloc(sizeof(cplx) * m);
+    for (int d = 0; d < 3; d++) {
+        for (long t = 0; t < m; t++) F[t] = (xbar[d * P + t] + vfac * pbar[d * P + t]) * to_mesh;
+        orc_fft3d((double *)F, n, -1);
+        for (long t = 0; t < m; t++) acc[t] += conj(ic_mult(s, t, n, d, 0, amp, 0.0)) * F[t];
+    }
+    if (nn > 0) {
+        long ns = s->n_sites, nsites = ns * ns * ns, R = n / ns;
+        int nd = 2 * s->n_fib + 1;
+        long per = nsites * nd;
+        double m1 = 0;
+        for (int j = 0; j < c->n_nu; j++) if (c->m_nu[j] > m1) m1 = c->m_nu[j];
+        double a0 = s->a0;
+        double kfs = 0.82 * sqrt(c->omega_L + c->omega_m / (a0 * a0 * a0)) * a0 * a0 * m1;
+        for (int d = 0; d < 3; d++) {
+            for (long t = 0; t < m; t++) F[t] = 0;
+            for (long j = 0; j < nsites; j++) {
+                long jj[3] = {j / (ns * ns), (j / ns) % ns, j % ns};
+                double sum = 0;
+                for (int sh = 0; sh < s->n_shell; sh++)
+                    for (int t = 0; t < nd; t++) {
+                        long idx = nc + sh * per + j * nd + t;
+                        sum += xbar[d * P + idx] + vfac * pbar[d * P + idx];
+                    }
+                long g[3];
+                for (int e = 0; e < 3; e++) g[e] = jj[e] * R + R / 2;
+                F[(g[0] * n + g[1]) * n + g[2]] = sum * to_mesh;
+            }
+            orc_fft3d((double *)F, n, -1);
+            for (long t = 0; t < m; t++) acc[t] += conj(ic_mult(s, t, n, d, 1, amp, kfs)) * F[t];
+        }
+    }
+    orc_fft3d((double *)acc, n, +1);
+    for (long t = 0; t < m; t++) wbar[t] = creal(acc[t]) / (double)m;
+    free(acc);
+    free(F);
+    return 0;
+}
+

@@ -15,6 +15,11 @@
  *   inverse DFT  x_j = sum_k X_k exp(+2 pi i j k / N), no scaling (callers
  *   divide by N^3 where a normalised inverse is meant).
  *   complex arrays are interleaved (re, im) doubles.
+ *
+ * Pins: tests/test_oracle_*.py check every function against closed forms,
+ * the paper's printed values, independent quadrature or brute force, and the
+ * reverse mode (adj.c, orc_ic_vjp) against central finite differences of the
+ * forward model.
  */
 #ifndef ORC_H
 #define ORC_H
@@ -90,6 +95,8 @@ double orc_pk_unnorm(const orc_sim *s, double k);
 double orc_sigma_R(const orc_sim *s, double amp, double R);
 double orc_pk_amplitude(const orc_sim *s);
 int    orc_ic(const orc_sim *s, const float *white, double *x, double *p, double *disp_cdm, double *disp_nu);
+int    orc_ic_w64(const orc_sim *s, const double *white, double *x, double *p);
+int    orc_ic_vjp(const orc_sim *s, const double *xbar, const double *pbar, double *wbar);
 
 /* ---------------- PM force and step (pm.c) ---------------- */
 void orc_paint_q(const double *x, long P, long off, long cnt, int64_t Qm, int n, int64_t *mesh);
@@ -99,6 +106,14 @@ void orc_force_mesh_from_delta(const double *delta, int n, double omega_m, doubl
 void orc_readout(const double *F, int n, const double *x, long P, double *acc);
 int  orc_force(const orc_sim *s, const double *x, double *acc);
 int  orc_step(const orc_sim *s, double *x, double *p, double kick, double drift, double *acc_out);
+
+/* ---------------- reverse mode (adj.c; ic.c for orc_ic_vjp) ---------------- */
+int  orc_density_cont(const orc_sim *s, const double *x, double *delta);
+int  orc_force_cont(const orc_sim *s, const double *x, double *acc);
+int  orc_step_cont(const orc_sim *s, double *x, double *p, double kick, double drift);
+int  orc_force_vjp(const orc_sim *s, const double *x, const double *g, double *xbar);
+int  orc_step_vjp(const orc_sim *s, const double *x, double kick, double drift, double *xbar, double *pbar);
+int  orc_density_vjp(const orc_sim *s, const double *x, const double *dmesh, double *xbar);
 
 /* ---------------- power spectrum (power.c) ---------------- */
 void orc_power(const double *da, const double *db, int n, double box, int nbins, int compensate,

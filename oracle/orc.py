@@ -13,7 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liborc.so")
-_SRC = ["fft.c", "cosmo.c", "nu.c", "ic.c", "pm.c", "power.c"]
+_SRC = ["fft.c", "cosmo.c", "nu.c", "ic.c", "pm.c", "power.c", "adj.c"]
 
 
 def build():
@@ -89,6 +89,14 @@ _sig("orc_readout", None, [_dp, C.c_int, _dp, C.c_long, _dp])
 _sig("orc_force", C.c_int, [C.POINTER(Sim), _dp, _dp])
 _sig("orc_step", C.c_int, [C.POINTER(Sim), _dp, _dp, C.c_double, C.c_double, C.c_void_p])
 _sig("orc_power", None, [_dp, _dp, C.c_int, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp])
+_sig("orc_ic_w64", C.c_int, [C.POINTER(Sim), _dp, _dp, _dp])
+_sig("orc_ic_vjp", C.c_int, [C.POINTER(Sim), _dp, _dp, _dp])
+_sig("orc_density_cont", C.c_int, [C.POINTER(Sim), _dp, _dp])
+_sig("orc_force_cont", C.c_int, [C.POINTER(Sim), _dp, _dp])
+_sig("orc_step_cont", C.c_int, [C.POINTER(Sim), _dp, _dp, C.c_double, C.c_double])
+_sig("orc_force_vjp", C.c_int, [C.POINTER(Sim), _dp, _dp, _dp])
+_sig("orc_step_vjp", C.c_int, [C.POINTER(Sim), _dp, C.c_double, C.c_double, _dp, _dp])
+_sig("orc_density_vjp", C.c_int, [C.POINTER(Sim), _dp, _dp, _dp])
 
 
 # ---------------------------------------------------------------- FFT
@@ -397,3 +405,74 @@ def run(sim, x, p, a, half, callback=None):
         if callback:
             callback(i, c, x, p)
     return x, p
+
+
+# ---------------------------------------------------------------- reverse mode
+# The differentiable model paints exact segment masses (the fixed-point paint
+# agrees with it to 2^-S per cell); see adj.c.
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def ic_w64(sim, white):
+    """Initial conditions from FP64 white noise (same arithmetic as ic)."""
+    P, _, _ = num_particles(sim)
+    x, p = np.empty(3 * P), np.empty(3 * P)
+    if _lib.orc_ic_w64(C.byref(sim), _c64(white).reshape(-1), x, p) != 0:
+        raise ValueError("ic failed")
+    return x.reshape(3, P), p.reshape(3, P)
+
+
+def ic_vjp(sim, xbar, pbar):
+    """(d(x0, p0)/dw)^T (xbar, pbar) as an n_cdm^3 array."""
+    n = sim.n_cdm
+    wbar = np.empty(n ** 3)
+    if _lib.orc_ic_vjp(C.byref(sim), _c64(xbar).reshape(-1), _c64(pbar).reshape(-1), wbar) != 0:
+        raise ValueError("ic_vjp failed")
+    return wbar.reshape(n, n, n)
+
+
+def density_cont(sim, x):
+    n = sim.n_mesh
+    d = np.empty(n ** 3)
+    if _lib.orc_density_cont(C.byref(sim), _c64(x).reshape(-1), d) != 0:
+        raise ValueError("density failed")
+    return d.reshape(n, n, n)
+
+
+def force_cont(sim, x):
+    x = _c64(x)
+    acc = np.empty_like(x)
+    if _lib.orc_force_cont(C.byref(sim), x.reshape(-1), acc.reshape(-1)) != 0:
+        raise ValueError("force failed")
+    return acc
+
+
+def step_cont(sim, x, p, kick, drift):
+    """In place, the differentiable model's step."""
+    assert x.dtype == np.float64 and p.dtype == np.float64 and x.flags.c_contiguous and p.flags.c_contiguous
+    if _lib.orc_step_cont(C.byref(sim), x.reshape(-1), p.reshape(-1), kick, drift) != 0:
+        raise ValueError("step failed")
+
+
+def force_vjp(sim, x, g):
+    xbar = np.zeros(np.shape(x))
+    if _lib.orc_force_vjp(C.byref(sim), _c64(x).reshape(-1), _c64(g).reshape(-1), xbar.reshape(-1)) != 0:
+        raise ValueError("force_vjp failed")
+    return xbar
+
+
+def step_vjp(sim, x, kick, drift, xbar, pbar):
+    """Cotangents of (x', p') -> cotangents of (x, p) for the step taken at x."""
+    xb, pb = _c64(xbar).copy(), _c64(pbar).copy()
+    if _lib.orc_step_vjp(C.byref(sim), _c64(x).reshape(-1), kick, drift, xb.reshape(-1), pb.reshape(-1)) != 0:
+        raise ValueError("step_vjp failed")
+    return xb, pb
+
+
+def density_vjp(sim, x, dmesh):
+    xbar = np.zeros(np.shape(x))
+    if _lib.orc_density_vjp(C.byref(sim), _c64(x).reshape(-1), _c64(dmesh).reshape(-1), xbar.reshape(-1)) != 0:
+        raise ValueError("density_vjp failed")
+    return xbar
+
