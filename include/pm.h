@@ -238,6 +238,47 @@ pm_status pm_trace_end(pm_ctx *ctx, int32_t max, int32_t *kind, float *ms, int32
 /* Name of a kernel kind reported by pm_trace_end ("paint", "axis0", ...). */
 const char *pm_kernel_name(int32_t kind);
 
+/* ---- Reverse mode (reconstruction of the initial modes, the application the
+ * paper's introduction and conclusions point to).  The differentiated model is
+ * the step above with every particle depositing its exact segment mass with
+ * cloud-in-cell weights (the fixed-point mesh agrees with it to 2^-shift per
+ * cell; the rounding has zero derivative).  The derivative of a weight at a
+ * cell face is the right derivative.  All arrays are device float32, SoA
+ * [3][P] for particle quantities, in the context's particle order; cotangent
+ * outputs are accumulated (+=) unless stated.  The reverse mode needs the
+ * particles to keep their order between the forward steps and the reverse
+ * pass: configure with PM_FLAG_NO_SORT (pm_step_vjp returns PM_ERR_STATE
+ * otherwise). */
+
+/* delta = sum_j m_j W(x_j, c) - 1 (the painted density contrast, from the
+ * fixed-point mesh) into a dense float32 [N]^3 mesh. */
+pm_status pm_density(pm_ctx *ctx, const float *x, float *delta, void *stream);
+
+/* xbar_j += m_j sum_c dmesh(c) dW(x_j, c)/dx_j: the transpose of pm_density
+ * for a cotangent mesh dmesh (dense float32 [N]^3). */
+pm_status pm_density_vjp(pm_ctx *ctx, const float *x, const float *dmesh, float *xbar, void *stream);
+
+/* xbar += (d acc / d x)^T g, acc the force of pm_force at x and g [3][P] its
+ * cotangent: the readout-derivative term plus the paint-derivative term
+ * through the transpose of the gradient of the inverse Laplacian (which is
+ * minus itself).  Uses the workspace mesh regions. */
+pm_status pm_force_vjp(pm_ctx *ctx, const float *x, const float *g, float *xbar, void *stream);
+
+/* Reverse mode of pm_step taken at positions x (the checkpoint: positions
+ * before the step) with the same four scale factors.  On entry xbar, pbar
+ * hold the cotangents of the positions and momenta after the step; on exit,
+ * those of the positions and momenta before it (updated in place):
+ * pbar += drift xbar, then xbar += kick (dF/dx)^T pbar. */
+pm_status pm_step_vjp(pm_ctx *ctx, const float *x, double a_force, double a_kick0, double a_kick1,
+                      double a_drift1, float *xbar, float *pbar, void *stream);
+
+/* Transpose of pm_ic with respect to the white noise: wbar (float32
+ * [n_cdm]^3, overwritten) = (d(x, p)/d white)^T (xbar, pbar).  The initial
+ * conditions are linear in the white noise: each displacement field is
+ * F^-1 diag(M) F white, whose transpose is F^-1 diag(conj M) F.  Cotangents in
+ * canonical order (PM_ERR_STATE after a sorted step). */
+pm_status pm_ic_vjp(pm_ctx *ctx, const float *xbar, const float *pbar, float *wbar, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

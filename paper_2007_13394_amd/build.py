@@ -25,6 +25,7 @@ SOURCES = {
     "paint.hip": ["-ffp-contract=off"],
     "particles.hip": [],
     "sort.hip": [],
+    "adjoint.hip": [],
     "host_cosmo.cpp": ["-ffp-contract=off", "-x", "hip"],
     "host.cpp": ["-x", "hip"],
 }

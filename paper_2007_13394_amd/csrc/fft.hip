@@ -345,6 +345,26 @@ __device__ __forceinline__ float2 mult_ic(float2 v, int d, int l, int o, int k2,
     return make_float2((float)re, (float)im);
 }
 
+// Transpose of the initial-condition transfer: acc (+)= sum_d conj(M_d) G_d
+// over three natural-order half spectra G_d (row stride nhp, field stride
+// fs); conj(M) v = conj(M conj(v)).
+__global__ void k_ic_adj_mult(const float2 *G, int64_t nhp, int64_t fs, int n, IcParams icp, float2 *acc,
+                              int accumulate)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int k2 = (int)(t % nhp);
+        const int64_t r = t / nhp;
+        const int i1 = (int)(r % n), i0 = (int)(r / n);
+        float2 s = accumulate ? acc[t] : make_float2(0.f, 0.f);
+        for (int d = 0; d < 3; d++) {
+            const float2 m = mult_ic(cconj(G[d * fs + t]), d, i0, i1, k2, n, icp);
+            s = cadd(s, cconj(m));
+        }
+        acc[t] = s;
+    }
+}
+
 template <int LOGN, int MODE, int NOUT>
 __global__ __launch_bounds__(Ax0Cfg<LOGN>::T) void k_axis0(const float2 *src, int64_t s_l, int64_t s_o,
                                                            float2 *out0, float2 *out1, float2 *out2,
@@ -855,6 +875,16 @@ hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_st
     default: C2RX(11); break;
     }
 #undef C2RX
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_adj_mult(const float2 *G, int64_t nhp, int64_t fs, int n, const IcParams *ic, float2 *acc,
+                              bool accumulate, hipStream_t s)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    int64_t b = (tot + 255) / 256;
+    if (b > 65536 * 16) b = 65536 * 16;
+    hipLaunchKernelGGL(k_ic_adj_mult, dim3((unsigned)b), dim3(256), 0, s, G, nhp, fs, n, *ic, acc, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -279,6 +279,41 @@ pm_status forward_density(pm_ctx *c, int64_t *q, double scale, hipStream_t s)
     return PM_OK;
 }
 
+// xbar += gscale (d acc / d x)^T g for the differentiable model (exact
+// segment masses, cloud-in-cell weights): the readout-derivative term from the
+// force meshes at x, then the cotangents painted with the readout weights,
+// the transpose of the gradient of the inverse Laplacian (minus itself) and
+// the paint-derivative term.  Natural-order transforms on the F region.
+pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, float *xbar, hipStream_t s)
+{
+    const int n = c->n, lg = c->logn;
+    const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n, cs = n2 * nhp;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    float2 *F = c->ws.f;
+    float *Fr = reinterpret_cast<float *>(F);
+    pm_status st = paint_all(c, x, s);
+    if (st == PM_OK) st = solve(c, c->ws.q, s);
+    if (st != PM_OK) return st;
+    LAUNCH(pm::K_ADJOINT, pm::launch_readout_grad3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, xbar, s));
+    LAUNCH(pm::K_FILL, pm::launch_fill_i64(reinterpret_cast<int64_t *>(F), 3 * cs, s));
+    LAUNCH(pm::K_ADJOINT, pm::launch_paint_vec3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, s));
+    for (int d = 0; d < 3; d++) {
+        float2 *Fd = F + d * cs;
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, reinterpret_cast<float *>(Fd), 2 * nhp, Fd, nhp, n2, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    }
+    const double coef = 1.5 * c->cfg.omega_m / ((double)n2 * n);
+    LAUNCH(pm::K_ADJOINT, pm::launch_green_adj(F, nhp, cs, n, coef, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F, nhp, Fr, 2 * nhp, n2, c->ws.tw, s));
+    LAUNCH(pm::K_ADJOINT, pm::launch_density_grad(x, c->P, Fr, 2 * nhp, n, c->nseg, c->ws.seg_off,
+                                                  c->permuted ? c->ws.tags : nullptr, c->ws.quanta,
+                                                  (float)ldexp(1.0, -c->cfg.shift), 1.0f, xbar, s));
+    return PM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -386,7 +421,7 @@ void pm_free(pm_ctx *ctx)
 static const char *kKernelNames[pm::K_COUNT] = {
     "fill",      "paint",        "r2c_rows",     "cols_fwd",   "axis0",      "cols_inv",   "c2r_rows",
     "readout_kick_drift", "readout", "power_bin", "power_reduce", "ic_particles", "copy", "sort_count",
-    "sort_scan", "sort_scatter", "x0_green", "r2c_x0", "c2r_x0"};
+    "sort_scan", "sort_scatter", "x0_green", "r2c_x0", "c2r_x0", "adjoint"};
 
 const char *pm_kernel_name(int32_t kind)
 {
@@ -712,6 +747,102 @@ pm_status pm_power(pm_ctx *c, const float *x, int32_t a_lo, int32_t a_hi, int32_
         k_mean[b] = w > 0 ? h[3 * b + 1] / w : 0.0;
     }
     return check_guards(c, s);
+}
+
+// ---- reverse mode
+
+pm_status pm_density(pm_ctx *c, const float *x, float *delta, void *stream)
+{
+    if (!c || !x || !delta) return fail(PM_ERR_ARG, "NULL argument to pm_density");
+    hipStream_t s = S(stream);
+    pm_status st = paint_all(c, x, s);
+    if (st != PM_OK) return st;
+    const int64_t n = c->n;
+    LAUNCH(pm::K_COPY, pm::launch_q_to_delta(c->ws.q, n * n * n, ldexp(1.0, -c->cfg.shift), delta, s));
+    return check_guards(c, s);
+}
+
+pm_status pm_density_vjp(pm_ctx *c, const float *x, const float *dmesh, float *xbar, void *stream)
+{
+    if (!c || !x || !dmesh || !xbar) return fail(PM_ERR_ARG, "NULL argument to pm_density_vjp");
+    hipStream_t s = S(stream);
+    LAUNCH(pm::K_ADJOINT, pm::launch_density_grad(x, c->P, dmesh, c->n, c->n, c->nseg, c->ws.seg_off,
+                                                  c->permuted ? c->ws.tags : nullptr, c->ws.quanta,
+                                                  (float)ldexp(1.0, -c->cfg.shift), 1.0f, xbar, s));
+    return PM_OK;
+}
+
+pm_status pm_force_vjp(pm_ctx *c, const float *x, const float *g, float *xbar, void *stream)
+{
+    if (!c || !x || !g || !xbar) return fail(PM_ERR_ARG, "NULL argument to pm_force_vjp");
+    hipStream_t s = S(stream);
+    pm_status st = force_vjp(c, x, g, 1.0, xbar, s);
+    return st == PM_OK ? check_guards(c, s) : st;
+}
+
+pm_status pm_step_vjp(pm_ctx *c, const float *x, double a_force, double a_kick0, double a_kick1, double a_drift1,
+                      float *xbar, float *pbar, void *stream)
+{
+    if (!c || !x || !xbar || !pbar) return fail(PM_ERR_ARG, "NULL argument to pm_step_vjp");
+    if (sorting_on(c))
+        return fail(PM_ERR_STATE, "the reverse mode needs PM_FLAG_NO_SORT: particles must keep their order");
+    double kick, drift;
+    pm_status st = pm_kdk_factors(c, a_force, a_kick0, a_kick1, a_drift1, &kick, &drift);
+    if (st != PM_OK) return st;
+    hipStream_t s = S(stream);
+    // x' = x + drift p', p' = p + kick F(x):  pbar += drift xbar, then
+    // xbar += kick (dF/dx)^T pbar
+    LAUNCH(pm::K_ADJOINT, pm::launch_axpy(pbar, xbar, (float)drift, 3 * c->P, s));
+    st = force_vjp(c, x, pbar, kick, xbar, s);
+    return st == PM_OK ? check_guards(c, s) : st;
+}
+
+pm_status pm_ic_vjp(pm_ctx *c, const float *xbar, const float *pbar, float *wbar, void *stream)
+{
+    if (!c || !xbar || !pbar || !wbar) return fail(PM_ERR_ARG, "NULL argument to pm_ic_vjp");
+    if (c->permuted) return fail(PM_ERR_STATE, "cotangents must be in the canonical particle order");
+    hipStream_t s = S(stream);
+    const pm_config &g = c->cfg;
+    const int nic = g.n_cdm, lg = ilog2i(nic), n = c->n;
+    const int64_t nhp = pm::half_pad(nic), n2 = (int64_t)nic * nic, cs = n2 * nhp;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    float2 *F = c->ws.f;
+    float *Fr = reinterpret_cast<float *>(F);
+    float2 *A = reinterpret_cast<float2 *>(c->ws.q);
+    const double a0 = g.a0;
+    const double D0 = pm::growth_D(*c, a0), D1 = pm::growth_D(*c, 1.0), G0 = pm::growth_G(*c, a0);
+    pm::IcParams ip{};
+    ip.amp_over_vcell = pm::pk_amplitude(*c) * (D0 / D1) * (D0 / D1) / pow(g.box / nic, 3);
+    ip.box = g.box;
+    ip.omh = g.omega_m * g.h;
+    ip.n_s = g.n_s;
+    ip.scale = ((double)n / g.box) / ((double)n2 * nic);
+    const float vfac = (float)(G0 / D0);
+    for (int pass = 0; pass < (c->nn > 0 ? 2 : 1); pass++) {
+        if (pass == 1) {
+            ip.kfs = 0.82 * sqrt(c->omega_L + g.omega_m / (a0 * a0 * a0)) * a0 * a0 * c->m1;
+            ip.half_cell = 0.5 * g.box / nic;
+        }
+        LAUNCH(pm::K_FILL, pm::launch_fill_i64(reinterpret_cast<int64_t *>(F), 3 * cs, s));
+        if (pass == 0)
+            LAUNCH(pm::K_ADJOINT, pm::launch_ic_adj_gather_cdm(xbar, pbar, c->P, nic, vfac, Fr, 2 * nhp, 2 * cs, s));
+        else
+            LAUNCH(pm::K_ADJOINT, pm::launch_ic_adj_gather_nu(xbar, pbar, c->P, c->nc, nic, g.n_sites, 2 * g.n_fib + 1,
+                                                              g.n_shell, vfac, Fr, 2 * nhp, 2 * cs, s));
+        for (int d = 0; d < 3; d++) {
+            float2 *Fd = F + d * cs;
+            LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, reinterpret_cast<float *>(Fd), 2 * nhp, Fd, nhp, n2,
+                                                      c->ws.tw, s));
+            LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, nhp, nic * nhp, nic, ncb, c->ws.tw, s));
+            LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, nic * nhp, nhp, nic, ncb, c->ws.tw, s));
+        }
+        LAUNCH(pm::K_ADJOINT, pm::launch_ic_adj_mult(F, nhp, cs, nic, &ip, A, pass > 0, s));
+    }
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, A, nic * nhp, nhp, nic, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, A, nhp, nic * nhp, nic, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, A, nhp, reinterpret_cast<float *>(A), 2 * nhp, n2, c->ws.tw, s));
+    LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(A), 2 * nhp, nic, wbar, s));
+    return PM_OK;
 }
 
 }  // extern "C"

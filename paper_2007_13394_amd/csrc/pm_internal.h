@@ -81,7 +81,7 @@ struct Workspace {
 enum KernelKind {
     K_FILL = 0, K_PAINT, K_R2C, K_COLS_FWD, K_AXIS0, K_COLS_INV, K_C2R, K_READOUT_KD, K_READOUT,
     K_POWER_BIN, K_POWER_REDUCE, K_IC_PARTICLES, K_COPY, K_SORT_COUNT, K_SORT_SCAN, K_SORT_SCATTER,
-    K_X0_GREEN, K_R2C_X0, K_C2R_X0, K_COUNT
+    K_X0_GREEN, K_R2C_X0, K_C2R_X0, K_ADJOINT, K_COUNT
 };
 
 struct TraceRec {
@@ -166,6 +166,25 @@ hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int
                          double offset, const float2 *tw, int *flag, hipStream_t s);
 hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int nhp, int64_t plane,
                          const float2 *tw, hipStream_t s);
+
+hipError_t launch_ic_adj_mult(const float2 *G, int64_t nhp, int64_t fs, int n, const IcParams *ic, float2 *acc,
+                              bool accumulate, hipStream_t s);
+
+// ---- launchers (adjoint.hip)
+hipError_t launch_axpy(float *y, const float *x, float a, int64_t n, hipStream_t s);
+hipError_t launch_readout_grad3(const float *x, int64_t P, const float *g, float gscale, const float *F, int64_t rs,
+                                int64_t cs, int n, float *xbar, hipStream_t s);
+hipError_t launch_paint_vec3(const float *x, int64_t P, const float *g, float gscale, float *G, int64_t rs,
+                             int64_t cs, int n, hipStream_t s);
+hipError_t launch_green_adj(float2 *F, int64_t nhp, int64_t fs, int n, double coef, hipStream_t s);
+hipError_t launch_density_grad(const float *x, int64_t P, const float *mesh, int64_t rs, int n, int nseg,
+                               const int64_t *seg_off, const uint8_t *tags, const int64_t *quanta, float qscale,
+                               float scale, float *xbar, hipStream_t s);
+hipError_t launch_q_to_delta(const int64_t *q, int64_t m, double scale, float *delta, hipStream_t s);
+hipError_t launch_ic_adj_gather_cdm(const float *xbar, const float *pbar, int64_t P, int nic, float vfac, float *F,
+                                    int64_t rs, int64_t cs, hipStream_t s);
+hipError_t launch_ic_adj_gather_nu(const float *xbar, const float *pbar, int64_t P, int64_t nc, int nic, int ns,
+                                   int nd, int n_shell, float vfac, float *F, int64_t rs, int64_t cs, hipStream_t s);
 
 // ---- launchers (paint.hip)
 hipError_t launch_paint(const float *x, int64_t stride, int64_t first, int64_t count, int64_t quantum,

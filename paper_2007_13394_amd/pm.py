@@ -79,6 +79,11 @@ _sig("pm_fft_c2r", [_vp, _vp, _vp, _vp])
 _sig("pm_force_mesh", [_vp, _vp, _vp, _vp])
 _sig("pm_force", [_vp, _vp, _vp, _vp])
 _sig("pm_step", [_vp, _vp, _vp, _dbl, _dbl, _dbl, _dbl, _vp])
+_sig("pm_density", [_vp, _vp, _vp, _vp])
+_sig("pm_density_vjp", [_vp, _vp, _vp, _vp, _vp])
+_sig("pm_force_vjp", [_vp, _vp, _vp, _vp, _vp])
+_sig("pm_step_vjp", [_vp, _vp, _dbl, _dbl, _dbl, _dbl, _vp, _vp, _vp])
+_sig("pm_ic_vjp", [_vp, _vp, _vp, _vp, _vp])
 _sig("pm_power", [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp])
 _sig("pm_trace_begin", [_vp, _i32])
 _sig("pm_attach_ids", [_vp, _vp])
@@ -91,7 +96,8 @@ _lib.pm_kernel_name.argtypes = [_i32]
 EXPORTS = ["pm_sizes", "pm_init", "pm_free", "pm_last_error", "pm_segments", "pm_shells", "pm_growth",
            "pm_kdk_factors", "pm_ic", "pm_paint_q", "pm_paint", "pm_fft_r2c", "pm_fft_c2r", "pm_force_mesh",
            "pm_force", "pm_step", "pm_power", "pm_trace_begin", "pm_trace_end", "pm_kernel_name", "pm_attach_ids",
-           "pm_segment_tags", "pm_reset_order"]
+           "pm_segment_tags", "pm_reset_order", "pm_density", "pm_density_vjp", "pm_force_vjp", "pm_step_vjp",
+           "pm_ic_vjp"]
 
 
 def _check(st):
@@ -279,3 +285,36 @@ def pm_segment_tags(ctx, out=None, stream=None):
 
 def pm_reset_order(ctx):
     _check(_lib.pm_reset_order(ctx.h))
+
+
+# ---- reverse mode (device float32 arrays; cotangents accumulate in place)
+def pm_density(ctx, x, delta, stream=None):
+    n = ctx.n
+    _check(_lib.pm_density(ctx.h, _dev(x, torch.float32, 3 * ctx.P, "x"),
+                           _dev(delta, torch.float32, n ** 3, "delta"), _stream(stream)))
+
+
+def pm_density_vjp(ctx, x, dmesh, xbar, stream=None):
+    n = ctx.n
+    _check(_lib.pm_density_vjp(ctx.h, _dev(x, torch.float32, 3 * ctx.P, "x"),
+                               _dev(dmesh, torch.float32, n ** 3, "dmesh"),
+                               _dev(xbar, torch.float32, 3 * ctx.P, "xbar"), _stream(stream)))
+
+
+def pm_force_vjp(ctx, x, g, xbar, stream=None):
+    _check(_lib.pm_force_vjp(ctx.h, _dev(x, torch.float32, 3 * ctx.P, "x"), _dev(g, torch.float32, 3 * ctx.P, "g"),
+                             _dev(xbar, torch.float32, 3 * ctx.P, "xbar"), _stream(stream)))
+
+
+def pm_step_vjp(ctx, x, a_force, a_kick0, a_kick1, a_drift1, xbar, pbar, stream=None):
+    _check(_lib.pm_step_vjp(ctx.h, _dev(x, torch.float32, 3 * ctx.P, "x"), a_force, a_kick0, a_kick1, a_drift1,
+                            _dev(xbar, torch.float32, 3 * ctx.P, "xbar"), _dev(pbar, torch.float32, 3 * ctx.P, "pbar"),
+                            _stream(stream)))
+
+
+def pm_ic_vjp(ctx, xbar, pbar, wbar, stream=None):
+    nc = ctx.cfg.n_cdm ** 3
+    _check(_lib.pm_ic_vjp(ctx.h, _dev(xbar, torch.float32, 3 * ctx.P, "xbar"),
+                          _dev(pbar, torch.float32, 3 * ctx.P, "pbar"), _dev(wbar, torch.float32, nc, "wbar"),
+                          _stream(stream)))
+

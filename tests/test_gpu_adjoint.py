@@ -1,0 +1,195 @@
+"""GPU reverse mode (pm_*_vjp through the C ABI, and the autograd layer)
+against the FP64 oracle's reverse mode, which is itself pinned by central
+finite differences (test_oracle_adjoint.py).  Same float32 inputs on both
+sides; bar: relative L2 <= 1e-4 (FP32 state and transforms, float atomics in
+the cotangent paint, against FP64)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2007_13394_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _setup(name, **over):
+    from paper_2007_13394_amd import pm
+    cfg = I.config(name, **over)
+    ctx = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_NO_SORT))
+    return pm, cfg, ctx, O.make_sim(cfg)
+
+
+def _calls(cfg, sim):
+    from paper_2007_13394_amd import run as R
+    a, half = R.schedule(cfg["a0"], cfg["n_lin"], cfg["n_log"], cfg["a_mid"])
+    calls = R.kdk_calls(a, half)
+    kick, drift = O.kdk_factors(sim.cosmo, *[list(c) for c in zip(*calls)])
+    return calls, kick, drift
+
+
+@pytest.mark.parametrize("name", ["C5_fd16", "C5_fd32", "C5"])
+def test_force_and_density_vjp_vs_oracle(dev, name):
+    pm, cfg, ctx, sim = _setup(name)
+    x32, _ = I.synthetic_state(cfg, seed=21)
+    P = x32.shape[1]
+    rng = np.random.default_rng(22)
+    g32 = rng.standard_normal((3, P)).astype(np.float32)
+    n = cfg["n_mesh"]
+    A32 = rng.standard_normal((n, n, n)).astype(np.float32)
+    x = torch.from_numpy(x32).to(dev)
+    xb = torch.zeros_like(x)
+    pm.pm_force_vjp(ctx, x, torch.from_numpy(g32).to(dev), xb)
+    ref = O.force_vjp(sim, x32.astype(np.float64), g32.astype(np.float64))
+    e1 = rel_l2(xb.cpu().numpy(), ref)
+    xb.zero_()
+    pm.pm_density_vjp(ctx, x, torch.from_numpy(A32).to(dev).reshape(-1), xb)
+    ref2 = O.density_vjp(sim, x32.astype(np.float64), A32.astype(np.float64))
+    e2 = rel_l2(xb.cpu().numpy(), ref2)
+    say(name, "force vjp rel L2", e1, "density vjp rel L2", e2)
+    assert e1 < TOL and e2 < TOL
+
+
+@pytest.mark.parametrize("name", ["C5_fd32", "C5"])
+def test_step_vjp_vs_oracle(dev, name):
+    pm, cfg, ctx, sim = _setup(name)
+    x32, _ = I.synthetic_state(cfg, seed=23)
+    P = x32.shape[1]
+    rng = np.random.default_rng(24)
+    a32 = rng.standard_normal((3, P)).astype(np.float32)
+    b32 = rng.standard_normal((3, P)).astype(np.float32)
+    calls, kick, drift = _calls(cfg, sim)
+    c = 3
+    x = torch.from_numpy(x32).to(dev)
+    xb, pb = torch.from_numpy(a32).to(dev), torch.from_numpy(b32).to(dev)
+    pm.pm_step_vjp(ctx, x, *calls[c], xb, pb)
+    rx, rp = O.step_vjp(sim, x32.astype(np.float64), kick[c], drift[c], a32, b32)
+    ex, ep = rel_l2(xb.cpu().numpy(), rx), rel_l2(pb.cpu().numpy(), rp)
+    say(name, "step vjp rel L2 x", ex, "p", ep)
+    assert ex < TOL and ep < TOL
+
+
+def test_step_vjp_refuses_sorted_context(dev):
+    from paper_2007_13394_amd import pm
+    cfg = I.config("C5_fd32")
+    ctx = pm.Ctx(pm.make_config(cfg))
+    x = torch.zeros((3, ctx.P), dtype=torch.float32, device=dev)
+    with pytest.raises(pm.PMError) as e:
+        pm.pm_step_vjp(ctx, x, 0.1, 0.1, 0.1, 0.1, torch.zeros_like(x), torch.zeros_like(x))
+    assert e.value.status == pm.PM_ERR_STATE
+
+
+@pytest.mark.parametrize("name", ["C5_fd16", "C5_fd32", "C5"])
+def test_ic_vjp_vs_oracle(dev, name):
+    pm, cfg, ctx, sim = _setup(name)
+    P = ctx.P
+    rng = np.random.default_rng(25)
+    a32 = rng.standard_normal((3, P)).astype(np.float32)
+    b32 = rng.standard_normal((3, P)).astype(np.float32)
+    nc = cfg["n_cdm"]
+    wb = torch.empty(nc ** 3, dtype=torch.float32, device=dev)
+    pm.pm_ic_vjp(ctx, torch.from_numpy(a32).to(dev), torch.from_numpy(b32).to(dev), wb)
+    ref = O.ic_vjp(sim, a32, b32)
+    e = rel_l2(wb.cpu().numpy().reshape(nc, nc, nc), ref)
+    say(name, "ic vjp rel L2", e)
+    assert e < TOL
+
+
+def _gpu_chain(pm, cfg, ctx, dev, n_calls):
+    """Autograd gradient of sum (delta - target)^2 with respect to the white
+    noise; the target is the run from another seed.  Also returns the GPU
+    forward states (the checkpoints: positions before every call, the final
+    positions and density), replayed bit-identically with the same kernels."""
+    from paper_2007_13394_amd import diff
+    sim = O.make_sim(cfg)
+    calls, kick, drift = _calls(cfg, sim)
+    calls = calls[:n_calls]
+    nc = cfg["n_cdm"]
+    wt = torch.from_numpy(I.white_noise(cfg["seed"], nc)).to(dev)
+    with torch.no_grad():
+        target = diff.final_density(ctx, wt, calls)
+    w = torch.from_numpy(I.white_noise(cfg["seed"] + 100, nc)).to(dev).requires_grad_(True)
+    delta = diff.final_density(ctx, w, calls)
+    loss = ((delta - target) ** 2).sum()
+    loss.backward()
+    with torch.no_grad():
+        x, p = ctx.particles()
+        pm.pm_ic(ctx, w.detach(), x, p)
+        cps = []
+        for c in calls:
+            cps.append(x.cpu().numpy().astype(np.float64))
+            pm.pm_step(ctx, x, p, *c)
+        xf = x.cpu().numpy().astype(np.float64)
+        d2 = torch.empty_like(delta)
+        pm.pm_density(ctx, x, d2)
+    assert torch.equal(d2, delta.detach())
+    return (float(loss.detach()), w.grad.cpu().numpy(), target.cpu().numpy(), kick[:n_calls], drift[:n_calls],
+            cps, xf, delta.detach().cpu().numpy())
+
+
+def _oracle_reverse(cfg, cps, xf, delta, target, kick, drift):
+    sim = O.make_sim(cfg)
+    xbar = O.density_vjp(sim, xf, 2.0 * (delta.astype(np.float64) - target.astype(np.float64)))
+    pbar = np.zeros_like(xbar)
+    for i in reversed(range(len(cps))):
+        xbar, pbar = O.step_vjp(sim, cps[i], kick[i], drift[i], xbar, pbar)
+    return O.ic_vjp(sim, xbar, pbar)
+
+
+def _oracle_chain(cfg, target, kick, drift):
+    sim = O.make_sim(cfg)
+    nc = cfg["n_cdm"]
+    w = I.white_noise(cfg["seed"] + 100, nc).astype(np.float64)
+    x, p = O.ic_w64(sim, w)
+    x, p = np.ascontiguousarray(x), np.ascontiguousarray(p)
+    cps = []
+    for i in range(len(kick)):
+        cps.append(x.copy())
+        O.step_cont(sim, x, p, kick[i], drift[i])
+    d = O.density_cont(sim, x)
+    t = target.astype(np.float64)
+    loss = float(np.sum((d - t) ** 2))
+    return loss, _oracle_reverse(cfg, cps, x, d, target, kick, drift)
+
+
+@pytest.mark.parametrize("name,n_calls", [("C5_fd16", 11), ("C5_fd32", 11), ("C5", 2)])
+def test_chain_gradient_vs_oracle(dev, name, n_calls):
+    """White noise -> initial conditions -> KDK calls -> painted density ->
+    L2 loss against a target density, differentiated through the autograd
+    layer (per-step checkpoints, hand-written reverse kernels).  The oracle's
+    reverse pass runs on the GPU's own forward states (same inputs for both
+    reverse passes): bar 1e-4 relative L2."""
+    pm, cfg, ctx, _ = _setup(name)
+    loss, grad, target, kick, drift, cps, xf, delta = _gpu_chain(pm, cfg, ctx, dev, n_calls)
+    rgrad = _oracle_reverse(cfg, cps, xf, delta, target, kick, drift)
+    e = rel_l2(grad.reshape(rgrad.shape), rgrad)
+    say(name, n_calls, "calls: loss", loss, "gradient rel L2 (same checkpoints)", e)
+    assert e < TOL
+
+
+@pytest.mark.parametrize("name", ["C5_fd16", "C5_fd32"])
+def test_chain_gradient_vs_independent_oracle_run(dev, name):
+    """The same gradient against a run of the oracle's FP64 forward model from
+    the same white noise.  The FP32 and FP64 trajectories differ at the 1e-6
+    level, and a particle that lands on the other side of a cell face changes
+    its derivative term, so the bar here is 5e-4 (loss: 1e-4)."""
+    pm, cfg, ctx, _ = _setup(name)
+    loss, grad, target, kick, drift, _, _, _ = _gpu_chain(pm, cfg, ctx, dev, 11)
+    rloss, rgrad = _oracle_chain(cfg, target, kick, drift)
+    e = rel_l2(grad.reshape(rgrad.shape), rgrad)
+    say(name, "independent runs: loss", loss, "oracle", rloss, "gradient rel L2", e)
+    assert abs(loss - rloss) / rloss < 1e-4
+    assert e < 5e-4
