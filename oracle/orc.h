@@ -115,6 +115,27 @@ int  orc_force_vjp(const orc_sim *s, const double *x, const double *g, double *x
 int  orc_step_vjp(const orc_sim *s, const double *x, double kick, double drift, double *xbar, double *pbar);
 int  orc_density_vjp(const orc_sim *s, const double *x, const double *dmesh, double *xbar);
 
+/* ---------------- learned force correction (net.c) ---------------- */
+#define NET_H 96      /* MLP hidden width */
+#define NET_NB 256    /* radial table bins */
+#define NET_C 16      /* CNN channels */
+enum {
+    NET_W0 = 0, NET_B0 = NET_W0 + NET_H * 2, NET_W1 = NET_B0 + NET_H, NET_B1 = NET_W1 + NET_H * NET_H,
+    NET_W2 = NET_B1 + NET_H, NET_B2 = NET_W2 + NET_H * NET_H, NET_W3 = NET_B2 + NET_H, NET_B3 = NET_W3 + NET_H,
+    NET_C1W = NET_B3 + 1, NET_C1B = NET_C1W + NET_C * 27, NET_C2W = NET_C1B + NET_C,
+    NET_C2B = NET_C2W + NET_C * NET_C * 27, NET_C3W = NET_C2B + NET_C, NET_C3B = NET_C3W + NET_C * 27,
+    NET_NPARAM = NET_C3B + 1
+};
+double orc_net_kt(int b);
+void   orc_net_table(const double *th, double a, double *table);
+void   orc_net_table_vjp(const double *th, double a, const double *tbar, double *dth);
+void   orc_conv3(const double *in, int ci_n, const double *W, const double *bias, int co_n, int n, double *out);
+void   orc_conv3_vjp(const double *in, int ci_n, const double *W, int co_n, int n, const double *dout, double *din,
+                     double *dW, double *db);
+int    orc_learned_force(const orc_sim *s, const double *th, double a, const double *x, double *acc);
+int    orc_learned_loss(const orc_sim *s, const double *th, double a, const double *x, const double *target,
+                        double *loss, double *dth);
+
 /* ---------------- power spectrum (power.c) ---------------- */
 void orc_power(const double *da, const double *db, int n, double box, int nbins, int compensate,
                double *k_mean, double *pk, double *n_modes);

@@ -13,7 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liborc.so")
-_SRC = ["fft.c", "cosmo.c", "nu.c", "ic.c", "pm.c", "power.c", "adj.c"]
+_SRC = ["fft.c", "cosmo.c", "nu.c", "ic.c", "pm.c", "power.c", "adj.c", "net.c"]
 
 
 def build():
@@ -97,6 +97,13 @@ _sig("orc_step_cont", C.c_int, [C.POINTER(Sim), _dp, _dp, C.c_double, C.c_double
 _sig("orc_force_vjp", C.c_int, [C.POINTER(Sim), _dp, _dp, _dp])
 _sig("orc_step_vjp", C.c_int, [C.POINTER(Sim), _dp, C.c_double, C.c_double, _dp, _dp])
 _sig("orc_density_vjp", C.c_int, [C.POINTER(Sim), _dp, _dp, _dp])
+_sig("orc_net_kt", C.c_double, [C.c_int])
+_sig("orc_net_table", None, [_dp, C.c_double, _dp])
+_sig("orc_net_table_vjp", None, [_dp, C.c_double, _dp, _dp])
+_sig("orc_conv3", None, [_dp, C.c_int, _dp, _dp, C.c_int, C.c_int, _dp])
+_sig("orc_conv3_vjp", None, [_dp, C.c_int, _dp, C.c_int, C.c_int, _dp, C.c_void_p, _dp, _dp])
+_sig("orc_learned_force", C.c_int, [C.POINTER(Sim), _dp, C.c_double, _dp, _dp])
+_sig("orc_learned_loss", C.c_int, [C.POINTER(Sim), _dp, C.c_double, _dp, _dp, C.POINTER(C.c_double), C.c_void_p])
 
 
 # ---------------------------------------------------------------- FFT
@@ -475,4 +482,73 @@ def density_vjp(sim, x, dmesh):
     if _lib.orc_density_vjp(C.byref(sim), _c64(x).reshape(-1), _c64(dmesh).reshape(-1), xbar.reshape(-1)) != 0:
         raise ValueError("density_vjp failed")
     return xbar
+
+
+# ---------------------------------------------------------------- learned correction (net.c)
+NET_H, NET_NB, NET_C = 96, 256, 16
+_NET_SIZES = [("W0", NET_H * 2), ("B0", NET_H), ("W1", NET_H * NET_H), ("B1", NET_H), ("W2", NET_H * NET_H),
+              ("B2", NET_H), ("W3", NET_H), ("B3", 1), ("C1W", NET_C * 27), ("C1B", NET_C),
+              ("C2W", NET_C * NET_C * 27), ("C2B", NET_C), ("C3W", NET_C * 27), ("C3B", 1)]
+NET_OFF = {}
+_o = 0
+for _k, _n in _NET_SIZES:
+    NET_OFF[_k] = (_o, _n)
+    _o += _n
+NET_NPARAM = _o
+
+
+def net_kt(b):
+    return _lib.orc_net_kt(b)
+
+
+def net_table(th, a):
+    t = np.empty(NET_NB)
+    _lib.orc_net_table(_c64(th), a, t)
+    return t
+
+
+def net_table_vjp(th, a, tbar):
+    d = np.zeros(NET_NPARAM)
+    _lib.orc_net_table_vjp(_c64(th), a, _c64(tbar), d)
+    return d
+
+
+def conv3(x, W, b):
+    """x [ci, n, n, n] -> [co, n, n, n] periodic 3^3 cross-correlation."""
+    x = _c64(x)
+    ci, n = x.shape[0], x.shape[1]
+    co = len(b)
+    out = np.empty((co, n, n, n))
+    _lib.orc_conv3(x.reshape(-1), ci, _c64(W).reshape(-1), _c64(b), co, n, out.reshape(-1))
+    return out
+
+
+def conv3_vjp(x, W, co, dout, want_dx=True):
+    x = _c64(x)
+    ci, n = x.shape[0], x.shape[1]
+    dx = np.zeros_like(x) if want_dx else None
+    dW = np.zeros(co * ci * 27)
+    db = np.zeros(co)
+    _lib.orc_conv3_vjp(x.reshape(-1), ci, _c64(W).reshape(-1), co, n, _c64(dout).reshape(-1),
+                       dx.ctypes.data if want_dx else None, dW, db)
+    return dx, dW, db
+
+
+def learned_force(sim, th, a, x):
+    x = _c64(x)
+    acc = np.empty_like(x)
+    if _lib.orc_learned_force(C.byref(sim), _c64(th), a, x.reshape(-1), acc.reshape(-1)) != 0:
+        raise ValueError("learned_force failed")
+    return acc
+
+
+def learned_loss(sim, th, a, x, target, grad=True):
+    """(loss, dloss/dth or None) of sum |F - target|^2 / sum |target|^2."""
+    loss = C.c_double()
+    d = np.zeros(NET_NPARAM) if grad else None
+    rc = _lib.orc_learned_loss(C.byref(sim), _c64(th), a, _c64(x).reshape(-1), _c64(target).reshape(-1),
+                               C.byref(loss), d.ctypes.data if grad else None)
+    if rc != 0:
+        raise ValueError("learned_loss failed")
+    return loss.value, d
 
