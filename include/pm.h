@@ -67,6 +67,8 @@ enum {
     PM_FLAG_NO_GUARDS = 2, /* skip the end-of-call device flag check (no host sync) */
     PM_FLAG_NO_SORT = 4,   /* keep particles in segment order (pm_step paints with
                               global atomics and gathers the force: slower) */
+    PM_FLAG_LEARNED = 8,   /* reserve the workspace of the learned force correction
+                              (pm_learned_*; N a power of two >= 16) */
 };
 
 /* Simulation parameters (Table 1 of the paper names the counts).  All
@@ -278,6 +280,41 @@ pm_status pm_step_vjp(pm_ctx *ctx, const float *x, double a_force, double a_kick
  * F^-1 diag(M) F white, whose transpose is F^-1 diag(conj M) F.  Cotangents in
  * canonical order (PM_ERR_STATE after a sorted step). */
 pm_status pm_ic_vjp(pm_ctx *ctx, const float *xbar, const float *pbar, float *wbar, void *stream);
+
+/* ---- Learned force correction (an addition to the method for the
+ * coarse-mesh use the paper's introduction motivates; configure with
+ * PM_FLAG_LEARNED).  Model: the potential spectrum -1.5 Omega_m0 delta(k) / k^2
+ * is multiplied by a radial filter g(k, a) = 1 + MLP(|k| / k_Nyq, a) (two
+ * inputs, three hidden layers of 96 SiLU units, tabulated at 256 radial bins
+ * and interpolated linearly); a periodic 3^3 CNN (1 -> 16 -> 16 -> 1
+ * channels, SiLU; BF16 activations and weights, FP32 accumulation) maps the
+ * filtered potential phi_f / D(a) to a correction, phi = phi_f + D(a) cnn; the
+ * force is minus its spectral gradient, read out with cloud-in-cell weights.
+ * With the output layers at zero it is the plain force.  theta: device
+ * float32 [pm_net_nparam()], the flat parameter array (MLP W0 [96][2], b0,
+ * W1 [96][96], b1, W2 [96][96], b2, W3 [96], b3; conv W [co][ci][27] and b for
+ * the three layers, taps (t0 3 + t1) 3 + t2 at offsets t_e - 1). */
+int32_t pm_net_nparam(void);
+
+/* Learned force on every particle at x (a: scale factor for the filter and
+ * D(a)).  acc: device [3][P]. */
+pm_status pm_learned_force(pm_ctx *ctx, const float *theta, double a, const float *x, float *acc, void *stream);
+
+/* pm_step with the learned force (same factors and semantics, unsorted). */
+pm_status pm_learned_step(pm_ctx *ctx, const float *theta, float *x, float *p, double a_force, double a_kick0,
+                          double a_kick1, double a_drift1, void *stream);
+
+/* Force-matching loss L = sum |acc - target|^2 / sum |target|^2 of the learned
+ * force at x against target [3][P] (device), written to *loss (host; the
+ * call waits for the stream), and dL/dtheta accumulated into dtheta (device
+ * float32, or NULL for the loss alone) by the hand-written reverse mode. */
+pm_status pm_learned_loss(pm_ctx *ctx, const float *theta, double a, const float *x, const float *target,
+                          double *loss, float *dtheta, void *stream);
+
+/* One Adam step (bias-corrected, step t >= 1) on n FP32 master weights theta
+ * with moments m, v and gradient g, all device arrays. */
+pm_status pm_adam(float *theta, float *m, float *v, const float *g, int64_t n, double lr, double beta1,
+                  double beta2, double eps, int32_t t, void *stream);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,7 @@ SOURCES = {
     "particles.hip": [],
     "sort.hip": [],
     "adjoint.hip": [],
+    "net.hip": [],
     "host_cosmo.cpp": ["-ffp-contract=off", "-x", "hip"],
     "host.cpp": ["-x", "hip"],
 }

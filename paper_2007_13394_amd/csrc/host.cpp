@@ -63,6 +63,8 @@ int ilog2i(int v)
 
 struct Layout {
     size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags, ids, koff, key, rank, cnt, bsum, total;
+    size_t net_phif, net_z1, net_a1, net_z2, net_a2, net_g1, net_g2, net_dpsi, net_dk, net_acc, net_table, net_tbar,
+        net_red;
     int64_t nkeys;
 };
 
@@ -120,6 +122,25 @@ Layout layout(const pm_config &c)
         L.rank = L.key + align256(4 * (size_t)P);
         L.cnt = L.rank + align256(4 * (size_t)P);
         L.bsum = L.cnt + align256(4 * (size_t)(L.nkeys + 1));
+    }
+    L.net_phif = L.net_z1 = L.net_a1 = L.net_z2 = L.net_a2 = L.net_g1 = L.net_g2 = L.net_dpsi = L.net_dk = 0;
+    L.net_acc = L.net_table = L.net_tbar = L.net_red = 0;
+    if (c.flags & PM_FLAG_LEARNED) {
+        const size_t M = (size_t)(n * n * n);
+        auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+        L.net_phif = take((size_t)(n * n * 2 * nhp) * 4);
+        L.net_z1 = take(M * pm::NET_C * 4);
+        L.net_a1 = take(M * pm::NET_C * 2);
+        L.net_z2 = take(M * pm::NET_C * 4);
+        L.net_a2 = take(M * pm::NET_C * 2);
+        L.net_g1 = take(M * pm::NET_C * 4);
+        L.net_g2 = take(M * pm::NET_C * 4);
+        L.net_dpsi = take(M * 4);
+        L.net_dk = take((size_t)(n * n * nhp) * 8);
+        L.net_acc = take((size_t)(3 * P) * 4);
+        L.net_table = take(pm::NET_NB * 4);
+        L.net_tbar = take(pm::NET_NB * 8);
+        L.net_red = take(64);
     }
     L.total = off;
     return L;
@@ -314,6 +335,52 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
     return PM_OK;
 }
 
+// Learned force meshes into the F region (real rows of stride 2 Nhp) from
+// the density in Q: natural-order transforms; the filtered potential, the
+// CNN activations and (keep) the density spectrum stay in the workspace for
+// the reverse mode.
+pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStream_t s)
+{
+    const int n = c->n, lg = c->logn;
+    const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n, cs = n2 * nhp, rs = 2 * nhp;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    const double M = (double)n2 * n;
+    float2 *F = c->ws.f;
+    const double Da = pm::growth_D(*c, a) / pm::growth_D(*c, 1.0);
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, F, nhp, n2, ldexp(1.0, -c->cfg.shift), -1.0, c->ws.tw,
+                                              c->ws.flag, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    if (keep) LAUNCH(pm::K_COPY, hipMemcpyAsync(c->ws.net_dk, F, (size_t)cs * 8, hipMemcpyDeviceToDevice, s));
+    LAUNCH(pm::K_NET, pm::launch_mlp_fwd(th, a, c->ws.net_table, s));
+    LAUNCH(pm::K_NET, pm::launch_spec_filter(F, F + cs, nhp, n, c->ws.net_table, -1.5 * c->cfg.omega_m / M, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + cs, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + cs, nhp, c->ws.net_phif, rs, n2, c->ws.tw, s));
+    LAUNCH(pm::K_NET, pm::launch_cnn_fwd(c->ws.net_phif, rs, n, 1.0 / Da, th, c->ws.net_z1, c->ws.net_a1,
+                                         c->ws.net_z2, c->ws.net_a2, c->ws.net_dpsi, s));
+    float *Fr = reinterpret_cast<float *>(F);
+    LAUNCH(pm::K_NET, pm::launch_combine(c->ws.net_phif, c->ws.net_dpsi, rs, n, Da, Fr, s));
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, Fr, rs, F, nhp, n2, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_NET, pm::launch_grad3(F, nhp, cs, n, 1.0 / M, false, s));
+    for (int d = 0; d < 3; d++) {
+        float2 *Fd = F + d * cs;
+        LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, Fd, n * nhp, nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, Fd, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, Fd, nhp, reinterpret_cast<float *>(Fd), rs, n2, c->ws.tw, s));
+    }
+    return PM_OK;
+}
+
+pm_status learned_ready(pm_ctx *c)
+{
+    if (!(c->cfg.flags & PM_FLAG_LEARNED)) return fail(PM_ERR_STATE, "configure the context with PM_FLAG_LEARNED");
+    if (c->n < 16) return fail(PM_ERR_STATE, "the learned correction needs N >= 16");
+    return PM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -374,6 +441,21 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
         c->ws.cnt = reinterpret_cast<int *>(b + L.cnt);
         c->ws.bsum = reinterpret_cast<int *>(b + L.bsum);
     }
+    if (cfg->flags & PM_FLAG_LEARNED) {
+        c->ws.net_phif = reinterpret_cast<float *>(b + L.net_phif);
+        c->ws.net_z1 = reinterpret_cast<float *>(b + L.net_z1);
+        c->ws.net_a1 = reinterpret_cast<uint16_t *>(b + L.net_a1);
+        c->ws.net_z2 = reinterpret_cast<float *>(b + L.net_z2);
+        c->ws.net_a2 = reinterpret_cast<uint16_t *>(b + L.net_a2);
+        c->ws.net_g1 = reinterpret_cast<float *>(b + L.net_g1);
+        c->ws.net_g2 = reinterpret_cast<float *>(b + L.net_g2);
+        c->ws.net_dpsi = reinterpret_cast<float *>(b + L.net_dpsi);
+        c->ws.net_dk = reinterpret_cast<float2 *>(b + L.net_dk);
+        c->ws.net_acc = reinterpret_cast<float *>(b + L.net_acc);
+        c->ws.net_table = reinterpret_cast<float *>(b + L.net_table);
+        c->ws.net_tbar = reinterpret_cast<double *>(b + L.net_tbar);
+        c->ws.net_red = reinterpret_cast<double *>(b + L.net_red);
+    }
     // twiddles for every power-of-two length L <= N: tw[L + m] = exp(-2 pi i m / L)
     const int n = c->n;
     c->tw_host.assign(2 * (size_t)n, make_float2(0.f, 0.f));
@@ -421,7 +503,7 @@ void pm_free(pm_ctx *ctx)
 static const char *kKernelNames[pm::K_COUNT] = {
     "fill",      "paint",        "r2c_rows",     "cols_fwd",   "axis0",      "cols_inv",   "c2r_rows",
     "readout_kick_drift", "readout", "power_bin", "power_reduce", "ic_particles", "copy", "sort_count",
-    "sort_scan", "sort_scatter", "x0_green", "r2c_x0", "c2r_x0", "adjoint"};
+    "sort_scan", "sort_scatter", "x0_green", "r2c_x0", "c2r_x0", "adjoint", "net"};
 
 const char *pm_kernel_name(int32_t kind)
 {
@@ -842,6 +924,103 @@ pm_status pm_ic_vjp(pm_ctx *c, const float *xbar, const float *pbar, float *wbar
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, A, nhp, nic * nhp, nic, ncb, c->ws.tw, s));
     LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, A, nhp, reinterpret_cast<float *>(A), 2 * nhp, n2, c->ws.tw, s));
     LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(A), 2 * nhp, nic, wbar, s));
+    return PM_OK;
+}
+
+// ---- learned force correction
+
+int32_t pm_net_nparam(void) { return pm::NET_NPARAM; }
+
+pm_status pm_learned_force(pm_ctx *c, const float *th, double a, const float *x, float *acc, void *stream)
+{
+    if (!c || !th || !x || !acc) return fail(PM_ERR_ARG, "NULL argument to pm_learned_force");
+    pm_status st = learned_ready(c);
+    if (st != PM_OK) return st;
+    hipStream_t s = S(stream);
+    st = paint_all(c, x, s);
+    if (st == PM_OK) st = learned_solve(c, th, a, false, s);
+    if (st != PM_OK) return st;
+    const int64_t n = c->n, nhp = pm::half_pad(c->n);
+    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, c->ws.f, nhp, n * n * nhp, c->n, acc, s));
+    return check_guards(c, s);
+}
+
+pm_status pm_learned_step(pm_ctx *c, const float *th, float *x, float *p, double a_force, double a_kick0,
+                          double a_kick1, double a_drift1, void *stream)
+{
+    if (!c || !th || !x || !p) return fail(PM_ERR_ARG, "NULL argument to pm_learned_step");
+    pm_status st = learned_ready(c);
+    if (st != PM_OK) return st;
+    double kick, drift;
+    st = pm_kdk_factors(c, a_force, a_kick0, a_kick1, a_drift1, &kick, &drift);
+    if (st != PM_OK) return st;
+    hipStream_t s = S(stream);
+    st = paint_all(c, x, s);
+    if (st == PM_OK) st = learned_solve(c, th, a_force, false, s);
+    if (st != PM_OK) return st;
+    const int64_t n = c->n, nhp = pm::half_pad(c->n);
+    LAUNCH(pm::K_READOUT_KD, pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, n * n * nhp, c->n, (float)kick,
+                                                           (float)drift, c->ws.flag, s));
+    return check_guards(c, s);
+}
+
+pm_status pm_learned_loss(pm_ctx *c, const float *th, double a, const float *x, const float *target, double *loss,
+                          float *dth, void *stream)
+{
+    if (!c || !th || !x || !target || !loss) return fail(PM_ERR_ARG, "NULL argument to pm_learned_loss");
+    pm_status st = learned_ready(c);
+    if (st != PM_OK) return st;
+    hipStream_t s = S(stream);
+    const int n = c->n, lg = c->logn;
+    const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n, cs = n2 * nhp, rs = 2 * nhp;
+    const int ncb = (int)(nhp / pm::TILE_W);
+    const double M = (double)n2 * n;
+    float2 *F = c->ws.f;
+    float *Fr = reinterpret_cast<float *>(F);
+    st = paint_all(c, x, s);
+    if (st == PM_OK) st = learned_solve(c, th, a, dth != nullptr, s);
+    if (st != PM_OK) return st;
+    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, F, nhp, cs, n, c->ws.net_acc, s));
+    LAUNCH(pm::K_NET, pm::launch_force_loss(c->ws.net_acc, target, 3 * c->P, c->ws.net_red, s));
+    double red[2];
+    if (hipMemcpyAsync(red, c->ws.net_red, sizeof(red), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(PM_ERR_DEVICE, "reading the loss back failed");
+    if (!(red[1] > 0)) return fail(PM_ERR_ARG, "the target forces are all zero");
+    *loss = red[0] / red[1];
+    if (!dth) return check_guards(c, s);
+    // readout transpose, gradient transpose, CNN and filter reverse mode
+    const double Da = pm::growth_D(*c, a) / pm::growth_D(*c, 1.0);
+    LAUNCH(pm::K_FILL, pm::launch_fill_i64(reinterpret_cast<int64_t *>(F), 3 * cs, s));
+    LAUNCH(pm::K_ADJOINT, pm::launch_paint_vec3(x, c->P, c->ws.net_acc, (float)(2.0 / red[1]), Fr, rs, 2 * cs, n, s));
+    for (int d = 0; d < 3; d++) {
+        float2 *Fd = F + d * cs;
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, reinterpret_cast<float *>(Fd), rs, Fd, nhp, n2, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    }
+    LAUNCH(pm::K_NET, pm::launch_grad3(F, nhp, cs, n, 1.0 / M, true, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F, nhp, Fr, rs, n2, c->ws.tw, s));
+    LAUNCH(pm::K_NET, pm::launch_cnn_bwd(c->ws.net_phif, Fr, rs, n, Da, th, c->ws.net_z1, c->ws.net_a1, c->ws.net_z2,
+                                         c->ws.net_a2, c->ws.net_g1, c->ws.net_g2, Fr, dth, s));
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, Fr, rs, F, nhp, n2, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    LAUNCH(pm::K_NET, pm::launch_spec_filter_bwd(c->ws.net_dk, F, nhp, n, -1.5 * c->cfg.omega_m / M,
+                                                 c->ws.net_tbar, s));
+    LAUNCH(pm::K_NET, pm::launch_mlp_bwd(th, a, c->ws.net_tbar, dth, s));
+    return check_guards(c, s);
+}
+
+pm_status pm_adam(float *th, float *m, float *v, const float *g, int64_t n, double lr, double beta1, double beta2,
+                  double eps, int32_t t, void *stream)
+{
+    if (!th || !m || !v || !g || n < 0 || t < 1) return fail(PM_ERR_ARG, "bad argument to pm_adam");
+    hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : nullptr;
+    if (pm::launch_adam(th, m, v, g, n, lr, beta1, beta2, eps, t, s) != hipSuccess)
+        return fail(PM_ERR_DEVICE, "adam launch failed");
     return PM_OK;
 }
 

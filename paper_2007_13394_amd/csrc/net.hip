@@ -1,0 +1,727 @@
+// Learned force correction: kernels of the forward model and its reverse mode.
+//
+// Model (an addition to the method; the paper's introduction motivates
+// learned corrections of fast particle-mesh codes): a radial filter
+// g(k, a) = 1 + MLP(|k| / k_Nyq, a) on the potential spectrum, tabulated at
+// NET_NB radial bins and interpolated linearly, and a 3-layer periodic 3^3
+// CNN (1 -> 16 -> 16 -> 1 channels, SiLU) on the filtered potential scaled by
+// 1 / D(a); the force is minus the spectral gradient of phi_f + D(a) cnn.
+// Parameters: one flat FP32 array (offsets in pm_internal.h).  The CNN takes
+// BF16 activations and weights and accumulates in FP32; the 16 -> 16 layer,
+// 89 % of the network's arithmetic, runs on MFMA (16x16x16 BF16 tiles).
+#include "pm_internal.h"
+
+namespace pm {
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536LL * 16)
+{
+    int64_t b = (n + block - 1) / block;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z)
+{
+    const float s = 1.f / (1.f + __expf(-z));
+    return s + z * s * (1.f - s);
+}
+// round to the nearest BF16 (ties to even) and back
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float bf16r(float f) { return from_bf16(to_bf16(f)); }
+
+__device__ __forceinline__ float bin_kt(int b) { return (float)b * 1.7320508075688772f / (float)(NET_NB - 1); }
+
+// ---------------------------------------------------------------- radial MLP table
+// One workgroup per bin, one thread per hidden unit.
+__global__ __launch_bounds__(128) void k_mlp_fwd(const float *__restrict__ th, float a, float *table)
+{
+    __shared__ float h[NET_H], red[128];
+    const int b = blockIdx.x, j = threadIdx.x;
+    const float kt = bin_kt(b);
+    float z = 0.f;
+    if (j < NET_H) h[j] = silu(th[NB0 + j] + th[NW0 + 2 * j] * kt + th[NW0 + 2 * j + 1] * a);
+    __syncthreads();
+#pragma unroll 1
+    for (int l = 0; l < 2; l++) {
+        const int W = l == 0 ? NW1 : NW2, B = l == 0 ? NB1 : NB2;
+        if (j < NET_H) {
+            z = th[B + j];
+            for (int i = 0; i < NET_H; i++) z += th[W + j * NET_H + i] * h[i];
+        }
+        __syncthreads();
+        if (j < NET_H) h[j] = silu(z);
+        __syncthreads();
+    }
+    red[j] = j < NET_H ? th[NW3 + j] * h[j] : 0.f;
+    __syncthreads();
+    for (int s = 64; s >= 1; s >>= 1) {
+        if (j < s) red[j] += red[j + s];
+        __syncthreads();
+    }
+    if (j == 0) table[b] = 1.f + th[NB3] + red[0];
+}
+
+// dth += tbar[b] d table[b] / d th (float atomics across bins).
+__global__ __launch_bounds__(128) void k_mlp_bwd(const float *__restrict__ th, float a, const double *tbar,
+                                                 float *dth)
+{
+    __shared__ float h0[NET_H], h1[NET_H], h2[NET_H], dd[NET_H];
+    const int b = blockIdx.x, j = threadIdx.x;
+    const float g = (float)tbar[b];
+    if (g == 0.f) return;   // uniform over the workgroup
+    const float kt = bin_kt(b);
+    float z0 = 0.f, z1 = 0.f, z2 = 0.f;
+    if (j < NET_H) {
+        z0 = th[NB0 + j] + th[NW0 + 2 * j] * kt + th[NW0 + 2 * j + 1] * a;
+        h0[j] = silu(z0);
+    }
+    __syncthreads();
+    if (j < NET_H) {
+        z1 = th[NB1 + j];
+        for (int i = 0; i < NET_H; i++) z1 += th[NW1 + j * NET_H + i] * h0[i];
+        h1[j] = silu(z1);
+    }
+    __syncthreads();
+    if (j < NET_H) {
+        z2 = th[NB2 + j];
+        for (int i = 0; i < NET_H; i++) z2 += th[NW2 + j * NET_H + i] * h1[i];
+        h2[j] = silu(z2);
+    }
+    __syncthreads();
+    if (j == 0) atomicAdd(dth + NB3, g);
+    if (j < NET_H) {
+        atomicAdd(dth + NW3 + j, g * h2[j]);
+        dd[j] = g * th[NW3 + j] * dsilu(z2);
+    }
+    __syncthreads();
+    float d = 0.f;
+    if (j < NET_H) {
+        atomicAdd(dth + NB2 + j, dd[j]);
+        for (int i = 0; i < NET_H; i++) atomicAdd(dth + NW2 + j * NET_H + i, dd[j] * h1[i]);
+        for (int k = 0; k < NET_H; k++) d += dd[k] * th[NW2 + k * NET_H + j];
+        d *= dsilu(z1);
+    }
+    __syncthreads();
+    if (j < NET_H) dd[j] = d;
+    __syncthreads();
+    d = 0.f;
+    if (j < NET_H) {
+        atomicAdd(dth + NB1 + j, dd[j]);
+        for (int i = 0; i < NET_H; i++) atomicAdd(dth + NW1 + j * NET_H + i, dd[j] * h0[i]);
+        for (int k = 0; k < NET_H; k++) d += dd[k] * th[NW1 + k * NET_H + j];
+        d *= dsilu(z0);
+        atomicAdd(dth + NB0 + j, d);
+        atomicAdd(dth + NW0 + 2 * j, d * kt);
+        atomicAdd(dth + NW0 + 2 * j + 1, d * a);
+    }
+}
+
+// ---------------------------------------------------------------- spectral parts
+// Natural-order half spectra [n][n][nhp]; mode t -> wave vector in grid units.
+struct Mode {
+    float k0, k1, k2, kk;
+    bool pad, nyq0, nyq1, nyq2;
+    int kz;
+};
+__device__ __forceinline__ Mode mode_of(int64_t t, int64_t nhp, int n)
+{
+    Mode m;
+    const int kz = (int)(t % nhp);
+    const int64_t r = t / nhp;
+    const int i1 = (int)(r % n), i0 = (int)(r / n);
+    const float sc = 6.28318530717958648f / (float)n;
+    m.k0 = sc * (i0 <= n / 2 ? i0 : i0 - n);
+    m.k1 = sc * (i1 <= n / 2 ? i1 : i1 - n);
+    m.k2 = sc * kz;
+    m.kk = m.k0 * m.k0 + m.k1 * m.k1 + m.k2 * m.k2;
+    m.pad = kz > n / 2;
+    m.nyq0 = i0 == n / 2;
+    m.nyq1 = i1 == n / 2;
+    m.nyq2 = kz == n / 2;
+    m.kz = kz;
+    return m;
+}
+
+__device__ __forceinline__ float table_at(const float *table, float kt, int &b, float &w)
+{
+    const float tt = kt * (float)(NET_NB - 1) / 1.7320508075688772f;
+    b = (int)floorf(tt);
+    if (b > NET_NB - 2) b = NET_NB - 2;
+    w = tt - (float)b;
+    return (1.f - w) * table[b] + w * table[b + 1];
+}
+
+// out = g(|k|) coef / k^2 in (k = 0 and padding -> 0).
+__global__ void k_spec_filter(const float2 *in, float2 *out, int64_t nhp, int n, const float *table, float coef)
+{
+    __shared__ float tab[NET_NB];
+    for (int i = threadIdx.x; i < NET_NB; i += blockDim.x) tab[i] = table[i];
+    __syncthreads();
+    const int64_t tot = (int64_t)n * n * nhp;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const Mode m = mode_of(t, nhp, n);
+        float2 o = make_float2(0.f, 0.f);
+        if (!m.pad && m.kk > 0.f) {
+            int b;
+            float w;
+            const float g = table_at(tab, sqrtf(m.kk) * 0.31830988618379067f, b, w) * coef / m.kk;
+            const float2 v = in[t];
+            o = make_float2(g * v.x, g * v.y);
+        }
+        out[t] = o;
+    }
+}
+
+// tbar[b] += sum over modes of the bin weights times Re[coef / k^2 dk conj(pf)],
+// each half-spectrum mode standing for its conjugate too (weight 2) except on
+// the planes kz = 0 and kz = n/2.
+__global__ __launch_bounds__(256) void k_spec_filter_bwd(const float2 *dk, const float2 *pf, int64_t nhp, int n,
+                                                         float coef, double *tbar)
+{
+    __shared__ double hist[NET_NB];
+    for (int i = threadIdx.x; i < NET_NB; i += blockDim.x) hist[i] = 0.0;
+    __syncthreads();
+    const int64_t tot = (int64_t)n * n * nhp;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const Mode m = mode_of(t, nhp, n);
+        if (m.pad || m.kk == 0.f) continue;
+        const float2 a = dk[t], c = pf[t];
+        const float mult = (m.kz == 0 || m.nyq2) ? 1.f : 2.f;
+        const float dg = mult * coef / m.kk * (a.x * c.x + a.y * c.y);
+        int b;
+        float w;
+        const float kt = sqrtf(m.kk) * 0.31830988618379067f;
+        const float tt = kt * (float)(NET_NB - 1) / 1.7320508075688772f;
+        b = (int)floorf(tt);
+        if (b > NET_NB - 2) b = NET_NB - 2;
+        w = tt - (float)b;
+        atomicAdd(&hist[b], (double)((1.f - w) * dg));
+        atomicAdd(&hist[b + 1], (double)(w * dg));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NET_NB; i += blockDim.x)
+        if (hist[i] != 0.0) atomicAdd(tbar + i, hist[i]);
+}
+
+// F_d = -i k_d phi scale (field 0 holds phi on entry; fields fs apart).
+__global__ void k_grad3(float2 *F, int64_t nhp, int64_t fs, int n, float scale)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const Mode m = mode_of(t, nhp, n);
+        const float2 v = F[t];
+        const float f0 = (m.pad || m.nyq0) ? 0.f : m.k0 * scale, f1 = (m.pad || m.nyq1) ? 0.f : m.k1 * scale,
+                    f2 = (m.pad || m.nyq2) ? 0.f : m.k2 * scale;
+        F[t] = make_float2(f0 * v.y, -f0 * v.x);
+        F[fs + t] = make_float2(f1 * v.y, -f1 * v.x);
+        F[2 * fs + t] = make_float2(f2 * v.y, -f2 * v.x);
+    }
+}
+
+// Transpose: phibar = sum_d i k_d Fbar_d scale into field 0.
+__global__ void k_grad3_t(float2 *F, int64_t nhp, int64_t fs, int n, float scale)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const Mode m = mode_of(t, nhp, n);
+        const float f0 = (m.pad || m.nyq0) ? 0.f : m.k0 * scale, f1 = (m.pad || m.nyq1) ? 0.f : m.k1 * scale,
+                    f2 = (m.pad || m.nyq2) ? 0.f : m.k2 * scale;
+        const float2 a = F[t], b = F[fs + t], c = F[2 * fs + t];
+        const float sx = f0 * a.x + f1 * b.x + f2 * c.x, sy = f0 * a.y + f1 * b.y + f2 * c.y;
+        F[t] = make_float2(-sy, sx);
+    }
+}
+
+// ---------------------------------------------------------------- convolutions
+// Voxel v = (i0 n + i1) n + i2; tap t = (t0 3 + t1) 3 + t2, offset t_e - 1.
+__device__ __forceinline__ int64_t nb_voxel(int i0, int i1, int i2, int t, int n)
+{
+    const int m = n - 1;
+    return ((int64_t)((i0 + t / 9 - 1) & m) * n + ((i1 + (t / 3) % 3 - 1) & m)) * n + ((i2 + t % 3 - 1) & m);
+}
+
+// conv1: psi = s phi_f (real rows of stride rs) rounded to BF16 -> z1 (FP32),
+// a1 = SiLU(z1) (BF16), 16 channels per voxel.
+__global__ __launch_bounds__(256) void k_conv1_fwd(const float *__restrict__ phif, int64_t rs, int n, float s,
+                                                   const float *__restrict__ th, float *z1, uint16_t *a1)
+{
+    __shared__ float W[NET_C * 27], B[NET_C];
+    for (int i = threadIdx.x; i < NET_C * 27; i += blockDim.x) W[i] = bf16r(th[NC1W + i]);
+    if (threadIdx.x < NET_C) B[threadIdx.x] = th[NC1B + threadIdx.x];
+    __syncthreads();
+    const int64_t M = (int64_t)n * n * n;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < M; v += (int64_t)gridDim.x * blockDim.x) {
+        const int i2 = (int)(v % n), i1 = (int)((v / n) % n), i0 = (int)(v / ((int64_t)n * n));
+        float x[27];
+#pragma unroll
+        for (int t = 0; t < 27; t++) {
+            const int64_t u = nb_voxel(i0, i1, i2, t, n);
+            x[t] = bf16r(s * phif[(u / n) * rs + u % n]);
+        }
+        float z[NET_C];
+#pragma unroll
+        for (int co = 0; co < NET_C; co++) {
+            float acc = B[co];
+#pragma unroll
+            for (int t = 0; t < 27; t++) acc += W[co * 27 + t] * x[t];
+            z[co] = acc;
+        }
+#pragma unroll
+        for (int co = 0; co < NET_C; co += 4) {
+            *reinterpret_cast<float4 *>(z1 + v * NET_C + co) = make_float4(z[co], z[co + 1], z[co + 2], z[co + 3]);
+            const uint32_t lo = (uint32_t)to_bf16(silu(z[co])) | ((uint32_t)to_bf16(silu(z[co + 1])) << 16);
+            const uint32_t hi = (uint32_t)to_bf16(silu(z[co + 2])) | ((uint32_t)to_bf16(silu(z[co + 3])) << 16);
+            *reinterpret_cast<uint2 *>(a1 + v * NET_C + co) = make_uint2(lo, hi);
+        }
+    }
+}
+
+// conv2 (16 -> 16) on MFMA.  Workgroup tile: 16 (axis 2) x 8 (axis 1) x 4
+// (axis 0) voxels with its one-voxel halo in LDS as BF16 [z][y][x][16]; the
+// weights as BF16 [tap][co][ci].  Per 16-voxel row and tap one
+// v_mfma_f32_16x16x16_bf16: D[co][vox] += W_t[co][ci] X_t[ci][vox] (lane l
+// holds A[co = l % 16][ci = 4 (l / 16) + r], B[ci = 4 (l / 16) + r][vox = l % 16]
+// and D[co = 4 (l / 16) + r][vox = l % 16]).
+constexpr int C2X = 16, C2Y = 8, C2Z = 4, C2HX = C2X + 2, C2HY = C2Y + 2, C2HZ = C2Z + 2;
+constexpr int C2HALO = C2HX * C2HY * C2HZ;
+
+__global__ __launch_bounds__(256) void k_conv2_fwd(const uint16_t *__restrict__ a1, int n,
+                                                   const float *__restrict__ th, float *z2, uint16_t *a2)
+{
+    __shared__ __align__(16) uint16_t X[C2HALO * NET_C];
+    __shared__ __align__(16) uint16_t W[27 * NET_C * NET_C];
+    __shared__ float B[NET_C];
+    const int tid = threadIdx.x;
+    const int ntx = n / C2X, nty = n / C2Y;
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int x0 = tx * C2X, y0 = ty * C2Y, z0 = tz * C2Z, m = n - 1;
+    // weights [co][ci][t] (FP32) -> LDS [t][co][ci] (BF16)
+    for (int e = tid; e < 27 * NET_C * NET_C; e += 256) {
+        const int t = e / (NET_C * NET_C), co = (e / NET_C) % NET_C, ci = e % NET_C;
+        W[e] = to_bf16(th[NC2W + (co * NET_C + ci) * 27 + t]);
+    }
+    if (tid < NET_C) B[tid] = th[NC2B + tid];
+    // halo tile: two 16-byte chunks per voxel
+    for (int e = tid; e < C2HALO * 2; e += 256) {
+        const int hv = e >> 1, half = e & 1;
+        const int hx = hv % C2HX, hy = (hv / C2HX) % C2HY, hz = hv / (C2HX * C2HY);
+        const int64_t g = ((int64_t)((z0 + hz - 1) & m) * n + ((y0 + hy - 1) & m)) * n + ((x0 + hx - 1) & m);
+        reinterpret_cast<uint4 *>(X)[hv * 2 + half] = reinterpret_cast<const uint4 *>(a1 + g * NET_C)[half];
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, kg = lane >> 4;   // voxel within the row / co and ci group
+    for (int row = wave; row < C2Y * C2Z; row += 4) {
+        const int ry = row % C2Y, rz = row / C2Y;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+        for (int t = 0; t < 27; t++) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const v4s wa = *reinterpret_cast<const v4s *>(W + (t * NET_C + col) * NET_C + 4 * kg);
+            const int hv = ((rz + dz) * C2HY + (ry + dy)) * C2HX + (col + dx);
+            const v4s xb = *reinterpret_cast<const v4s *>(X + hv * NET_C + 4 * kg);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa, xb, acc, 0, 0, 0);
+        }
+        // lane holds D[co = 4 kg + r][vox = col]
+        const int64_t v = ((int64_t)(z0 + rz) * n + (y0 + ry)) * n + (x0 + col);
+        float zz[4];
+        uint16_t aa[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            zz[r] = acc[r] + B[4 * kg + r];
+            aa[r] = to_bf16(silu(zz[r]));
+        }
+        *reinterpret_cast<float4 *>(z2 + v * NET_C + 4 * kg) = make_float4(zz[0], zz[1], zz[2], zz[3]);
+        *reinterpret_cast<uint2 *>(a2 + v * NET_C + 4 * kg) =
+            make_uint2((uint32_t)aa[0] | ((uint32_t)aa[1] << 16), (uint32_t)aa[2] | ((uint32_t)aa[3] << 16));
+    }
+}
+
+// conv3 (16 -> 1): out(v) = b + sum_{ci,t} W[ci][t] a2[v + o(t)][ci].
+__global__ __launch_bounds__(256) void k_conv3_fwd(const uint16_t *__restrict__ a2, int n,
+                                                   const float *__restrict__ th, float *out)
+{
+    __shared__ float W[27 * NET_C];   // [t][ci]
+    for (int e = threadIdx.x; e < 27 * NET_C; e += blockDim.x) {
+        const int t = e / NET_C, ci = e % NET_C;
+        W[e] = bf16r(th[NC3W + ci * 27 + t]);
+    }
+    __syncthreads();
+    const float b = th[NC3B];
+    const int64_t M = (int64_t)n * n * n;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < M; v += (int64_t)gridDim.x * blockDim.x) {
+        const int i2 = (int)(v % n), i1 = (int)((v / n) % n), i0 = (int)(v / ((int64_t)n * n));
+        float acc = b;
+        for (int t = 0; t < 27; t++) {
+            const int64_t u = nb_voxel(i0, i1, i2, t, n);
+            const uint4 *p = reinterpret_cast<const uint4 *>(a2 + u * NET_C);
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const uint4 q = p[h];
+                const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int ci = h * 8 + 2 * k;
+                    acc += W[t * NET_C + ci] * from_bf16((uint16_t)(w4[k] & 0xffff)) +
+                           W[t * NET_C + ci + 1] * from_bf16((uint16_t)(w4[k] >> 16));
+                }
+            }
+        }
+        out[v] = acc;
+    }
+}
+
+// phi = phi_f + D(a) dpsi on real rows of stride rs.
+__global__ void k_combine(const float *phif, const float *dpsi, int64_t rs, int n, float Da, float *out)
+{
+    const int64_t M = (int64_t)n * n * n;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < M; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = (v / n) * rs + v % n;
+        out[o] = phif[o] + Da * dpsi[v];
+    }
+}
+
+// ---- reverse mode of the CNN
+// conv3 data: g2[v][ci] = dsilu(z2[v][ci]) sum_t W3[ci][t] dout(v - o(t)),
+// dout = D(a) phibar on real rows of stride rs.
+__global__ __launch_bounds__(256) void k_conv3_bwd_data(const float *__restrict__ phibar, int64_t rs, int n,
+                                                        float Da, const float *__restrict__ th,
+                                                        const float *__restrict__ z2, float *g2)
+{
+    __shared__ float W[27 * NET_C];   // [t][ci]
+    for (int e = threadIdx.x; e < 27 * NET_C; e += blockDim.x) {
+        const int t = e / NET_C, ci = e % NET_C;
+        W[e] = bf16r(th[NC3W + ci * 27 + t]);
+    }
+    __syncthreads();
+    const int64_t M = (int64_t)n * n * n;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < M; v += (int64_t)gridDim.x * blockDim.x) {
+        const int i2 = (int)(v % n), i1 = (int)((v / n) % n), i0 = (int)(v / ((int64_t)n * n));
+        float acc[NET_C];
+#pragma unroll
+        for (int c = 0; c < NET_C; c++) acc[c] = 0.f;
+        for (int t = 0; t < 27; t++) {
+            const int64_t u = nb_voxel(i0, i1, i2, 26 - t, n);   // v - o(t)
+            const float d = Da * phibar[(u / n) * rs + u % n];
+#pragma unroll
+            for (int c = 0; c < NET_C; c++) acc[c] += W[t * NET_C + c] * d;
+        }
+#pragma unroll
+        for (int c = 0; c < NET_C; c += 4) {
+            const float4 z = *reinterpret_cast<const float4 *>(z2 + v * NET_C + c);
+            *reinterpret_cast<float4 *>(g2 + v * NET_C + c) =
+                make_float4(acc[c] * dsilu(z.x), acc[c + 1] * dsilu(z.y), acc[c + 2] * dsilu(z.z),
+                            acc[c + 3] * dsilu(z.w));
+        }
+    }
+}
+
+// conv2 data: g1[v][ci] = dsilu(z1[v][ci]) sum_{co,t} W2[co][ci][t] g2[v - o(t)][co].
+__global__ __launch_bounds__(256) void k_conv2_bwd_data(const float *__restrict__ g2, int n,
+                                                        const float *__restrict__ th,
+                                                        const float *__restrict__ z1, float *g1)
+{
+    __shared__ float W[27 * NET_C * NET_C];   // [t][co][ci]
+    for (int e = threadIdx.x; e < 27 * NET_C * NET_C; e += blockDim.x) {
+        const int t = e / (NET_C * NET_C), co = (e / NET_C) % NET_C, ci = e % NET_C;
+        W[e] = bf16r(th[NC2W + (co * NET_C + ci) * 27 + t]);
+    }
+    __syncthreads();
+    const int64_t M = (int64_t)n * n * n;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < M; v += (int64_t)gridDim.x * blockDim.x) {
+        const int i2 = (int)(v % n), i1 = (int)((v / n) % n), i0 = (int)(v / ((int64_t)n * n));
+        float acc[NET_C];
+#pragma unroll
+        for (int c = 0; c < NET_C; c++) acc[c] = 0.f;
+        for (int t = 0; t < 27; t++) {
+            const int64_t u = nb_voxel(i0, i1, i2, 26 - t, n);
+            const float4 *gp = reinterpret_cast<const float4 *>(g2 + u * NET_C);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float4 gv = gp[q];
+                const float gg[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int co = 4 * q + r;
+#pragma unroll
+                    for (int c = 0; c < NET_C; c++) acc[c] += W[(t * NET_C + co) * NET_C + c] * gg[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NET_C; c += 4) {
+            const float4 z = *reinterpret_cast<const float4 *>(z1 + v * NET_C + c);
+            *reinterpret_cast<float4 *>(g1 + v * NET_C + c) =
+                make_float4(acc[c] * dsilu(z.x), acc[c + 1] * dsilu(z.y), acc[c + 2] * dsilu(z.z),
+                            acc[c + 3] * dsilu(z.w));
+        }
+    }
+}
+
+// conv1 data: phibar_f(v) += s sum_{co,t} W1[co][t] g1[v - o(t)][co] on real rows.
+__global__ __launch_bounds__(256) void k_conv1_bwd_data(const float *__restrict__ g1, int n,
+                                                        const float *__restrict__ th, float s, float *phibar,
+                                                        int64_t rs)
+{
+    __shared__ float W[27 * NET_C];   // [t][co]
+    for (int e = threadIdx.x; e < 27 * NET_C; e += blockDim.x) {
+        const int t = e / NET_C, co = e % NET_C;
+        W[e] = bf16r(th[NC1W + co * 27 + t]);
+    }
+    __syncthreads();
+    const int64_t M = (int64_t)n * n * n;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < M; v += (int64_t)gridDim.x * blockDim.x) {
+        const int i2 = (int)(v % n), i1 = (int)((v / n) % n), i0 = (int)(v / ((int64_t)n * n));
+        float acc = 0.f;
+        for (int t = 0; t < 27; t++) {
+            const int64_t u = nb_voxel(i0, i1, i2, 26 - t, n);
+            const float4 *gp = reinterpret_cast<const float4 *>(g1 + u * NET_C);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float4 gv = gp[q];
+                acc += W[t * NET_C + 4 * q] * gv.x + W[t * NET_C + 4 * q + 1] * gv.y +
+                       W[t * NET_C + 4 * q + 2] * gv.z + W[t * NET_C + 4 * q + 3] * gv.w;
+            }
+        }
+        phibar[(v / n) * rs + v % n] += s * acc;
+    }
+}
+
+// Weight gradients dW[co][ci][t] += sum_v in_ci(v + o(t)) dout_co(v), db[co] += sum_v dout_co(v).
+// in: KIN 0 = real rows (stride rs, times s, rounded to BF16: the conv1 input),
+//     KIN 1 = BF16 [v][16]; dout: KOUT 0 = real rows times s_out (conv3), KOUT 1 = FP32 [v][16].
+// A workgroup walks tiles of 16 x 8 x 4 voxels with LDS copies of the input
+// halo and the output gradient; each thread owns CO CI 27 / 256 entries.
+template <int CI, int CO, int KIN, int KOUT>
+__global__ __launch_bounds__(256) void k_conv_bwd_w(const void *in_, int64_t rs_in, float s_in, const void *dout_,
+                                                    int64_t rs_out, float s_out, int n, float *dW, float *db)
+{
+    constexpr int NE = CO * CI * 27, PER = (NE + 255) / 256;
+    __shared__ float Xs[C2HALO * CI];
+    __shared__ float Gs[C2X * C2Y * C2Z * CO];
+    const int tid = threadIdx.x, m = n - 1;
+    const int ntx = n / C2X, nty = n / C2Y, ntz = n / C2Z, ntiles = ntx * nty * ntz;
+    float acc[PER], bacc = 0.f;
+#pragma unroll
+    for (int k = 0; k < PER; k++) acc[k] = 0.f;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+        const int x0 = tx * C2X, y0 = ty * C2Y, z0 = tz * C2Z;
+        __syncthreads();
+        for (int e = tid; e < C2HALO * CI; e += 256) {
+            const int hv = e / CI, ci = e % CI;
+            const int hx = hv % C2HX, hy = (hv / C2HX) % C2HY, hz = hv / (C2HX * C2HY);
+            const int64_t g = ((int64_t)((z0 + hz - 1) & m) * n + ((y0 + hy - 1) & m)) * n + ((x0 + hx - 1) & m);
+            float val;
+            if constexpr (KIN == 0)
+                val = bf16r(s_in * reinterpret_cast<const float *>(in_)[(g / n) * rs_in + g % n]);
+            else
+                val = from_bf16(reinterpret_cast<const uint16_t *>(in_)[g * CI + ci]);
+            Xs[e] = val;
+        }
+        for (int e = tid; e < C2X * C2Y * C2Z * CO; e += 256) {
+            const int lv = e / CO, co = e % CO;
+            const int lx = lv % C2X, ly = (lv / C2X) % C2Y, lz = lv / (C2X * C2Y);
+            const int64_t g = ((int64_t)(z0 + lz) * n + (y0 + ly)) * n + (x0 + lx);
+            float val;
+            if constexpr (KOUT == 0)
+                val = s_out * reinterpret_cast<const float *>(dout_)[(g / n) * rs_out + g % n];
+            else
+                val = reinterpret_cast<const float *>(dout_)[g * CO + co];
+            Gs[e] = val;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int e = tid + 256 * k;
+            if (e < NE) {
+                const int co = e / (CI * 27), ci = (e / 27) % CI, t = e % 27;
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                float s = 0.f;
+                for (int lz = 0; lz < C2Z; lz++)
+                    for (int ly = 0; ly < C2Y; ly++)
+                        for (int lx = 0; lx < C2X; lx++) {
+                            const int hv = ((lz + dz) * C2HY + (ly + dy)) * C2HX + (lx + dx);
+                            const int lv = (lz * C2Y + ly) * C2X + lx;
+                            s += Xs[hv * CI + ci] * Gs[lv * CO + co];
+                        }
+                acc[k] += s;
+            }
+        }
+        if (tid < CO) {
+            float s = 0.f;
+            for (int lv = 0; lv < C2X * C2Y * C2Z; lv++) s += Gs[lv * CO + tid];
+            bacc += s;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const int e = tid + 256 * k;
+        if (e < NE) atomicAdd(dW + e, acc[k]);
+    }
+    if (tid < CO) atomicAdd(db + tid, bacc);
+}
+
+// ---- loss and optimiser
+// red[0] += sum (acc - target)^2, red[1] += sum target^2; acc -= target.
+__global__ __launch_bounds__(256) void k_force_loss(float *acc, const float *target, int64_t n3, double *red)
+{
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = acc[i] - target[i];
+        a += (double)d * d;
+        b += (double)target[i] * target[i];
+        acc[i] = d;
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(red, sa[0]);
+        atomicAdd(red + 1, sb[0]);
+    }
+}
+
+// Adam with bias correction (FP32 master weights).
+__global__ void k_adam(float *th, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void k_zero_f64(double *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_mlp_fwd(const float *th, double a, float *table, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(NET_NB), dim3(128), 0, s, th, (float)a, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_bwd(const float *th, double a, const double *tbar, float *dth, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(NET_NB), dim3(128), 0, s, th, (float)a, tbar, dth);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_filter(const float2 *in, float2 *out, int64_t nhp, int n, const float *table, double coef,
+                              hipStream_t s)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    hipLaunchKernelGGL(k_spec_filter, dim3(grid_for(tot, 256, 4096)), dim3(256), 0, s, in, out, nhp, n, table,
+                       (float)coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_filter_bwd(const float2 *dk, const float2 *pf, int64_t nhp, int n, double coef, double *tbar,
+                                  hipStream_t s)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, tbar, NET_NB);
+    hipLaunchKernelGGL(k_spec_filter_bwd, dim3(grid_for(tot, 256, 1024)), dim3(256), 0, s, dk, pf, nhp, n,
+                       (float)coef, tbar);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad3(float2 *F, int64_t nhp, int64_t fs, int n, double scale, bool transpose, hipStream_t s)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    if (transpose)
+        hipLaunchKernelGGL(k_grad3_t, dim3(grid_for(tot, 256)), dim3(256), 0, s, F, nhp, fs, n, (float)scale);
+    else
+        hipLaunchKernelGGL(k_grad3, dim3(grid_for(tot, 256)), dim3(256), 0, s, F, nhp, fs, n, (float)scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_fwd(const float *phif, int64_t rs, int n, double inv_Da, const float *th, float *z1,
+                          uint16_t *a1, float *z2, uint16_t *a2, float *dpsi, hipStream_t s)
+{
+    if (n < C2X || n % C2X) return hipErrorInvalidValue;
+    const int64_t M = (int64_t)n * n * n;
+    hipLaunchKernelGGL(k_conv1_fwd, dim3(grid_for(M, 256)), dim3(256), 0, s, phif, rs, n, (float)inv_Da, th, z1, a1);
+    hipLaunchKernelGGL(k_conv2_fwd, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, a1, n, th, z2, a2);
+    hipLaunchKernelGGL(k_conv3_fwd, dim3(grid_for(M, 256)), dim3(256), 0, s, a2, n, th, dpsi);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int n, double Da, float *out,
+                          hipStream_t s)
+{
+    const int64_t M = (int64_t)n * n * n;
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(M, 256)), dim3(256), 0, s, phif, dpsi, rs, n, (float)Da, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_bwd(const float *phif, const float *phibar, int64_t rs, int n, double Da, const float *th,
+                          const float *z1, const uint16_t *a1, const float *z2, const uint16_t *a2, float *g1,
+                          float *g2, float *phibar_f, float *dth, hipStream_t s)
+{
+    if (n < C2X || n % C2X) return hipErrorInvalidValue;
+    const int64_t M = (int64_t)n * n * n;
+    const int ntiles = (int)(M / (C2X * C2Y * C2Z));
+    const unsigned gw = (unsigned)(ntiles < 2048 ? ntiles : 2048);
+    const float fDa = (float)Da, inv = (float)(1.0 / Da);
+    // conv3: dW3, db3 from a2 and D(a) phibar; g2 = dsilu(z2) W3^T dout
+    hipLaunchKernelGGL((k_conv_bwd_w<NET_C, 1, 1, 0>), dim3(gw), dim3(256), 0, s, (const void *)a2, (int64_t)0, 1.f,
+                       (const void *)phibar, rs, fDa, n, dth + NC3W, dth + NC3B);
+    hipLaunchKernelGGL(k_conv3_bwd_data, dim3(grid_for(M, 256)), dim3(256), 0, s, phibar, rs, n, fDa, th, z2, g2);
+    // conv2
+    hipLaunchKernelGGL((k_conv_bwd_w<NET_C, NET_C, 1, 1>), dim3(gw), dim3(256), 0, s, (const void *)a1, (int64_t)0,
+                       1.f, (const void *)g2, (int64_t)0, 1.f, n, dth + NC2W, dth + NC2B);
+    hipLaunchKernelGGL(k_conv2_bwd_data, dim3(grid_for(M, 256)), dim3(256), 0, s, g2, n, th, z1, g1);
+    // conv1: input psi = phif / D(a)
+    hipLaunchKernelGGL((k_conv_bwd_w<1, NET_C, 0, 1>), dim3(gw), dim3(256), 0, s, (const void *)phif, rs, inv,
+                       (const void *)g1, (int64_t)0, 1.f, n, dth + NC1W, dth + NC1B);
+    hipLaunchKernelGGL(k_conv1_bwd_data, dim3(grid_for(M, 256)), dim3(256), 0, s, g1, n, th, inv, phibar_f, rs);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_loss(float *acc, const float *target, int64_t n3, double *red, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, red, 2);
+    hipLaunchKernelGGL(k_force_loss, dim3(grid_for(n3, 256, 2048)), dim3(256), 0, s, acc, target, n3, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t n, double lr, double b1, double b2,
+                       double eps, int t, hipStream_t s)
+{
+    const float c1 = (float)(1.0 - pow(b1, t)), c2 = (float)(1.0 - pow(b2, t));
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n, 256)), dim3(256), 0, s, th, m, v, g, n, (float)lr, (float)b1,
+                       (float)b2, (float)eps, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace pm

@@ -75,13 +75,32 @@ struct Workspace {
     int *cnt = nullptr;          // counts per key (K + 1)
     int *koff = nullptr;         // exclusive offsets per key (K + 1)
     int *bsum = nullptr;         // scan block sums
+    // learned force correction (PM_FLAG_LEARNED)
+    float *net_phif = nullptr;   // filtered potential, real rows of stride 2 Nhp
+    float *net_z1 = nullptr, *net_z2 = nullptr;      // CNN pre-activations [N^3][16] FP32
+    uint16_t *net_a1 = nullptr, *net_a2 = nullptr;   // CNN activations [N^3][16] BF16
+    float *net_g1 = nullptr, *net_g2 = nullptr;      // reverse-mode buffers [N^3][16]
+    float *net_dpsi = nullptr;   // CNN output [N^3]
+    float2 *net_dk = nullptr;    // density spectrum kept for the reverse mode
+    float *net_acc = nullptr;    // forces on the particles [3][P]
+    float *net_table = nullptr;  // radial filter table [NET_NB]
+    double *net_tbar = nullptr;  // its cotangent [NET_NB]
+    double *net_red = nullptr;   // loss reductions [2]
 };
+
+// Learned force correction: MLP width, radial table bins, CNN channels, and
+// offsets into the flat parameter array.
+constexpr int NET_H = 96, NET_NB = 256, NET_C = 16;
+constexpr int NW0 = 0, NB0 = NW0 + NET_H * 2, NW1 = NB0 + NET_H, NB1 = NW1 + NET_H * NET_H, NW2 = NB1 + NET_H,
+              NB2 = NW2 + NET_H * NET_H, NW3 = NB2 + NET_H, NB3 = NW3 + NET_H, NC1W = NB3 + 1,
+              NC1B = NC1W + NET_C * 27, NC2W = NC1B + NET_C, NC2B = NC2W + NET_C * NET_C * 27,
+              NC3W = NC2B + NET_C, NC3B = NC3W + NET_C * 27, NET_NPARAM = NC3B + 1;
 
 // Kernel kinds recorded by the launch trace (pm_trace_begin / pm_trace_end).
 enum KernelKind {
     K_FILL = 0, K_PAINT, K_R2C, K_COLS_FWD, K_AXIS0, K_COLS_INV, K_C2R, K_READOUT_KD, K_READOUT,
     K_POWER_BIN, K_POWER_REDUCE, K_IC_PARTICLES, K_COPY, K_SORT_COUNT, K_SORT_SCAN, K_SORT_SCATTER,
-    K_X0_GREEN, K_R2C_X0, K_C2R_X0, K_ADJOINT, K_COUNT
+    K_X0_GREEN, K_R2C_X0, K_C2R_X0, K_ADJOINT, K_NET, K_COUNT
 };
 
 struct TraceRec {
@@ -185,6 +204,25 @@ hipError_t launch_ic_adj_gather_cdm(const float *xbar, const float *pbar, int64_
                                     int64_t rs, int64_t cs, hipStream_t s);
 hipError_t launch_ic_adj_gather_nu(const float *xbar, const float *pbar, int64_t P, int64_t nc, int nic, int ns,
                                    int nd, int n_shell, float vfac, float *F, int64_t rs, int64_t cs, hipStream_t s);
+
+// ---- launchers (net.hip)
+hipError_t launch_mlp_fwd(const float *th, double a, float *table, hipStream_t s);
+hipError_t launch_mlp_bwd(const float *th, double a, const double *tbar, float *dth, hipStream_t s);
+hipError_t launch_spec_filter(const float2 *in, float2 *out, int64_t nhp, int n, const float *table, double coef,
+                              hipStream_t s);
+hipError_t launch_spec_filter_bwd(const float2 *dk, const float2 *pf, int64_t nhp, int n, double coef, double *tbar,
+                                  hipStream_t s);
+hipError_t launch_grad3(float2 *F, int64_t nhp, int64_t fs, int n, double scale, bool transpose, hipStream_t s);
+hipError_t launch_cnn_fwd(const float *phif, int64_t rs, int n, double inv_Da, const float *th, float *z1,
+                          uint16_t *a1, float *z2, uint16_t *a2, float *dpsi, hipStream_t s);
+hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int n, double Da, float *out,
+                          hipStream_t s);
+hipError_t launch_cnn_bwd(const float *phif, const float *phibar, int64_t rs, int n, double Da, const float *th,
+                          const float *z1, const uint16_t *a1, const float *z2, const uint16_t *a2, float *g1,
+                          float *g2, float *phibar_f, float *dth, hipStream_t s);
+hipError_t launch_force_loss(float *acc, const float *target, int64_t n3, double *red, hipStream_t s);
+hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t n, double lr, double b1, double b2,
+                       double eps, int t, hipStream_t s);
 
 // ---- launchers (paint.hip)
 hipError_t launch_paint(const float *x, int64_t stride, int64_t first, int64_t count, int64_t quantum,

@@ -84,6 +84,12 @@ _sig("pm_density_vjp", [_vp, _vp, _vp, _vp, _vp])
 _sig("pm_force_vjp", [_vp, _vp, _vp, _vp, _vp])
 _sig("pm_step_vjp", [_vp, _vp, _dbl, _dbl, _dbl, _dbl, _vp, _vp, _vp])
 _sig("pm_ic_vjp", [_vp, _vp, _vp, _vp, _vp])
+_sig("pm_learned_force", [_vp, _vp, _dbl, _vp, _vp, _vp])
+_sig("pm_learned_step", [_vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _dbl, _vp])
+_sig("pm_learned_loss", [_vp, _vp, _dbl, _vp, _vp, C.POINTER(C.c_double), _vp, _vp])
+_sig("pm_adam", [_vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _dbl, _dbl, _i32, _vp])
+_lib.pm_net_nparam.restype = C.c_int32
+_lib.pm_net_nparam.argtypes = []
 _sig("pm_power", [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp])
 _sig("pm_trace_begin", [_vp, _i32])
 _sig("pm_attach_ids", [_vp, _vp])
@@ -97,7 +103,7 @@ EXPORTS = ["pm_sizes", "pm_init", "pm_free", "pm_last_error", "pm_segments", "pm
            "pm_kdk_factors", "pm_ic", "pm_paint_q", "pm_paint", "pm_fft_r2c", "pm_fft_c2r", "pm_force_mesh",
            "pm_force", "pm_step", "pm_power", "pm_trace_begin", "pm_trace_end", "pm_kernel_name", "pm_attach_ids",
            "pm_segment_tags", "pm_reset_order", "pm_density", "pm_density_vjp", "pm_force_vjp", "pm_step_vjp",
-           "pm_ic_vjp"]
+           "pm_ic_vjp", "pm_net_nparam", "pm_learned_force", "pm_learned_step", "pm_learned_loss", "pm_adam"]
 
 
 def _check(st):
@@ -317,4 +323,42 @@ def pm_ic_vjp(ctx, xbar, pbar, wbar, stream=None):
     _check(_lib.pm_ic_vjp(ctx.h, _dev(xbar, torch.float32, 3 * ctx.P, "xbar"),
                           _dev(pbar, torch.float32, 3 * ctx.P, "pbar"), _dev(wbar, torch.float32, nc, "wbar"),
                           _stream(stream)))
+
+
+# ---- learned force correction (PM_FLAG_LEARNED contexts)
+PM_FLAG_LEARNED = 8
+
+
+def pm_net_nparam():
+    return int(_lib.pm_net_nparam())
+
+
+def pm_learned_force(ctx, theta, a, x, acc, stream=None):
+    _check(_lib.pm_learned_force(ctx.h, _dev(theta, torch.float32, pm_net_nparam(), "theta"), float(a),
+                                 _dev(x, torch.float32, 3 * ctx.P, "x"), _dev(acc, torch.float32, 3 * ctx.P, "acc"),
+                                 _stream(stream)))
+
+
+def pm_learned_step(ctx, theta, x, p, a_force, a_kick0, a_kick1, a_drift1, stream=None):
+    _check(_lib.pm_learned_step(ctx.h, _dev(theta, torch.float32, pm_net_nparam(), "theta"),
+                                _dev(x, torch.float32, 3 * ctx.P, "x"), _dev(p, torch.float32, 3 * ctx.P, "p"),
+                                a_force, a_kick0, a_kick1, a_drift1, _stream(stream)))
+
+
+def pm_learned_loss(ctx, theta, a, x, target, dtheta=None, stream=None):
+    """Force-matching loss; dL/dtheta is accumulated into dtheta when given."""
+    loss = C.c_double()
+    _check(_lib.pm_learned_loss(ctx.h, _dev(theta, torch.float32, pm_net_nparam(), "theta"), float(a),
+                                _dev(x, torch.float32, 3 * ctx.P, "x"),
+                                _dev(target, torch.float32, 3 * ctx.P, "target"), C.byref(loss),
+                                _dev(dtheta, torch.float32, pm_net_nparam(), "dtheta") if dtheta is not None else None,
+                                _stream(stream)))
+    return loss.value
+
+
+def pm_adam(theta, m, v, g, lr, beta1, beta2, eps, t, stream=None):
+    n = theta.numel()
+    _check(_lib.pm_adam(_dev(theta, torch.float32, n, "theta"), _dev(m, torch.float32, n, "m"),
+                        _dev(v, torch.float32, n, "v"), _dev(g, torch.float32, n, "g"), n, lr, beta1, beta2, eps,
+                        int(t), _stream(stream)))
 

@@ -1,0 +1,123 @@
+"""GPU learned force correction (libpm through its C ABI) against the FP64
+oracle of the same network (net.c, pinned by finite differences).  The GPU
+CNN takes BF16 activations and weights with FP32 accumulation, so parity is
+by relative tolerance: forces <= 1e-2, loss <= 1e-2, gradients <= 2e-2
+(relative L2 per parameter block)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2007_13394_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def _params(seed, zero_out=False):
+    rng = np.random.default_rng(seed)
+    th = np.zeros(O.NET_NPARAM)
+    for k, (o, n) in O.NET_OFF.items():
+        fan = {"W0": 2, "W1": O.NET_H, "W2": O.NET_H, "W3": O.NET_H, "C1W": 27, "C2W": 27 * O.NET_C,
+               "C3W": 27 * O.NET_C}.get(k, 1)
+        s = (0.3 if k.startswith(("W", "B")) else 0.15) / np.sqrt(fan)
+        th[o:o + n] = rng.standard_normal(n) * s
+    if zero_out:
+        for k in ("W3", "B3", "C3W", "C3B"):
+            o, n = O.NET_OFF[k]
+            th[o:o + n] = 0.0
+    return th.astype(np.float32)
+
+
+def _setup(name):
+    from paper_2007_13394_amd import pm
+    cfg = I.config(name)
+    ctx = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_LEARNED | pm.PM_FLAG_NO_SORT))
+    return pm, cfg, ctx, O.make_sim(cfg)
+
+
+def test_parameter_count_matches_the_oracle():
+    from paper_2007_13394_amd import pm
+    assert pm.pm_net_nparam() == O.NET_NPARAM
+
+
+@pytest.mark.parametrize("name", ["C5_fd16", "C5_fd32"])
+def test_zero_output_layers_give_the_plain_force(dev, name):
+    pm, cfg, ctx, _ = _setup(name)
+    x32, _ = I.synthetic_state(cfg, seed=31)
+    x = torch.from_numpy(x32).to(dev)
+    th = torch.from_numpy(_params(32, zero_out=True)).to(dev)
+    acc = torch.empty_like(x)
+    pm.pm_learned_force(ctx, th, 0.5, x, acc)
+    ref = torch.empty_like(x)
+    pm.pm_force(ctx, x, ref)
+    e = rel_l2(acc.cpu().numpy(), ref.cpu().numpy())
+    say(name, "learned (zero output layers) vs plain force rel L2", e)
+    assert e < 1e-5
+
+
+@pytest.mark.parametrize("name", ["C5_fd16", "C5_fd32"])
+def test_learned_force_vs_oracle(dev, name):
+    pm, cfg, ctx, sim = _setup(name)
+    x32, _ = I.synthetic_state(cfg, seed=33)
+    th32 = _params(34)
+    x = torch.from_numpy(x32).to(dev)
+    acc = torch.empty_like(x)
+    pm.pm_learned_force(ctx, torch.from_numpy(th32).to(dev), 0.6, x, acc)
+    ref = O.learned_force(sim, th32.astype(np.float64), 0.6, x32.astype(np.float64))
+    plain = O.force_cont(sim, x32.astype(np.float64))
+    e = rel_l2(acc.cpu().numpy(), ref)
+    say(name, "learned force rel L2", e, "(correction vs plain:", rel_l2(ref, plain), ")")
+    assert rel_l2(ref, plain) > 0.05     # the network does change the force
+    assert e < 1e-2
+
+
+@pytest.mark.parametrize("name", ["C5_fd16", "C5_fd32"])
+def test_learned_loss_and_gradient_vs_oracle(dev, name):
+    pm, cfg, ctx, sim = _setup(name)
+    x32, _ = I.synthetic_state(cfg, seed=35)
+    th32 = _params(36)
+    rng = np.random.default_rng(37)
+    target32 = (O.force_cont(sim, x32.astype(np.float64)) * (1 + 0.2 * rng.standard_normal(x32.shape))).astype(
+        np.float32)
+    x = torch.from_numpy(x32).to(dev)
+    th = torch.from_numpy(th32).to(dev)
+    d = torch.zeros_like(th)
+    loss = pm.pm_learned_loss(ctx, th, 0.6, x, torch.from_numpy(target32).to(dev), d)
+    rloss, rd = O.learned_loss(sim, th32.astype(np.float64), 0.6, x32.astype(np.float64),
+                               target32.astype(np.float64))
+    gd = d.cpu().numpy()
+    say(name, "loss", loss, "oracle", rloss)
+    assert abs(loss - rloss) / rloss < 1e-2
+    for blk in (("W0", "B0", "W1", "B1", "W2", "B2", "W3", "B3"), ("C1W", "C1B"), ("C2W", "C2B"), ("C3W", "C3B")):
+        idx = np.concatenate([np.arange(O.NET_OFF[k][0], O.NET_OFF[k][0] + O.NET_OFF[k][1]) for k in blk])
+        e = rel_l2(gd[idx], rd[idx])
+        say(name, "gradient block", blk[0], "rel L2", e)
+        assert e < 2e-2
+
+
+def test_adam_step_matches_definition(dev):
+    from paper_2007_13394_amd import pm
+    rng = np.random.default_rng(38)
+    n = 1000
+    th, m, v, g = (rng.standard_normal(n).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    t = 3
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    T = [torch.from_numpy(a.copy()).to(dev) for a in (th, m, v, g)]
+    pm.pm_adam(*T, lr, b1, b2, eps, t)
+    m1 = b1 * m + (1 - b1) * g
+    v1 = b2 * v + (1 - b2) * g * g
+    th1 = th - lr * (m1 / (1 - b1 ** t)) / (np.sqrt(v1 / (1 - b2 ** t)) + eps)
+    assert np.allclose(T[0].cpu().numpy(), th1, rtol=1e-5, atol=1e-6)

@@ -121,7 +121,15 @@ def test_learned_loss_gradient_finite_differences(name):
     a = 0.6
     loss, d = O.learned_loss(sim, th, a, x, target)
     assert loss > 0
-    h = 1e-6
+    # Richardson-extrapolated central differences: O(h^4) truncation, and a
+    # step large enough that the loss's roundoff stays ~1e-9 relative
+    h = 1e-5
+
+    def cd(v, hh):
+        lp, _ = O.learned_loss(sim, th + hh * v, a, x, target, grad=False)
+        lm, _ = O.learned_loss(sim, th - hh * v, a, x, target, grad=False)
+        return (lp - lm) / (2 * hh)
+
     for part in ("W1", "C2W", "B0", "C1W", "C3W", None):
         v = np.zeros_like(th)
         if part is None:
@@ -129,7 +137,5 @@ def test_learned_loss_gradient_finite_differences(name):
         else:
             o, n = O.NET_OFF[part]
             v[o:o + n] = rng.standard_normal(n)
-        lp, _ = O.learned_loss(sim, th + h * v, a, x, target, grad=False)
-        lm, _ = O.learned_loss(sim, th - h * v, a, x, target, grad=False)
-        fd = (lp - lm) / (2 * h)
+        fd = (4.0 * cd(v, h / 2) - cd(v, h)) / 3.0
         assert _rel(fd, np.sum(d * v)) < 1e-7, part
