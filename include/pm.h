@@ -211,6 +211,12 @@ pm_status pm_power(pm_ctx *ctx, const float *x, int32_t a_lo, int32_t a_hi, int3
                    int32_t b_hi, int32_t nbins, int32_t compensate, double *k_mean, double *pk,
                    double *n_modes, void *stream);
 
+/* The same estimator on two given density-contrast meshes da, db (device
+ * float32 [N]^3, equal for an auto spectrum): cross power Re(da(k) db(k)*).
+ * Used to compare runs painted on one mesh (spectra ratios, r(k)). */
+pm_status pm_power_mesh(pm_ctx *ctx, const float *da, const float *db, int32_t nbins, int32_t compensate,
+                        double *k_mean, double *pk, double *n_modes, void *stream);
+
 /* Attach a caller-owned device array of P uint32 ids (or NULL to detach)
  * that pm_step permutes together with the particles; its initial content is
  * the caller's (for instance 0..P-1 in canonical order).  Errors: PM_ERR_STATE

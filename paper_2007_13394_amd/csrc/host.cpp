@@ -831,6 +831,46 @@ pm_status pm_power(pm_ctx *c, const float *x, int32_t a_lo, int32_t a_hi, int32_
     return check_guards(c, s);
 }
 
+pm_status pm_power_mesh(pm_ctx *c, const float *da, const float *db, int32_t nbins, int32_t compensate,
+                        double *k_mean, double *pk, double *n_modes, void *stream)
+{
+    if (!c || !da || !db || !k_mean || !pk || !n_modes) return fail(PM_ERR_ARG, "NULL argument to pm_power_mesh");
+    if (nbins < 1 || nbins > pm::MAX_BINS) return fail(PM_ERR_ARG, "nbins must be in [1, %d]", pm::MAX_BINS);
+    hipStream_t s = S(stream);
+    const int n = c->n, lg = c->logn;
+    const int64_t M = (int64_t)n * n * n, n2 = (int64_t)n * n, nhp = pm::half_pad(n);
+    const int ncb = (int)(nhp / pm::TILE_W);
+    auto spectrum = [&](const float *d, float2 *S) -> pm_status {
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, d, n, S, n, n2, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_AXIS0, pm::launch_axis0(lg, pm::MULT_NONE, S, n2, n, S, nullptr, nullptr, n2, n, ncb, 0.0,
+                                             nullptr, c->ws.tw, s));
+        return PM_OK;
+    };
+    float2 *A = reinterpret_cast<float2 *>(c->ws.q), *B = A;
+    pm_status st = spectrum(da, A);
+    if (st == PM_OK && db != da) {
+        B = reinterpret_cast<float2 *>(c->ws.f);
+        st = spectrum(db, B);
+    }
+    if (st != PM_OK) return st;
+    const double V = pow(c->cfg.box, 3);
+    double *out = c->ws.partial + (size_t)pm::POWER_BLOCKS * 3 * pm::MAX_BINS;
+    LAUNCH(pm::K_POWER_BIN, pm::launch_power_bin(A, B, n, n, nbins, compensate, V / ((double)M * (double)M),
+                                                 2.0 * M_PI / c->cfg.box, c->ws.partial, s));
+    LAUNCH(pm::K_POWER_REDUCE, pm::launch_power_reduce(c->ws.partial, nbins, out, s));
+    std::vector<double> h(3 * (size_t)nbins);
+    HIPCHK(hipMemcpyAsync(h.data(), out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < nbins; b++) {
+        const double w = h[3 * b + 2];
+        n_modes[b] = w;
+        pk[b] = w > 0 ? h[3 * b] / w : 0.0;
+        k_mean[b] = w > 0 ? h[3 * b + 1] / w : 0.0;
+    }
+    return PM_OK;
+}
+
 // ---- reverse mode
 
 pm_status pm_density(pm_ctx *c, const float *x, float *delta, void *stream)

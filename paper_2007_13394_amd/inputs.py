@@ -14,7 +14,10 @@ count)^(1/3) / 4, 10 shells, N_fib = 3, i.e. 70 particles per site):
   C3  2048^3 mesh, L = 1024 Mpc/h, 1024^3 CDM, 128^3 sites, M_nu = 0.06 eV normal
       hierarchy as one effective species, 5 log steps to z = 19 + 20 linear
   C4  256^3 (coarse) / 1024^3 (fine) mesh, L = 256 Mpc/h, 256^3 CDM, 32^3 sites,
-      M_nu = 0.1 eV, 25 linear steps
+      M_nu = 0.1 eV, 25 linear steps, started at z = 19: a mesh four times finer
+      than the particle lattice, run from z = 99, builds spurious large-scale
+      power from lattice discreteness, so the fine-mesh truth of the learned
+      correction starts later (coarse and fine runs alike)
   C5  256^3 mesh, L = 256 Mpc/h, 128^3 CDM, 16^3 sites, M_nu = 0.1 eV, 10 linear steps
 """
 import numpy as np
@@ -39,9 +42,14 @@ CONFIGS = {
     "C3": dict(_COMMON, box=1024.0, n_mesh=2048, n_cdm=1024, n_sites=128, m_nu=NH_006,
                n_lin=20, n_log=5, a_mid=0.05, seed=3),
     "C4_coarse": dict(_COMMON, box=256.0, n_mesh=256, n_cdm=256, n_sites=32, m_nu=_deg(0.1),
-                      n_lin=25, n_log=0, a_mid=None, seed=200),
+                      n_lin=25, n_log=0, a_mid=None, seed=200, a0=0.05),
     "C4_fine": dict(_COMMON, box=256.0, n_mesh=1024, n_cdm=256, n_sites=32, m_nu=_deg(0.1),
-                    n_lin=25, n_log=0, a_mid=None, seed=200),
+                    n_lin=25, n_log=0, a_mid=None, seed=200, a0=0.05),
+    # a small instance of the C4 setting (same box, 4x coarser particles)
+    "C4s_coarse": dict(_COMMON, box=256.0, n_mesh=64, n_cdm=64, n_sites=8, m_nu=_deg(0.1),
+                       n_lin=10, n_log=0, a_mid=None, seed=150, a0=0.05),
+    "C4s_fine": dict(_COMMON, box=256.0, n_mesh=256, n_cdm=64, n_sites=8, m_nu=_deg(0.1),
+                     n_lin=10, n_log=0, a_mid=None, seed=150, a0=0.05),
     "C5": dict(_COMMON, box=256.0, n_mesh=256, n_cdm=128, n_sites=16, m_nu=_deg(0.1),
                n_lin=10, n_log=0, a_mid=None, seed=301),
     "C5_fd16": dict(_COMMON, box=256.0, n_mesh=16, n_cdm=8, n_sites=2, m_nu=_deg(0.1),

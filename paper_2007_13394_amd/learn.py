@@ -1,0 +1,231 @@
+"""Training and judging of the learned force correction.
+
+Orchestration only: every force, loss, gradient and optimiser step runs in
+libpm's kernels (pm_force, pm_learned_loss, pm_adam, pm_learned_step,
+pm_step, pm_density, pm_power_mesh); PyTorch holds device memory.
+
+Training pairs come from plain runs on the fine mesh (4x the coarse mesh per
+side), started from seeded white noise: at every `snap_every`-th force
+evaluation the particle positions and the fine-mesh forces are kept, both
+rescaled to coarse-mesh units (positions / 4, forces / 4: a force in grid
+units scales with the number of cells per side for the same physical force).
+The network is trained by force matching on the coarse mesh, and judged by
+running coarse learned and plain simulations and a fine plain simulation from
+a held-out seed and comparing their power spectra at the end, all painted on
+the coarse mesh.
+"""
+import time
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import pm
+from . import run as R
+
+NET_H, NET_C = 96, 16
+
+
+def _offsets():
+    sizes = [("W0", NET_H * 2), ("B0", NET_H), ("W1", NET_H * NET_H), ("B1", NET_H), ("W2", NET_H * NET_H),
+             ("B2", NET_H), ("W3", NET_H), ("B3", 1), ("C1W", NET_C * 27), ("C1B", NET_C),
+             ("C2W", NET_C * NET_C * 27), ("C2B", NET_C), ("C3W", NET_C * 27), ("C3B", 1)]
+    off, o = {}, 0
+    for k, n in sizes:
+        off[k] = (o, n)
+        o += n
+    return off, o
+
+
+NET_OFF, NET_NPARAM = _offsets()
+
+
+def init_params(seed, device, hidden_scale=1.0):
+    """Scaled-normal hidden layers; output layers at zero, so the untrained
+    network is the plain particle-mesh force."""
+    rng = np.random.default_rng(seed)
+    th = np.zeros(NET_NPARAM, dtype=np.float32)
+    fans = {"W0": 2, "W1": NET_H, "W2": NET_H, "C1W": 27, "C2W": 27 * NET_C}
+    for k, fan in fans.items():
+        o, n = NET_OFF[k]
+        th[o:o + n] = rng.standard_normal(n) * hidden_scale / np.sqrt(fan)
+    assert NET_NPARAM == pm.pm_net_nparam()
+    return torch.from_numpy(th).to(device)
+
+
+def make_ctx(cfg, learned=False):
+    flags = pm.PM_FLAG_NO_SORT | (pm.PM_FLAG_LEARNED if learned else 0)
+    return pm.Ctx(pm.make_config(cfg, flags=flags))
+
+
+def _calls(cfg):
+    a, half = R.schedule(cfg["a0"], cfg["n_lin"], cfg["n_log"], cfg["a_mid"])
+    return R.kdk_calls(a, half)
+
+
+def fine_pairs(cfg_fine, seeds, snap_every, device, log=print):
+    """[(a, x_coarse, F_coarse)] from plain fine-mesh runs (canonical order)."""
+    ratio = cfg_fine["n_mesh"] // cfg_fine["coarse_mesh"]
+    ctx = make_ctx(cfg_fine)
+    calls = _calls(cfg_fine)
+    pairs = []
+    for seed in seeds:
+        x, p = ctx.particles()
+        w = torch.from_numpy(I.white_noise(seed, cfg_fine["n_cdm"])).to(device)
+        pm.pm_ic(ctx, w, x, p)
+        del w
+        acc = torch.empty_like(x)
+        for i, c in enumerate(calls):
+            if i % snap_every == snap_every - 1 or i == len(calls) - 1:
+                pm.pm_force(ctx, x, acc)
+                pairs.append((c[0], (x / ratio).contiguous(), (acc / ratio).contiguous()))
+            pm.pm_step(ctx, x, p, *c)
+        log(f"[learn] fine run seed {seed}: {len(pairs)} pairs")
+    del ctx
+    torch.cuda.empty_cache()
+    return pairs
+
+
+def train(ctx, theta, pairs, iters, lr=2e-3, lr_end=2e-4, seed=0, log=print):
+    """Adam on the force-matching loss, one pair per step in shuffled order."""
+    rng = np.random.default_rng(seed)
+    m, v, g = torch.zeros_like(theta), torch.zeros_like(theta), torch.zeros_like(theta)
+    hist = []
+    order = []
+    for t in range(1, iters + 1):
+        if not order:
+            order = list(rng.permutation(len(pairs)))
+        a, x, F = pairs[order.pop()]
+        g.zero_()
+        loss = pm.pm_learned_loss(ctx, theta, a, x, F, g)
+        lr_t = lr * (lr_end / lr) ** ((t - 1) / max(1, iters - 1))
+        pm.pm_adam(theta, m, v, g, lr_t, 0.9, 0.999, 1e-8, t)
+        hist.append(loss)
+        if t % 50 == 0 or t == 1:
+            log(f"[learn] step {t}: loss {np.mean(hist[-50:]):.4g}")
+    return hist
+
+
+def pair_loss(ctx, theta, pairs):
+    return float(np.mean([pm.pm_learned_loss(ctx, theta, a, x, F) for a, x, F in pairs]))
+
+
+def simulate(ctx, cfg, seed, device, theta=None, scale=1):
+    """Run the full schedule; returns final positions (in units of the mesh of
+    `ctx` divided by `scale`) and the wall time of the steps."""
+    x, p = ctx.particles()
+    w = torch.from_numpy(I.white_noise(seed, cfg["n_cdm"])).to(device)
+    pm.pm_ic(ctx, w, x, p)
+    del w
+    ids = None
+    if ctx.sorts:
+        # a sorting context permutes the particles: carry ids to restore the
+        # canonical order (segment masses are looked up by position)
+        ids = torch.arange(ctx.P, dtype=torch.int32, device=device)
+        pm.pm_attach_ids(ctx, ids)
+    calls = _calls(cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in calls:
+        if theta is None:
+            pm.pm_step(ctx, x, p, *c)
+        else:
+            pm.pm_learned_step(ctx, theta, x, p, *c)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if ids is not None:
+        pm.pm_attach_ids(ctx, None)
+        xc = torch.empty_like(x)
+        xc[:, ids.long()] = x
+        x = xc
+    return (x / scale).contiguous(), dt, len(calls)
+
+
+def spectra(ctx, xs, nbins):
+    """Auto spectra of each position set and cross spectra with the first one,
+    all painted on the mesh of `ctx`."""
+    n = ctx.n
+    dens = []
+    for x in xs:
+        d = torch.empty(n ** 3, dtype=torch.float32, device=x.device)
+        pm.pm_density(ctx, x, d)
+        dens.append(d)
+    k, p0, nm = pm.pm_power_mesh(ctx, dens[0], dens[0], nbins)
+    autos, cross = [p0], [p0]
+    for d in dens[1:]:
+        autos.append(pm.pm_power_mesh(ctx, d, d, nbins)[1])
+        cross.append(pm.pm_power_mesh(ctx, dens[0], d, nbins)[1])
+    return k, nm, autos, cross
+
+
+def judge(coarse_name, fine_name, train_seeds, test_seed, snap_every=5, iters=400, lr=2e-3, device="cuda",
+          log=print):
+    """Train on fine-mesh force pairs, then compare learned coarse, plain
+    coarse and plain fine runs from a held-out seed.  Returns a dict."""
+    cc, cf = I.config(coarse_name), I.config(fine_name)
+    ratio = cf["n_mesh"] // cc["n_mesh"]
+    cf = dict(cf, coarse_mesh=cc["n_mesh"])
+    t0 = time.perf_counter()
+    pairs = fine_pairs(cf, train_seeds, snap_every, device, log)
+    test_pairs = fine_pairs(cf, [test_seed], snap_every, device, log)
+    t_pairs = time.perf_counter() - t0
+    ctx = make_ctx(cc, learned=True)
+    theta = init_params(1, device)
+    base_train, base_test = pair_loss(ctx, theta, pairs), pair_loss(ctx, theta, test_pairs)
+    t0 = time.perf_counter()
+    hist = train(ctx, theta, pairs, iters, lr=lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    tr_train, tr_test = pair_loss(ctx, theta, pairs), pair_loss(ctx, theta, test_pairs)
+    del test_pairs, pairs
+    torch.cuda.empty_cache()
+    # held-out runs
+    x_l, t_l, ncalls = simulate(ctx, cc, test_seed, device, theta=theta)
+    x_c, t_c, _ = simulate(make_ctx(cc), cc, test_seed, device)
+    ctx_f = pm.Ctx(pm.make_config(cf))
+    x_f, t_f, _ = simulate(ctx_f, cf, test_seed, device, scale=ratio)
+    del ctx_f
+    torch.cuda.empty_cache()
+    nb = cc["n_mesh"] // 2
+    k, nm, autos, cross = spectra(make_ctx(cc), [x_f, x_l, x_c], nb)
+    kn = np.pi * cc["n_mesh"] / cc["box"]
+    sel = (nm > 0) & (k > 0) & (k < kn / 2)
+    err_l = np.abs(autos[1][sel] / autos[0][sel] - 1)
+    err_c = np.abs(autos[2][sel] / autos[0][sel] - 1)
+    r_l = cross[1][sel] / np.sqrt(autos[0][sel] * autos[1][sel])
+    r_c = cross[2][sel] / np.sqrt(autos[0][sel] * autos[2][sel])
+    P = ctx.P
+    out = {
+        "coarse": coarse_name, "fine": fine_name, "particles": P, "train_seeds": list(train_seeds),
+        "test_seed": test_seed, "iters": iters, "pairs_s": round(t_pairs, 2), "train_s": round(t_train, 2),
+        "force_loss": {"plain_train": base_train, "learned_train": tr_train, "plain_test": base_test,
+                       "learned_test": tr_test},
+        "pk_max_rel_err": {"learned": float(err_l.max()), "plain_coarse": float(err_c.max())},
+        "k_range_hMpc": [float(k[sel].min()), float(k[sel].max())],
+        "r_min": {"learned": float(r_l.min()), "plain_coarse": float(r_c.min())},
+        "particle_steps_per_s": {"learned_coarse": P * ncalls / t_l, "plain_coarse": P * ncalls / t_c,
+                                 "plain_fine": P * ncalls / t_f},
+        "speedup_vs_fine": t_f / t_l,
+        "pk": {"k": k[sel].tolist(), "fine": autos[0][sel].tolist(), "learned": autos[1][sel].tolist(),
+               "plain_coarse": autos[2][sel].tolist()},
+        "loss_history": [float(h) for h in hist[::10]],
+    }
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="train and judge the learned force correction")
+    ap.add_argument("--coarse", default="C4_coarse")
+    ap.add_argument("--fine", default="C4_fine")
+    ap.add_argument("--train-seeds", default="100,101,102,103,104,105,106,107")
+    ap.add_argument("--test-seed", type=int, default=200)
+    ap.add_argument("--snap-every", type=int, default=5)
+    ap.add_argument("--iters", type=int, default=400)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    a = ap.parse_args()
+    res = judge(a.coarse, a.fine, [int(s) for s in a.train_seeds.split(",")], a.test_seed, a.snap_every, a.iters,
+                a.lr, log=lambda *m: print(*m, file=sys.stderr, flush=True))
+    print(json.dumps(res), flush=True)

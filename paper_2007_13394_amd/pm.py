@@ -88,6 +88,7 @@ _sig("pm_learned_force", [_vp, _vp, _dbl, _vp, _vp, _vp])
 _sig("pm_learned_step", [_vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _dbl, _vp])
 _sig("pm_learned_loss", [_vp, _vp, _dbl, _vp, _vp, C.POINTER(C.c_double), _vp, _vp])
 _sig("pm_adam", [_vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _dbl, _dbl, _i32, _vp])
+_sig("pm_power_mesh", [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp])
 _lib.pm_net_nparam.restype = C.c_int32
 _lib.pm_net_nparam.argtypes = []
 _sig("pm_power", [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp])
@@ -103,7 +104,8 @@ EXPORTS = ["pm_sizes", "pm_init", "pm_free", "pm_last_error", "pm_segments", "pm
            "pm_kdk_factors", "pm_ic", "pm_paint_q", "pm_paint", "pm_fft_r2c", "pm_fft_c2r", "pm_force_mesh",
            "pm_force", "pm_step", "pm_power", "pm_trace_begin", "pm_trace_end", "pm_kernel_name", "pm_attach_ids",
            "pm_segment_tags", "pm_reset_order", "pm_density", "pm_density_vjp", "pm_force_vjp", "pm_step_vjp",
-           "pm_ic_vjp", "pm_net_nparam", "pm_learned_force", "pm_learned_step", "pm_learned_loss", "pm_adam"]
+           "pm_ic_vjp", "pm_net_nparam", "pm_learned_force", "pm_learned_step", "pm_learned_loss", "pm_adam",
+           "pm_power_mesh"]
 
 
 def _check(st):
@@ -149,6 +151,11 @@ class Ctx:
         _check(_lib.pm_init(C.byref(cfg), C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), _stream(stream), C.byref(h)))
         self.h = h
         self._free = _lib.pm_free   # held here: module globals may be gone at interpreter exit
+
+    @property
+    def sorts(self):
+        """Whether pm_step tile-sorts (and so permutes) the particles."""
+        return self.n // 16 >= 2 and self.P < 2 ** 31 and not (self.cfg.flags & PM_FLAG_NO_SORT)
 
     def close(self):
         """Release the context (the workspace tensor is freed with the object)."""
@@ -361,4 +368,14 @@ def pm_adam(theta, m, v, g, lr, beta1, beta2, eps, t, stream=None):
     _check(_lib.pm_adam(_dev(theta, torch.float32, n, "theta"), _dev(m, torch.float32, n, "m"),
                         _dev(v, torch.float32, n, "v"), _dev(g, torch.float32, n, "g"), n, lr, beta1, beta2, eps,
                         int(t), _stream(stream)))
+
+
+def pm_power_mesh(ctx, da, db, nbins, compensate=False, stream=None):
+    """(k_mean, P(k), n_modes) of two density meshes on the context's mesh."""
+    n = ctx.n
+    k, pk, nm = np.zeros(nbins), np.zeros(nbins), np.zeros(nbins)
+    _check(_lib.pm_power_mesh(ctx.h, _dev(da, torch.float32, n ** 3, "da"), _dev(db, torch.float32, n ** 3, "db"),
+                              nbins, int(bool(compensate)), k.ctypes.data, pk.ctypes.data, nm.ctypes.data,
+                              _stream(stream)))
+    return k, pk, nm
 
