@@ -306,7 +306,8 @@ int32_t pm_net_nparam(void);
  * D(a)).  acc: device [3][P]. */
 pm_status pm_learned_force(pm_ctx *ctx, const float *theta, double a, const float *x, float *acc, void *stream);
 
-/* pm_step with the learned force (same factors and semantics, unsorted). */
+/* pm_step with the learned force: same factors and semantics, including the
+ * tile sort (particles come back in sorted order) unless PM_FLAG_NO_SORT. */
 pm_status pm_learned_step(pm_ctx *ctx, const float *theta, float *x, float *p, double a_force, double a_kick0,
                           double a_kick1, double a_drift1, void *stream);
 

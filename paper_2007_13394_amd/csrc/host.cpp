@@ -64,7 +64,7 @@ int ilog2i(int v)
 struct Layout {
     size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags, ids, koff, key, rank, cnt, bsum, total;
     size_t net_phif, net_z1, net_a1, net_z2, net_a2, net_g1, net_g2, net_dpsi, net_dk, net_acc, net_table, net_tbar,
-        net_red;
+        net_red, net_wpk;
     int64_t nkeys;
 };
 
@@ -124,7 +124,7 @@ Layout layout(const pm_config &c)
         L.bsum = L.cnt + align256(4 * (size_t)(L.nkeys + 1));
     }
     L.net_phif = L.net_z1 = L.net_a1 = L.net_z2 = L.net_a2 = L.net_g1 = L.net_g2 = L.net_dpsi = L.net_dk = 0;
-    L.net_acc = L.net_table = L.net_tbar = L.net_red = 0;
+    L.net_acc = L.net_table = L.net_tbar = L.net_red = L.net_wpk = 0;
     if (c.flags & PM_FLAG_LEARNED) {
         const size_t M = (size_t)(n * n * n);
         auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
@@ -141,6 +141,7 @@ Layout layout(const pm_config &c)
         L.net_table = take(pm::NET_NB * 4);
         L.net_tbar = take(pm::NET_NB * 8);
         L.net_red = take(64);
+        L.net_wpk = take(pm::NET_WPK_BYTES);
     }
     L.total = off;
     return L;
@@ -336,9 +337,10 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
 }
 
 // Learned force meshes into the F region (real rows of stride 2 Nhp) from
-// the density in Q: natural-order transforms; the filtered potential, the
-// CNN activations and (keep) the density spectrum stay in the workspace for
-// the reverse mode.
+// the density in Q: natural-order transforms.  With keep, the filtered
+// potential, every CNN pre-activation and activation and the density
+// spectrum stay in the workspace for the reverse mode; without, the fused
+// inference CNN keeps only the filtered potential and a2.
 pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStream_t s)
 {
     const int n = c->n, lg = c->logn;
@@ -357,10 +359,15 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + cs, n * nhp, nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + cs, nhp, c->ws.net_phif, rs, n2, c->ws.tw, s));
-    LAUNCH(pm::K_NET, pm::launch_cnn_fwd(c->ws.net_phif, rs, n, 1.0 / Da, th, c->ws.net_z1, c->ws.net_a1,
-                                         c->ws.net_z2, c->ws.net_a2, c->ws.net_dpsi, s));
     float *Fr = reinterpret_cast<float *>(F);
-    LAUNCH(pm::K_NET, pm::launch_combine(c->ws.net_phif, c->ws.net_dpsi, rs, n, Da, Fr, s));
+    if (keep) {
+        // the reverse mode needs every pre-activation and activation
+        LAUNCH(pm::K_NET, pm::launch_cnn_fwd(c->ws.net_phif, rs, n, 1.0 / Da, th, c->ws.net_z1, c->ws.net_a1,
+                                             c->ws.net_z2, c->ws.net_a2, c->ws.net_dpsi, s));
+        LAUNCH(pm::K_NET, pm::launch_combine(c->ws.net_phif, c->ws.net_dpsi, rs, n, Da, Fr, s));
+    } else {
+        LAUNCH(pm::K_NET, pm::launch_cnn_inf(c->ws.net_phif, rs, n, Da, th, c->ws.net_wpk, c->ws.net_a2, Fr, s));
+    }
     LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, Fr, rs, F, nhp, n2, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
@@ -455,6 +462,7 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
         c->ws.net_table = reinterpret_cast<float *>(b + L.net_table);
         c->ws.net_tbar = reinterpret_cast<double *>(b + L.net_tbar);
         c->ws.net_red = reinterpret_cast<double *>(b + L.net_red);
+        c->ws.net_wpk = reinterpret_cast<uint16_t *>(b + L.net_wpk);
     }
     // twiddles for every power-of-two length L <= N: tw[L + m] = exp(-2 pi i m / L)
     const int n = c->n;
@@ -995,10 +1003,25 @@ pm_status pm_learned_step(pm_ctx *c, const float *th, float *x, float *p, double
     st = pm_kdk_factors(c, a_force, a_kick0, a_kick1, a_drift1, &kick, &drift);
     if (st != PM_OK) return st;
     hipStream_t s = S(stream);
+    const int64_t n = c->n, nhp = pm::half_pad(c->n);
+    if (sorting_on(c)) {
+        // as pm_step: tile sort, tile paint, (learned) solve, tile readout
+        st = tile_sort(c, x, p, s);
+        if (st != PM_OK) return st;
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, 0, c->nseg, c->n,
+                                                   c->ws.q, s));
+        st = learned_solve(c, th, a_force, false, s);
+        if (st != PM_OK) return st;
+        LAUNCH(pm::K_READOUT_KD,
+               pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * n * nhp, c->n,
+                                           (float)kick, (float)drift, x, p, c->ws.tags, c->ws.ids_tmp, c->ids,
+                                           c->ws.flag, s));
+        c->permuted = true;
+        return check_guards(c, s);
+    }
     st = paint_all(c, x, s);
     if (st == PM_OK) st = learned_solve(c, th, a_force, false, s);
     if (st != PM_OK) return st;
-    const int64_t n = c->n, nhp = pm::half_pad(c->n);
     LAUNCH(pm::K_READOUT_KD, pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, n * n * nhp, c->n, (float)kick,
                                                            (float)drift, c->ws.flag, s));
     return check_guards(c, s);

@@ -16,6 +16,13 @@ namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+
+// sum + a.lo b.lo + a.hi b.hi for BF16 pairs, FP32 accumulation
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float sum)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2bf, a), __builtin_bit_cast(v2bf, b), sum, false);
+}
 
 inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536LL * 16)
 {
@@ -25,19 +32,14 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536LL * 16)
     return (unsigned)b;
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 __device__ __forceinline__ float dsilu(float z)
 {
     const float s = 1.f / (1.f + __expf(-z));
     return s + z * s * (1.f - s);
 }
-// round to the nearest BF16 (ties to even) and back
-__device__ __forceinline__ uint16_t to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// round to the nearest BF16 (ties to even; the hardware conversion) and back
+__device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ float bf16r(float f) { return from_bf16(to_bf16(f)); }
 
@@ -384,6 +386,196 @@ __global__ __launch_bounds__(256) void k_conv3_fwd(const uint16_t *__restrict__ 
     }
 }
 
+// ---- inference path: no pre-activations kept, a1 never leaves LDS
+// conv1 + conv2.  The 16 x 8 x 4 output tile of conv2 needs a1 on the tile
+// and its one-voxel halo (C2HALO voxels); conv1 computes those on MFMA from
+// psi on a two-voxel halo, staged in LDS as BF16.  Per group of 16 halo
+// voxels: D[co][vox] = W1[co][tap] U[tap][vox] over 32 taps (27 real, 5 zero
+// weights and zero data), two 16x16x16 MFMAs.  conv2 as k_conv2_fwd with the
+// 27 weight fragments in registers; only a2 (BF16) is written.
+constexpr int U1X = C2X + 4, U1Y = C2Y + 4, U1Z = C2Z + 4, U1N = U1X * U1Y * U1Z;
+// Inference weights repacked once per call (byte offsets in wpk): conv2 BF16
+// [t][co][ci], conv1 BF16 [co][32 taps, zero past 27], conv3 BF16 [t][ci].
+constexpr int WPK_W2 = 0, WPK_W1 = 27 * NET_C * NET_C * 2, WPK_W3 = WPK_W1 + NET_C * 32 * 2,
+              WPK_END = WPK_W3 + 27 * NET_C * 2;
+static_assert(WPK_END <= NET_WPK_BYTES && WPK_W1 % 16 == 0 && WPK_W3 % 16 == 0, "packed weight layout");
+
+__global__ __launch_bounds__(256) void k_pack_w(const float *__restrict__ th, uint16_t *wpk)
+{
+    uint16_t *w2 = wpk + WPK_W2 / 2, *w1 = wpk + WPK_W1 / 2, *w3 = wpk + WPK_W3 / 2;
+    for (int e = threadIdx.x; e < 27 * NET_C * NET_C; e += 256) {
+        const int co = e / (27 * NET_C), ci = (e / 27) % NET_C, t = e % 27;
+        w2[(t * NET_C + co) * NET_C + ci] = to_bf16(th[NC2W + e]);
+    }
+    for (int e = threadIdx.x; e < NET_C * 32; e += 256) {
+        const int co = e / 32, t = e % 32;
+        w1[e] = t < 27 ? to_bf16(th[NC1W + co * 27 + t]) : (uint16_t)0;
+    }
+    for (int e = threadIdx.x; e < 27 * NET_C; e += 256) {
+        const int t = e / NET_C, ci = e % NET_C;
+        w3[e] = to_bf16(th[NC3W + ci * 27 + t]);
+    }
+}
+constexpr int NG1 = (C2HALO + 15) / 16;
+
+__device__ __forceinline__ int u1_off(int t) { return ((t / 9) * U1Y + (t / 3) % 3) * U1X + t % 3; }
+
+__global__ __launch_bounds__(256) void k_cnn12_inf(const float *__restrict__ phif, int64_t rs, int n, float s,
+                                                   const float *__restrict__ th, const uint16_t *__restrict__ wpk,
+                                                   uint16_t *a2)
+{
+    __shared__ __align__(16) uint16_t U[U1N];
+    __shared__ __align__(16) uint16_t X[C2HALO * NET_C];
+    __shared__ __align__(16) uint16_t W2s[27 * NET_C * NET_C];
+    __shared__ __align__(16) uint16_t W1s[NET_C * 32];
+    __shared__ float B1[NET_C], B2[NET_C];
+    const int tid = threadIdx.x;
+    const int ntx = n / C2X, nty = n / C2Y;
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int x0 = tx * C2X, y0 = ty * C2Y, z0 = tz * C2Z, m = n - 1;
+    for (int e = tid; e < WPK_W3 / 16; e += 256)   // conv2 then conv1 weights, adjacent in LDS and wpk
+        reinterpret_cast<uint4 *>(e < WPK_W1 / 16 ? W2s : W1s)[e < WPK_W1 / 16 ? e : e - WPK_W1 / 16] =
+            reinterpret_cast<const uint4 *>(wpk)[e];
+    if (tid < NET_C) {
+        B1[tid] = th[NC1B + tid];
+        B2[tid] = th[NC2B + tid];
+    }
+    for (int e = tid; e < U1N; e += 256) {
+        const int ux = e % U1X, uy = (e / U1X) % U1Y, uz = e / (U1X * U1Y);
+        const int64_t row = (int64_t)((z0 + uz - 2) & m) * n + ((y0 + uy - 2) & m);
+        U[e] = to_bf16(s * phif[row * rs + ((x0 + ux - 2) & m)]);
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, kg = lane >> 4;
+    {
+        const v4s w1a = *reinterpret_cast<const v4s *>(W1s + col * 32 + 4 * kg);
+        const v4s w1b = *reinterpret_cast<const v4s *>(W1s + col * 32 + 16 + 4 * kg);
+        int oa[4], ob[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            oa[r] = u1_off(4 * kg + r);
+            ob[r] = 16 + 4 * kg + r < 27 ? u1_off(16 + 4 * kg + r) : -1;
+        }
+        float bias[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) bias[r] = B1[4 * kg + r];
+        for (int g = wave; g < NG1; g += 4) {
+            const int hv = g * 16 + col;
+            const int hc = hv < C2HALO ? hv : C2HALO - 1;
+            const int hx = hc % C2HX, hy = (hc / C2HX) % C2HY, hz = hc / (C2HX * C2HY);
+            const int base = (hz * U1Y + hy) * U1X + hx;
+            v4s b0, b1;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                b0[r] = (short)U[base + oa[r]];
+                b1[r] = ob[r] >= 0 ? (short)U[base + ob[r]] : (short)0;
+            }
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1a, b0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1b, b1, acc, 0, 0, 0);
+            // lane holds D[co = 4 kg + r][vox = col]
+            if (hv < C2HALO) {
+                uint16_t aa[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) aa[r] = to_bf16(silu(acc[r] + bias[r]));
+                *reinterpret_cast<uint2 *>(X + hv * NET_C + 4 * kg) =
+                    make_uint2((uint32_t)aa[0] | ((uint32_t)aa[1] << 16), (uint32_t)aa[2] | ((uint32_t)aa[3] << 16));
+            }
+        }
+    }
+    __syncthreads();
+    v4s wa[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++) wa[t] = *reinterpret_cast<const v4s *>(W2s + (t * NET_C + col) * NET_C + 4 * kg);
+    float bias[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) bias[r] = B2[4 * kg + r];
+    for (int row = wave; row < C2Y * C2Z; row += 4) {
+        const int ry = row % C2Y, rz = row / C2Y;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 27; t++) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const int hv = ((rz + dz) * C2HY + (ry + dy)) * C2HX + (col + dx);
+            const v4s xb = *reinterpret_cast<const v4s *>(X + hv * NET_C + 4 * kg);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], xb, acc, 0, 0, 0);
+        }
+        const int64_t v = ((int64_t)(z0 + rz) * n + (y0 + ry)) * n + (x0 + col);
+        uint16_t aa[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) aa[r] = to_bf16(silu(acc[r] + bias[r]));
+        *reinterpret_cast<uint2 *>(a2 + v * NET_C + 4 * kg) =
+            make_uint2((uint32_t)aa[0] | ((uint32_t)aa[1] << 16), (uint32_t)aa[2] | ((uint32_t)aa[3] << 16));
+    }
+}
+
+// conv3 fused with the combination: out = phi_f + D(a) (b3 + conv3(a2)) on
+// real rows of stride rs.  Tile 16 x 16 x 4 with a2's one-voxel halo in LDS;
+// a thread owns a column of 4 voxels along axis 0, so each halo voxel it reads
+// feeds up to three taps.
+constexpr int C3X = 16, C3Y = 16, C3Z = 4, C3HX = C3X + 2, C3HY = C3Y + 2, C3HZ = C3Z + 2;
+constexpr int C3HALO = C3HX * C3HY * C3HZ;
+
+__global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ a2, int n,
+                                                   const float *__restrict__ th, const uint16_t *__restrict__ wpk,
+                                                   const float *__restrict__ phif, int64_t rs, float Da, float *out)
+{
+    // channel halves of each halo voxel in two planes: 16-byte rows, no bank conflicts
+    __shared__ __align__(16) uint4 X[2 * C3HALO];
+    __shared__ __align__(16) uint32_t W[27 * NET_C / 2];   // BF16 pairs [t][ci / 2]
+    const int tid = threadIdx.x;
+    const int ntx = n / C3X, nty = n / C3Y;
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int x0 = tx * C3X, y0 = ty * C3Y, z0 = tz * C3Z, m = n - 1;
+    for (int e = tid; e < 27 * NET_C / 8; e += 256)
+        reinterpret_cast<uint4 *>(W)[e] = reinterpret_cast<const uint4 *>(wpk + WPK_W3 / 2)[e];
+    for (int e = tid; e < C3HALO * 2; e += 256) {
+        const int hv = e >> 1, half = e & 1;
+        const int hx = hv % C3HX, hy = (hv / C3HX) % C3HY, hz = hv / (C3HX * C3HY);
+        const int64_t g = ((int64_t)((z0 + hz - 1) & m) * n + ((y0 + hy - 1) & m)) * n + ((x0 + hx - 1) & m);
+        X[half * C3HALO + hv] = reinterpret_cast<const uint4 *>(a2 + g * NET_C)[half];
+    }
+    __syncthreads();
+    const int lx = tid % C3X, ly = tid / C3X;
+    const float b = th[NC3B];
+    float acc[C3Z];
+#pragma unroll
+    for (int z = 0; z < C3Z; z++) acc[z] = b;
+#pragma unroll 1
+    for (int t2 = 0; t2 < 9; t2++) {
+        const int dy = t2 / 3, dx = t2 % 3;
+        uint32_t w[3][NET_C / 2];
+#pragma unroll
+        for (int dz = 0; dz < 3; dz++)
+#pragma unroll
+            for (int k = 0; k < NET_C / 2; k++) w[dz][k] = W[(dz * 9 + t2) * (NET_C / 2) + k];
+        const int h0 = (ly + dy) * C3HX + lx + dx;
+#pragma unroll
+        for (int hz = 0; hz < C3HZ; hz++) {
+            const int hv = h0 + hz * C3HY * C3HX;
+            const uint4 q0 = X[hv], q1 = X[C3HALO + hv];
+            const uint32_t xv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+            for (int dz = 0; dz < 3; dz++) {
+                const int lz = hz - dz;
+                if (lz < 0 || lz >= C3Z) continue;
+                float sum = acc[lz];
+#pragma unroll
+                for (int k = 0; k < NET_C / 2; k++) sum = dot2_bf16(w[dz][k], xv[k], sum);
+                acc[lz] = sum;
+            }
+        }
+    }
+#pragma unroll
+    for (int z = 0; z < C3Z; z++) {
+        const int64_t o = ((int64_t)(z0 + z) * n + (y0 + ly)) * rs + (x0 + lx);
+        out[o] = phif[o] + Da * acc[z];
+    }
+}
+
 // phi = phi_f + D(a) dpsi on real rows of stride rs.
 __global__ void k_combine(const float *phif, const float *dpsi, int64_t rs, int n, float Da, float *out)
 {
@@ -673,6 +865,19 @@ hipError_t launch_cnn_fwd(const float *phif, int64_t rs, int n, double inv_Da, c
     hipLaunchKernelGGL(k_conv1_fwd, dim3(grid_for(M, 256)), dim3(256), 0, s, phif, rs, n, (float)inv_Da, th, z1, a1);
     hipLaunchKernelGGL(k_conv2_fwd, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, a1, n, th, z2, a2);
     hipLaunchKernelGGL(k_conv3_fwd, dim3(grid_for(M, 256)), dim3(256), 0, s, a2, n, th, dpsi);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_inf(const float *phif, int64_t rs, int n, double Da, const float *th, uint16_t *wpk,
+                          uint16_t *a2, float *out, hipStream_t s)
+{
+    if (n < C3Y || n % C3Y || n % C3Z) return hipErrorInvalidValue;
+    const int64_t M = (int64_t)n * n * n;
+    hipLaunchKernelGGL(k_pack_w, dim3(1), dim3(256), 0, s, th, wpk);
+    hipLaunchKernelGGL(k_cnn12_inf, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, phif, rs, n,
+                       (float)(1.0 / Da), th, wpk, a2);
+    hipLaunchKernelGGL(k_conv3_inf, dim3((unsigned)(M / (C3X * C3Y * C3Z))), dim3(256), 0, s, a2, n, th, wpk, phif,
+                       rs, (float)Da, out);
     return hipGetLastError();
 }
 

@@ -86,11 +86,13 @@ struct Workspace {
     float *net_table = nullptr;  // radial filter table [NET_NB]
     double *net_tbar = nullptr;  // its cotangent [NET_NB]
     double *net_red = nullptr;   // loss reductions [2]
+    uint16_t *net_wpk = nullptr; // inference weights in LDS layout [NET_WPK_BYTES]
 };
 
 // Learned force correction: MLP width, radial table bins, CNN channels, and
 // offsets into the flat parameter array.
 constexpr int NET_H = 96, NET_NB = 256, NET_C = 16;
+constexpr int NET_WPK_BYTES = 32768;
 constexpr int NW0 = 0, NB0 = NW0 + NET_H * 2, NW1 = NB0 + NET_H, NB1 = NW1 + NET_H * NET_H, NW2 = NB1 + NET_H,
               NB2 = NW2 + NET_H * NET_H, NW3 = NB2 + NET_H, NB3 = NW3 + NET_H, NC1W = NB3 + 1,
               NC1B = NC1W + NET_C * 27, NC2W = NC1B + NET_C, NC2B = NC2W + NET_C * NET_C * 27,
@@ -217,6 +219,11 @@ hipError_t launch_cnn_fwd(const float *phif, int64_t rs, int n, double inv_Da, c
                           uint16_t *a1, float *z2, uint16_t *a2, float *dpsi, hipStream_t s);
 hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int n, double Da, float *out,
                           hipStream_t s);
+// Inference CNN fused with the combination: out = phi_f + D(a) cnn(phi_f / D(a))
+// on real rows; a2: BF16 [n^3][16] scratch, wpk: NET_WPK_BYTES scratch for the
+// repacked weights.  n a multiple of 16.
+hipError_t launch_cnn_inf(const float *phif, int64_t rs, int n, double Da, const float *th, uint16_t *wpk,
+                          uint16_t *a2, float *out, hipStream_t s);
 hipError_t launch_cnn_bwd(const float *phif, const float *phibar, int64_t rs, int n, double Da, const float *th,
                           const float *z1, const uint16_t *a1, const float *z2, const uint16_t *a2, float *g1,
                           float *g2, float *phibar_f, float *dth, hipStream_t s);

@@ -53,8 +53,11 @@ def init_params(seed, device, hidden_scale=1.0):
     return torch.from_numpy(th).to(device)
 
 
-def make_ctx(cfg, learned=False):
-    flags = pm.PM_FLAG_NO_SORT | (pm.PM_FLAG_LEARNED if learned else 0)
+def make_ctx(cfg, learned=False, sort=False):
+    """Training contexts keep the particles in canonical order (no tile sort),
+    since a force pair and the loss take segment masses by array position;
+    timed runs sort."""
+    flags = (0 if sort else pm.PM_FLAG_NO_SORT) | (pm.PM_FLAG_LEARNED if learned else 0)
     return pm.Ctx(pm.make_config(cfg, flags=flags))
 
 
@@ -180,8 +183,10 @@ def judge(coarse_name, fine_name, train_seeds, test_seed, snap_every=5, iters=40
     del test_pairs, pairs
     torch.cuda.empty_cache()
     # held-out runs
-    x_l, t_l, ncalls = simulate(ctx, cc, test_seed, device, theta=theta)
-    x_c, t_c, _ = simulate(make_ctx(cc), cc, test_seed, device)
+    del ctx
+    torch.cuda.empty_cache()
+    x_l, t_l, ncalls = simulate(make_ctx(cc, learned=True, sort=True), cc, test_seed, device, theta=theta)
+    x_c, t_c, _ = simulate(make_ctx(cc, sort=True), cc, test_seed, device)
     ctx_f = pm.Ctx(pm.make_config(cf))
     x_f, t_f, _ = simulate(ctx_f, cf, test_seed, device, scale=ratio)
     del ctx_f
@@ -194,7 +199,7 @@ def judge(coarse_name, fine_name, train_seeds, test_seed, snap_every=5, iters=40
     err_c = np.abs(autos[2][sel] / autos[0][sel] - 1)
     r_l = cross[1][sel] / np.sqrt(autos[0][sel] * autos[1][sel])
     r_c = cross[2][sel] / np.sqrt(autos[0][sel] * autos[2][sel])
-    P = ctx.P
+    P = x_f.shape[1]
     out = {
         "coarse": coarse_name, "fine": fine_name, "particles": P, "train_seeds": list(train_seeds),
         "test_seed": test_seed, "iters": iters, "pairs_s": round(t_pairs, 2), "train_s": round(t_train, 2),

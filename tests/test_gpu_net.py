@@ -121,3 +121,45 @@ def test_adam_step_matches_definition(dev):
     v1 = b2 * v + (1 - b2) * g * g
     th1 = th - lr * (m1 / (1 - b1 ** t)) / (np.sqrt(v1 / (1 - b2 ** t)) + eps)
     assert np.allclose(T[0].cpu().numpy(), th1, rtol=1e-5, atol=1e-6)
+
+
+def test_learned_step_sorted_and_unsorted_agree(dev):
+    """The tile-sorted learned step (particles come back permuted; ids map
+    them back) against the unsorted one, and the unsorted one against kick
+    and drift applied to the learned force."""
+    from paper_2007_13394_amd import pm
+    cfg = I.config("C1")
+    n = cfg["n_mesh"]
+    th = torch.from_numpy(_params(41)).to(dev)
+    calls = [(0.5, 0.5, 0.55, 0.6), (0.6, 0.55, 0.65, 0.7)]
+    x32, p32 = I.synthetic_state(cfg, seed=42)
+    cs = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_LEARNED))
+    cu = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_LEARNED | pm.PM_FLAG_NO_SORT))
+    assert cs.sorts and not cu.sorts
+    ids = torch.arange(cs.P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(cs, ids)
+    xs, ps = torch.from_numpy(x32).to(dev), torch.from_numpy(p32).to(dev)
+    xu, pu = xs.clone(), ps.clone()
+    for i, c in enumerate(calls):
+        if i == 0:
+            acc = torch.empty_like(xu)
+            pm.pm_learned_force(cu, th, c[0], xu, acc)
+            kick, drift = pm.pm_kdk_factors(cu, *c)
+            p_ref = pu.double() + kick * acc.double()
+            x_ref = torch.remainder(xu.double() + drift * p_ref, n)
+        pm.pm_learned_step(cs, th, xs, ps, *c)
+        pm.pm_learned_step(cu, th, xu, pu, *c)
+        if i == 0:
+            ex = rel_l2(pu.cpu().numpy(), p_ref.cpu().numpy())
+            dx = (xu.double() - x_ref).abs()
+            dx = torch.minimum(dx, n - dx).max().item()
+            say("unsorted learned step vs kick/drift of the learned force: p rel L2", ex, "max |dx|", dx)
+            assert ex < 1e-6 and dx < 1e-4
+    pm.pm_attach_ids(cs, None)
+    order = torch.argsort(ids.long())
+    xo, po = xs[:, order], ps[:, order]
+    dx = (xo - xu).abs()
+    dx = torch.minimum(dx, n - dx).max().item()
+    ep = rel_l2(po.cpu().numpy(), pu.cpu().numpy())
+    say("sorted vs unsorted learned steps: max |dx|", dx, "p rel L2", ep)
+    assert dx < 1e-4 and ep < 1e-5
