@@ -318,6 +318,16 @@ pm_status pm_learned_step(pm_ctx *ctx, const float *theta, float *x, float *p, d
 pm_status pm_learned_loss(pm_ctx *ctx, const float *theta, double a, const float *x, const float *target,
                           double *loss, float *dtheta, void *stream);
 
+/* The radial filter table g(k_b, a) = 1 + MLP(kt_b, a) at the NET_NB = 256 bins
+ * kt_b = b sqrt(3) / 255 (|k| in units of the Nyquist wavenumber), as the
+ * learned force applies it.  theta, table: device float32 [pm_net_nparam()],
+ * [256]. */
+pm_status pm_net_table(const float *theta, double a, float *table, void *stream);
+
+/* dtheta += sum_b tbar[b] d table[b] / d theta (reverse mode of
+ * pm_net_table).  tbar: device float64 [256]; dtheta: device float32. */
+pm_status pm_net_table_vjp(const float *theta, double a, const double *tbar, float *dtheta, void *stream);
+
 /* One Adam step (bias-corrected, step t >= 1) on n FP32 master weights theta
  * with moments m, v and gradient g, all device arrays. */
 pm_status pm_adam(float *theta, float *m, float *v, const float *g, int64_t n, double lr, double beta1,

@@ -1077,6 +1077,23 @@ pm_status pm_learned_loss(pm_ctx *c, const float *th, double a, const float *x, 
     return check_guards(c, s);
 }
 
+pm_status pm_net_table(const float *th, double a, float *table, void *stream)
+{
+    if (!th || !table) return fail(PM_ERR_ARG, "NULL argument to pm_net_table");
+    hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : nullptr;
+    if (pm::launch_mlp_fwd(th, a, table, s) != hipSuccess) return fail(PM_ERR_DEVICE, "filter table launch failed");
+    return PM_OK;
+}
+
+pm_status pm_net_table_vjp(const float *th, double a, const double *tbar, float *dth, void *stream)
+{
+    if (!th || !tbar || !dth) return fail(PM_ERR_ARG, "NULL argument to pm_net_table_vjp");
+    hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : nullptr;
+    if (pm::launch_mlp_bwd(th, a, tbar, dth, s) != hipSuccess)
+        return fail(PM_ERR_DEVICE, "filter table reverse-mode launch failed");
+    return PM_OK;
+}
+
 pm_status pm_adam(float *th, float *m, float *v, const float *g, int64_t n, double lr, double beta1, double beta2,
                   double eps, int32_t t, void *stream)
 {

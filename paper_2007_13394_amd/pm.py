@@ -88,6 +88,8 @@ _sig("pm_learned_force", [_vp, _vp, _dbl, _vp, _vp, _vp])
 _sig("pm_learned_step", [_vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _dbl, _vp])
 _sig("pm_learned_loss", [_vp, _vp, _dbl, _vp, _vp, C.POINTER(C.c_double), _vp, _vp])
 _sig("pm_adam", [_vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _dbl, _dbl, _i32, _vp])
+_sig("pm_net_table", [_vp, _dbl, _vp, _vp])
+_sig("pm_net_table_vjp", [_vp, _dbl, _vp, _vp, _vp])
 _sig("pm_power_mesh", [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp])
 _lib.pm_net_nparam.restype = C.c_int32
 _lib.pm_net_nparam.argtypes = []
@@ -105,7 +107,7 @@ EXPORTS = ["pm_sizes", "pm_init", "pm_free", "pm_last_error", "pm_segments", "pm
            "pm_force", "pm_step", "pm_power", "pm_trace_begin", "pm_trace_end", "pm_kernel_name", "pm_attach_ids",
            "pm_segment_tags", "pm_reset_order", "pm_density", "pm_density_vjp", "pm_force_vjp", "pm_step_vjp",
            "pm_ic_vjp", "pm_net_nparam", "pm_learned_force", "pm_learned_step", "pm_learned_loss", "pm_adam",
-           "pm_power_mesh"]
+           "pm_power_mesh", "pm_net_table", "pm_net_table_vjp"]
 
 
 def _check(st):
@@ -368,6 +370,25 @@ def pm_adam(theta, m, v, g, lr, beta1, beta2, eps, t, stream=None):
     _check(_lib.pm_adam(_dev(theta, torch.float32, n, "theta"), _dev(m, torch.float32, n, "m"),
                         _dev(v, torch.float32, n, "v"), _dev(g, torch.float32, n, "g"), n, lr, beta1, beta2, eps,
                         int(t), _stream(stream)))
+
+
+NET_NB = 256
+
+
+def pm_net_table(theta, a, table=None, stream=None):
+    """Radial filter table [256] (float32 device tensor) at scale factor a."""
+    if table is None:
+        table = torch.empty(NET_NB, dtype=torch.float32, device=theta.device)
+    _check(_lib.pm_net_table(_dev(theta, torch.float32, pm_net_nparam(), "theta"), float(a),
+                             _dev(table, torch.float32, NET_NB, "table"), _stream(stream)))
+    return table
+
+
+def pm_net_table_vjp(theta, a, tbar, dtheta, stream=None):
+    """dtheta += tbar . d table / d theta (tbar float64 [256])."""
+    _check(_lib.pm_net_table_vjp(_dev(theta, torch.float32, pm_net_nparam(), "theta"), float(a),
+                                 _dev(tbar, torch.float64, NET_NB, "tbar"),
+                                 _dev(dtheta, torch.float32, pm_net_nparam(), "dtheta"), _stream(stream)))
 
 
 def pm_power_mesh(ctx, da, db, nbins, compensate=False, stream=None):

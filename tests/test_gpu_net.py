@@ -163,3 +163,20 @@ def test_learned_step_sorted_and_unsorted_agree(dev):
     ep = rel_l2(po.cpu().numpy(), pu.cpu().numpy())
     say("sorted vs unsorted learned steps: max |dx|", dx, "p rel L2", ep)
     assert dx < 1e-4 and ep < 1e-5
+
+
+def test_filter_table_and_its_vjp_vs_oracle(dev):
+    from paper_2007_13394_amd import pm
+    th32 = _params(51)
+    th = torch.from_numpy(th32).to(dev)
+    rng = np.random.default_rng(52)
+    tbar = rng.standard_normal(O.NET_NB)
+    for a in (0.05, 0.5, 1.0):
+        tab = pm.pm_net_table(th, a).cpu().numpy()
+        ref = O.net_table(th32.astype(np.float64), a)
+        d = torch.zeros_like(th)
+        pm.pm_net_table_vjp(th, a, torch.from_numpy(tbar).to(dev), d)
+        dref = O.net_table_vjp(th32.astype(np.float64), a, tbar)
+        e_t, e_d = np.max(np.abs(tab - ref)), rel_l2(d.cpu().numpy(), dref)
+        say("a", a, "table max abs err", e_t, "vjp rel L2", e_d)
+        assert e_t < 1e-5 and e_d < 1e-4
