@@ -318,11 +318,46 @@ def judge(coarse_name, fine_name, train_seeds, test_seed, snap_every=5, iters=40
     return out
 
 
+def time_steps(cfg_name, steps, device="cuda", seed=200):
+    """ms per learned and per plain step on a sorted context of `cfg_name`
+    (parameters: the seeded initialisation with every entry perturbed by 1 %
+    noise, so that every layer runs with non-zero weights), from the initial
+    conditions of `seed`."""
+    cfg = I.config(cfg_name)
+    theta = init_params(1, device)
+    theta += 0.01 * torch.from_numpy(np.random.default_rng(seed).standard_normal(theta.numel()).astype(np.float32)).to(
+        device)
+    calls = _calls(cfg)[:steps + 2]
+    out = {}
+    for name, learned in (("learned", True), ("plain", False)):
+        ctx = make_ctx(cfg, learned=learned, sort=True)
+        x, p = ctx.particles()
+        w = torch.from_numpy(I.white_noise(seed, cfg["n_cdm"])).to(device)
+        pm.pm_ic(ctx, w, x, p)
+        del w
+        for i, c in enumerate(calls):
+            if i == 2:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if learned:
+                pm.pm_learned_step(ctx, theta, x, p, *c)
+            else:
+                pm.pm_step(ctx, x, p, *c)
+        torch.cuda.synchronize()
+        out[name + "_ms_per_step"] = (time.perf_counter() - t0) / (len(calls) - 2) * 1e3
+        out["particles"] = ctx.P
+        del ctx, x, p
+        torch.cuda.empty_cache()
+    return out
+
+
 if __name__ == "__main__":
     import argparse
     import json
     import sys
     ap = argparse.ArgumentParser(description="train and judge the learned force correction")
+    ap.add_argument("--time-steps", type=int, default=0,
+                    help="only time this many learned and plain steps on the coarse workload")
     ap.add_argument("--coarse", default="C4_coarse")
     ap.add_argument("--fine", default="C4_fine")
     ap.add_argument("--train-seeds", default="100,101,102,103,104,105,106,107")
@@ -331,6 +366,9 @@ if __name__ == "__main__":
     ap.add_argument("--iters", type=int, default=400)
     ap.add_argument("--lr", type=float, default=2e-3)
     a = ap.parse_args()
+    if a.time_steps:
+        print(json.dumps(dict(time_steps(a.coarse, a.time_steps), workload=a.coarse)), flush=True)
+        sys.exit(0)
     res = judge(a.coarse, a.fine, [int(s) for s in a.train_seeds.split(",")], a.test_seed, a.snap_every, a.iters,
                 a.lr, log=lambda *m: print(*m, file=sys.stderr, flush=True))
     print(json.dumps(res), flush=True)
