@@ -294,8 +294,9 @@ pm_status pm_ic_vjp(pm_ctx *ctx, const float *xbar, const float *pbar, float *wb
  * inputs, three hidden layers of 96 SiLU units, tabulated at 256 radial bins
  * and interpolated linearly); a periodic 3^3 CNN (1 -> 16 -> 16 -> 1
  * channels, SiLU; BF16 activations and weights, FP32 accumulation) maps the
- * filtered potential phi_f / D(a) to a correction, phi = phi_f + D(a) cnn; the
- * force is minus its spectral gradient, read out with cloud-in-cell weights.
+ * painted density contrast to a potential correction, phi = phi_f + cnn(delta);
+ * the force is minus its spectral gradient, read out with cloud-in-cell
+ * weights.
  * With the output layers at zero it is the plain force.  theta: device
  * float32 [pm_net_nparam()], the flat parameter array (MLP W0 [96][2], b0,
  * W1 [96][96], b1, W2 [96][96], b2, W3 [96], b3; conv W [co][ci][27] and b for

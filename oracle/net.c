@@ -11,12 +11,15 @@
  *     interpolated in between;
  *   filtered potential: phi_f = F^-1 [ g(k, a) (-1.5 Omega_m0 / k^2) F delta ] / M
  *     (zero at k = 0), delta the painted density contrast;
- *   CNN on psi = phi_f / D(a) (D normalised to 1 today): periodic 3^3
- *     cross-correlations 1 -> 16 (SiLU) -> 16 (SiLU) -> 1, out[co](v) =
- *     b[co] + sum_{ci, t} W[co][ci][t] in[ci](v + o(t)), tap t = (t0 3 + t1) 3
- *     + t2 with offsets o_e = t_e - 1 along mesh axes (0, 1, 2);
- *   potential phi = phi_f + D(a) cnn(psi); force F_d = F^-1 [ -i k_d F phi ] / M
+ *   CNN on the density contrast delta: periodic 3^3 cross-correlations
+ *     1 -> 16 (SiLU) -> 16 (SiLU) -> 1, out[co](v) = b[co] + sum_{ci, t}
+ *     W[co][ci][t] in[ci](v + o(t)), tap t = (t0 3 + t1) 3 + t2 with offsets
+ *     o_e = t_e - 1 along mesh axes (0, 1, 2);
+ *   potential phi = phi_f + cnn(delta); force F_d = F^-1 [ -i k_d F phi ] / M
  *     (zero on the Nyquist plane of d), read out with cloud-in-cell weights.
+ * The CNN sees the local mass distribution, not the potential: its output
+ * then changes the force at wavenumber k in proportion to k^2 relative to
+ * the Newtonian force, so it cannot rescale the large-scale force.
  * With the last layers of the MLP and of the CNN at zero this is the plain
  * force of pm.c.  Parameters are one flat array (offsets in orc.h).
  */
@@ -184,8 +187,9 @@ static double interp(const double *table, double kt, int *b0, double *f)
 typedef struct {
     int n;
     long M;
-    double omega_m, Da;
+    double omega_m;
     double table[NET_NB];
+    double *delta; /* density contrast (the CNN input) */
     cplx *dk;      /* F delta */
     double *phif;  /* filtered potential */
     double *z1, *a1, *z2, *a2, *dphi;  /* CNN pre-activations / activations / output */
@@ -194,15 +198,8 @@ typedef struct {
 
 static void free_state(fwd_state *st)
 {
-    free(st->dk); free(st->phif); free(st->z1); free(st->a1); free(st->z2); free(st->a2); free(st->dphi);
+    free(st->delta); free(st->dk); free(st->phif); free(st->z1); free(st->a1); free(st->z2); free(st->a2); free(st->dphi);
     free(st->F);
-}
-
-static double growth_ratio(const orc_sim *s, double a)
-{
-    double aa[2] = {a, 1.0}, D[2], G[2];
-    orc_growth(&s->cosmo, 2, aa, D, G, 1e-3);
-    return D[0] / D[1];
 }
 
 static int forward(const orc_sim *s, const double *th, double a, const double *x, fwd_state *st)
@@ -212,13 +209,11 @@ static int forward(const orc_sim *s, const double *th, double a, const double *x
     st->n = n;
     st->M = M;
     st->omega_m = s->cosmo.omega_m;
-    st->Da = growth_ratio(s, a);
     orc_net_table(th, a, st->table);
-    double *delta = malloc(sizeof(double) * M);
-    if (orc_density_cont(s, x, delta)) { free(delta); return -1; }
+    st->delta = malloc(sizeof(double) * M);
+    if (orc_density_cont(s, x, st->delta)) { free(st->delta); st->delta = NULL; return -1; }
     st->dk = malloc(sizeof(cplx) * M);
-    for (long t = 0; t < M; t++) st->dk[t] = delta[t];
-    free(delta);
+    for (long t = 0; t < M; t++) st->dk[t] = st->delta[t];
     orc_fft3d((double *)st->dk, n, -1);
     cplx *f = malloc(sizeof(cplx) * M);
     for (long t = 0; t < M; t++) {
@@ -235,22 +230,19 @@ static int forward(const orc_sim *s, const double *th, double a, const double *x
     orc_fft3d((double *)f, n, +1);
     st->phif = malloc(sizeof(double) * M);
     for (long t = 0; t < M; t++) st->phif[t] = creal(f[t]) / (double)M;
-    /* CNN */
-    double *psi = malloc(sizeof(double) * M);
-    for (long t = 0; t < M; t++) psi[t] = st->phif[t] / st->Da;
+    /* CNN on delta */
     st->z1 = malloc(sizeof(double) * NET_C * M);
     st->a1 = malloc(sizeof(double) * NET_C * M);
     st->z2 = malloc(sizeof(double) * NET_C * M);
     st->a2 = malloc(sizeof(double) * NET_C * M);
     st->dphi = malloc(sizeof(double) * M);
-    orc_conv3(psi, 1, th + NET_C1W, th + NET_C1B, NET_C, n, st->z1);
+    orc_conv3(st->delta, 1, th + NET_C1W, th + NET_C1B, NET_C, n, st->z1);
     for (long t = 0; t < NET_C * M; t++) st->a1[t] = silu(st->z1[t]);
     orc_conv3(st->a1, NET_C, th + NET_C2W, th + NET_C2B, NET_C, n, st->z2);
     for (long t = 0; t < NET_C * M; t++) st->a2[t] = silu(st->z2[t]);
     orc_conv3(st->a2, NET_C, th + NET_C3W, th + NET_C3B, 1, n, st->dphi);
-    free(psi);
     /* force */
-    for (long t = 0; t < M; t++) f[t] = st->phif[t] + st->Da * st->dphi[t];
+    for (long t = 0; t < M; t++) f[t] = st->phif[t] + st->dphi[t];
     orc_fft3d((double *)f, n, -1);
     st->F = malloc(sizeof(double) * 3 * M);
     cplx *g = malloc(sizeof(cplx) * M);
@@ -337,20 +329,16 @@ int orc_learned_loss(const orc_sim *s, const double *th, double a, const double 
     double *phibar = malloc(sizeof(double) * M);
     for (long t = 0; t < M; t++) phibar[t] = creal(pb[t]) / (double)M;
     free(Fbar);
-    /* phi = phif + Da cnn(phif / Da) */
+    /* phi = phif + cnn(delta); delta does not depend on the parameters */
     double *d2 = malloc(sizeof(double) * NET_C * M), *d1 = malloc(sizeof(double) * NET_C * M);
-    double *dout = malloc(sizeof(double) * M), *dpsi = calloc(M, sizeof(double));
-    for (long t = 0; t < M; t++) dout[t] = st.Da * phibar[t];
+    double *ddelta = calloc(M, sizeof(double));   /* unused: delta is not a parameter */
     memset(d2, 0, sizeof(double) * NET_C * M);
-    orc_conv3_vjp(st.a2, NET_C, th + NET_C3W, 1, n, dout, d2, dth + NET_C3W, dth + NET_C3B);
+    orc_conv3_vjp(st.a2, NET_C, th + NET_C3W, 1, n, phibar, d2, dth + NET_C3W, dth + NET_C3B);
     for (long t = 0; t < NET_C * M; t++) d2[t] *= dsilu(st.z2[t]);
     memset(d1, 0, sizeof(double) * NET_C * M);
     orc_conv3_vjp(st.a1, NET_C, th + NET_C2W, NET_C, n, d2, d1, dth + NET_C2W, dth + NET_C2B);
     for (long t = 0; t < NET_C * M; t++) d1[t] *= dsilu(st.z1[t]);
-    double *psi = malloc(sizeof(double) * M);
-    for (long t = 0; t < M; t++) psi[t] = st.phif[t] / st.Da;
-    orc_conv3_vjp(psi, 1, th + NET_C1W, NET_C, n, d1, dpsi, dth + NET_C1W, dth + NET_C1B);
-    for (long t = 0; t < M; t++) phibar[t] += dpsi[t] / st.Da;
+    orc_conv3_vjp(st.delta, 1, th + NET_C1W, NET_C, n, d1, ddelta, dth + NET_C1W, dth + NET_C1B);
     /* phif = F^-1 [g G F delta] / M:  dL/dg(k) = Re[G_k dk_k conj(F phibar)_k] / M
      * per mode of the full spectrum, distributed to the two table bins */
     for (long t = 0; t < M; t++) h[t] = phibar[t];
@@ -371,7 +359,7 @@ int orc_learned_loss(const orc_sim *s, const double *th, double a, const double 
         tbar[b0 + 1] += w * dg;
     }
     orc_net_table_vjp(th, a, tbar, dth);
-    free(pb); free(h); free(phibar); free(d2); free(d1); free(dout); free(dpsi); free(psi); free(acc);
+    free(pb); free(h); free(phibar); free(d2); free(d1); free(ddelta); free(acc);
     free_state(&st);
     return 0;
 }

@@ -348,8 +348,8 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
     const int ncb = (int)(nhp / pm::TILE_W);
     const double M = (double)n2 * n;
     float2 *F = c->ws.f;
-    const double Da = pm::growth_D(*c, a) / pm::growth_D(*c, 1.0);
-    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, F, nhp, n2, ldexp(1.0, -c->cfg.shift), -1.0, c->ws.tw,
+    const double qs = ldexp(1.0, -c->cfg.shift);
+    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, F, nhp, n2, qs, -1.0, c->ws.tw,
                                               c->ws.flag, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
@@ -362,11 +362,12 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
     float *Fr = reinterpret_cast<float *>(F);
     if (keep) {
         // the reverse mode needs every pre-activation and activation
-        LAUNCH(pm::K_NET, pm::launch_cnn_fwd(c->ws.net_phif, rs, n, 1.0 / Da, th, c->ws.net_z1, c->ws.net_a1,
-                                             c->ws.net_z2, c->ws.net_a2, c->ws.net_dpsi, s));
-        LAUNCH(pm::K_NET, pm::launch_combine(c->ws.net_phif, c->ws.net_dpsi, rs, n, Da, Fr, s));
+        LAUNCH(pm::K_NET, pm::launch_cnn_fwd(c->ws.q, qs, n, th, c->ws.net_z1, c->ws.net_a1, c->ws.net_z2,
+                                             c->ws.net_a2, c->ws.net_dpsi, s));
+        LAUNCH(pm::K_NET, pm::launch_combine(c->ws.net_phif, c->ws.net_dpsi, rs, n, Fr, s));
     } else {
-        LAUNCH(pm::K_NET, pm::launch_cnn_inf(c->ws.net_phif, rs, n, Da, th, c->ws.net_wpk, c->ws.net_a2, Fr, s));
+        LAUNCH(pm::K_NET, pm::launch_cnn_inf(c->ws.q, qs, c->ws.net_phif, rs, n, th, c->ws.net_wpk, c->ws.net_a2, Fr,
+                                             s));
     }
     LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, Fr, rs, F, nhp, n2, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
@@ -1053,7 +1054,6 @@ pm_status pm_learned_loss(pm_ctx *c, const float *th, double a, const float *x, 
     *loss = red[0] / red[1];
     if (!dth) return check_guards(c, s);
     // readout transpose, gradient transpose, CNN and filter reverse mode
-    const double Da = pm::growth_D(*c, a) / pm::growth_D(*c, 1.0);
     LAUNCH(pm::K_FILL, pm::launch_fill_i64(reinterpret_cast<int64_t *>(F), 3 * cs, s));
     LAUNCH(pm::K_ADJOINT, pm::launch_paint_vec3(x, c->P, c->ws.net_acc, (float)(2.0 / red[1]), Fr, rs, 2 * cs, n, s));
     for (int d = 0; d < 3; d++) {
@@ -1066,8 +1066,8 @@ pm_status pm_learned_loss(pm_ctx *c, const float *th, double a, const float *x, 
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F, nhp, Fr, rs, n2, c->ws.tw, s));
-    LAUNCH(pm::K_NET, pm::launch_cnn_bwd(c->ws.net_phif, Fr, rs, n, Da, th, c->ws.net_z1, c->ws.net_a1, c->ws.net_z2,
-                                         c->ws.net_a2, c->ws.net_g1, c->ws.net_g2, Fr, dth, s));
+    LAUNCH(pm::K_NET, pm::launch_cnn_bwd(c->ws.q, ldexp(1.0, -c->cfg.shift), Fr, rs, n, th, c->ws.net_z1,
+                                         c->ws.net_a1, c->ws.net_z2, c->ws.net_a2, c->ws.net_g1, c->ws.net_g2, dth, s));
     LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, Fr, rs, F, nhp, n2, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));

@@ -4,8 +4,8 @@
 // learned corrections of fast particle-mesh codes): a radial filter
 // g(k, a) = 1 + MLP(|k| / k_Nyq, a) on the potential spectrum, tabulated at
 // NET_NB radial bins and interpolated linearly, and a 3-layer periodic 3^3
-// CNN (1 -> 16 -> 16 -> 1 channels, SiLU) on the filtered potential scaled by
-// 1 / D(a); the force is minus the spectral gradient of phi_f + D(a) cnn.
+// CNN (1 -> 16 -> 16 -> 1 channels, SiLU) on the density contrast (read from
+// the int64 mesh); the force is minus the spectral gradient of phi_f + cnn.
 // Parameters: one flat FP32 array (offsets in pm_internal.h).  The CNN takes
 // BF16 activations and weights and accumulates in FP32; the 16 -> 16 layer,
 // 89 % of the network's arithmetic, runs on MFMA (16x16x16 BF16 tiles).
@@ -254,9 +254,12 @@ __device__ __forceinline__ int64_t nb_voxel(int i0, int i1, int i2, int t, int n
     return ((int64_t)((i0 + t / 9 - 1) & m) * n + ((i1 + (t / 3) % 3 - 1) & m)) * n + ((i2 + t % 3 - 1) & m);
 }
 
-// conv1: psi = s phi_f (real rows of stride rs) rounded to BF16 -> z1 (FP32),
+// The CNN input: density contrast q 2^-S - 1 of the int64 mesh, rounded to BF16.
+__device__ __forceinline__ uint16_t delta_bf16(int64_t q, double qs) { return to_bf16((float)((double)q * qs - 1.0)); }
+
+// conv1: delta (int64 mesh q, quantum qs) rounded to BF16 -> z1 (FP32),
 // a1 = SiLU(z1) (BF16), 16 channels per voxel.
-__global__ __launch_bounds__(256) void k_conv1_fwd(const float *__restrict__ phif, int64_t rs, int n, float s,
+__global__ __launch_bounds__(256) void k_conv1_fwd(const int64_t *__restrict__ q, double qs, int n,
                                                    const float *__restrict__ th, float *z1, uint16_t *a1)
 {
     __shared__ float W[NET_C * 27], B[NET_C];
@@ -269,8 +272,7 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float *__restrict__ phi
         float x[27];
 #pragma unroll
         for (int t = 0; t < 27; t++) {
-            const int64_t u = nb_voxel(i0, i1, i2, t, n);
-            x[t] = bf16r(s * phif[(u / n) * rs + u % n]);
+            x[t] = from_bf16(delta_bf16(q[nb_voxel(i0, i1, i2, t, n)], qs));
         }
         float z[NET_C];
 #pragma unroll
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(256) void k_conv3_fwd(const uint16_t *__restrict__ 
 // ---- inference path: no pre-activations kept, a1 never leaves LDS
 // conv1 + conv2.  The 16 x 8 x 4 output tile of conv2 needs a1 on the tile
 // and its one-voxel halo (C2HALO voxels); conv1 computes those on MFMA from
-// psi on a two-voxel halo, staged in LDS as BF16.  Per group of 16 halo
+// delta on a two-voxel halo, staged in LDS as BF16.  Per group of 16 halo
 // voxels: D[co][vox] = W1[co][tap] U[tap][vox] over 32 taps (27 real, 5 zero
 // weights and zero data), two 16x16x16 MFMAs.  conv2 as k_conv2_fwd with the
 // 27 weight fragments in registers; only a2 (BF16) is written.
@@ -420,7 +422,7 @@ constexpr int NG1 = (C2HALO + 15) / 16;
 
 __device__ __forceinline__ int u1_off(int t) { return ((t / 9) * U1Y + (t / 3) % 3) * U1X + t % 3; }
 
-__global__ __launch_bounds__(256) void k_cnn12_inf(const float *__restrict__ phif, int64_t rs, int n, float s,
+__global__ __launch_bounds__(256) void k_cnn12_inf(const int64_t *__restrict__ q, double qs, int n,
                                                    const float *__restrict__ th, const uint16_t *__restrict__ wpk,
                                                    uint16_t *a2)
 {
@@ -444,7 +446,7 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const float *__restrict__ phi
     for (int e = tid; e < U1N; e += 256) {
         const int ux = e % U1X, uy = (e / U1X) % U1Y, uz = e / (U1X * U1Y);
         const int64_t row = (int64_t)((z0 + uz - 2) & m) * n + ((y0 + uy - 2) & m);
-        U[e] = to_bf16(s * phif[row * rs + ((x0 + ux - 2) & m)]);
+        U[e] = delta_bf16(q[row * n + ((x0 + ux - 2) & m)], qs);
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
@@ -511,7 +513,7 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const float *__restrict__ phi
     }
 }
 
-// conv3 fused with the combination: out = phi_f + D(a) (b3 + conv3(a2)) on
+// conv3 fused with the combination: out = phi_f + b3 + conv3(a2) on
 // real rows of stride rs.  Tile 16 x 16 x 4 with a2's one-voxel halo in LDS;
 // a thread owns a column of 4 voxels along axis 0, so each halo voxel it reads
 // feeds up to three taps.
@@ -520,7 +522,7 @@ constexpr int C3HALO = C3HX * C3HY * C3HZ;
 
 __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ a2, int n,
                                                    const float *__restrict__ th, const uint16_t *__restrict__ wpk,
-                                                   const float *__restrict__ phif, int64_t rs, float Da, float *out)
+                                                   const float *__restrict__ phif, int64_t rs, float *out)
 {
     // channel halves of each halo voxel in two planes: 16-byte rows, no bank conflicts
     __shared__ __align__(16) uint4 X[2 * C3HALO];
@@ -572,25 +574,25 @@ __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ 
 #pragma unroll
     for (int z = 0; z < C3Z; z++) {
         const int64_t o = ((int64_t)(z0 + z) * n + (y0 + ly)) * rs + (x0 + lx);
-        out[o] = phif[o] + Da * acc[z];
+        out[o] = phif[o] + acc[z];
     }
 }
 
-// phi = phi_f + D(a) dpsi on real rows of stride rs.
-__global__ void k_combine(const float *phif, const float *dpsi, int64_t rs, int n, float Da, float *out)
+// phi = phi_f + dpsi on real rows of stride rs.
+__global__ void k_combine(const float *phif, const float *dpsi, int64_t rs, int n, float *out)
 {
     const int64_t M = (int64_t)n * n * n;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < M; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t o = (v / n) * rs + v % n;
-        out[o] = phif[o] + Da * dpsi[v];
+        out[o] = phif[o] + dpsi[v];
     }
 }
 
 // ---- reverse mode of the CNN
-// conv3 data: g2[v][ci] = dsilu(z2[v][ci]) sum_t W3[ci][t] dout(v - o(t)),
-// dout = D(a) phibar on real rows of stride rs.
+// conv3 data: g2[v][ci] = dsilu(z2[v][ci]) sum_t W3[ci][t] phibar(v - o(t)),
+// phibar on real rows of stride rs.
 __global__ __launch_bounds__(256) void k_conv3_bwd_data(const float *__restrict__ phibar, int64_t rs, int n,
-                                                        float Da, const float *__restrict__ th,
+                                                        const float *__restrict__ th,
                                                         const float *__restrict__ z2, float *g2)
 {
     __shared__ float W[27 * NET_C];   // [t][ci]
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(256) void k_conv3_bwd_data(const float *__restrict_
         for (int c = 0; c < NET_C; c++) acc[c] = 0.f;
         for (int t = 0; t < 27; t++) {
             const int64_t u = nb_voxel(i0, i1, i2, 26 - t, n);   // v - o(t)
-            const float d = Da * phibar[(u / n) * rs + u % n];
+            const float d = phibar[(u / n) * rs + u % n];
 #pragma unroll
             for (int c = 0; c < NET_C; c++) acc[c] += W[t * NET_C + c] * d;
         }
@@ -663,43 +665,14 @@ __global__ __launch_bounds__(256) void k_conv2_bwd_data(const float *__restrict_
     }
 }
 
-// conv1 data: phibar_f(v) += s sum_{co,t} W1[co][t] g1[v - o(t)][co] on real rows.
-__global__ __launch_bounds__(256) void k_conv1_bwd_data(const float *__restrict__ g1, int n,
-                                                        const float *__restrict__ th, float s, float *phibar,
-                                                        int64_t rs)
-{
-    __shared__ float W[27 * NET_C];   // [t][co]
-    for (int e = threadIdx.x; e < 27 * NET_C; e += blockDim.x) {
-        const int t = e / NET_C, co = e % NET_C;
-        W[e] = bf16r(th[NC1W + co * 27 + t]);
-    }
-    __syncthreads();
-    const int64_t M = (int64_t)n * n * n;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < M; v += (int64_t)gridDim.x * blockDim.x) {
-        const int i2 = (int)(v % n), i1 = (int)((v / n) % n), i0 = (int)(v / ((int64_t)n * n));
-        float acc = 0.f;
-        for (int t = 0; t < 27; t++) {
-            const int64_t u = nb_voxel(i0, i1, i2, 26 - t, n);
-            const float4 *gp = reinterpret_cast<const float4 *>(g1 + u * NET_C);
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const float4 gv = gp[q];
-                acc += W[t * NET_C + 4 * q] * gv.x + W[t * NET_C + 4 * q + 1] * gv.y +
-                       W[t * NET_C + 4 * q + 2] * gv.z + W[t * NET_C + 4 * q + 3] * gv.w;
-            }
-        }
-        phibar[(v / n) * rs + v % n] += s * acc;
-    }
-}
-
 // Weight gradients dW[co][ci][t] += sum_v in_ci(v + o(t)) dout_co(v), db[co] += sum_v dout_co(v).
-// in: KIN 0 = real rows (stride rs, times s, rounded to BF16: the conv1 input),
-//     KIN 1 = BF16 [v][16]; dout: KOUT 0 = real rows times s_out (conv3), KOUT 1 = FP32 [v][16].
+// in: KIN 0 = the int64 density mesh as BF16 delta (quantum qs: the conv1 input),
+//     KIN 1 = BF16 [v][16]; dout: KOUT 0 = real rows of stride rs_out (conv3), KOUT 1 = FP32 [v][16].
 // A workgroup walks tiles of 16 x 8 x 4 voxels with LDS copies of the input
 // halo and the output gradient; each thread owns CO CI 27 / 256 entries.
 template <int CI, int CO, int KIN, int KOUT>
-__global__ __launch_bounds__(256) void k_conv_bwd_w(const void *in_, int64_t rs_in, float s_in, const void *dout_,
-                                                    int64_t rs_out, float s_out, int n, float *dW, float *db)
+__global__ __launch_bounds__(256) void k_conv_bwd_w(const void *in_, double qs, const void *dout_, int64_t rs_out,
+                                                    int n, float *dW, float *db)
 {
     constexpr int NE = CO * CI * 27, PER = (NE + 255) / 256;
     __shared__ float Xs[C2HALO * CI];
@@ -719,7 +692,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const void *in_, int64_t rs_
             const int64_t g = ((int64_t)((z0 + hz - 1) & m) * n + ((y0 + hy - 1) & m)) * n + ((x0 + hx - 1) & m);
             float val;
             if constexpr (KIN == 0)
-                val = bf16r(s_in * reinterpret_cast<const float *>(in_)[(g / n) * rs_in + g % n]);
+                val = from_bf16(delta_bf16(reinterpret_cast<const int64_t *>(in_)[g], qs));
             else
                 val = from_bf16(reinterpret_cast<const uint16_t *>(in_)[g * CI + ci]);
             Xs[e] = val;
@@ -730,7 +703,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const void *in_, int64_t rs_
             const int64_t g = ((int64_t)(z0 + lz) * n + (y0 + ly)) * n + (x0 + lx);
             float val;
             if constexpr (KOUT == 0)
-                val = s_out * reinterpret_cast<const float *>(dout_)[(g / n) * rs_out + g % n];
+                val = reinterpret_cast<const float *>(dout_)[(g / n) * rs_out + g % n];
             else
                 val = reinterpret_cast<const float *>(dout_)[g * CO + co];
             Gs[e] = val;
@@ -857,59 +830,55 @@ hipError_t launch_grad3(float2 *F, int64_t nhp, int64_t fs, int n, double scale,
     return hipGetLastError();
 }
 
-hipError_t launch_cnn_fwd(const float *phif, int64_t rs, int n, double inv_Da, const float *th, float *z1,
-                          uint16_t *a1, float *z2, uint16_t *a2, float *dpsi, hipStream_t s)
+hipError_t launch_cnn_fwd(const int64_t *q, double qs, int n, const float *th, float *z1, uint16_t *a1, float *z2,
+                          uint16_t *a2, float *dpsi, hipStream_t s)
 {
     if (n < C2X || n % C2X) return hipErrorInvalidValue;
     const int64_t M = (int64_t)n * n * n;
-    hipLaunchKernelGGL(k_conv1_fwd, dim3(grid_for(M, 256)), dim3(256), 0, s, phif, rs, n, (float)inv_Da, th, z1, a1);
+    hipLaunchKernelGGL(k_conv1_fwd, dim3(grid_for(M, 256)), dim3(256), 0, s, q, qs, n, th, z1, a1);
     hipLaunchKernelGGL(k_conv2_fwd, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, a1, n, th, z2, a2);
     hipLaunchKernelGGL(k_conv3_fwd, dim3(grid_for(M, 256)), dim3(256), 0, s, a2, n, th, dpsi);
     return hipGetLastError();
 }
 
-hipError_t launch_cnn_inf(const float *phif, int64_t rs, int n, double Da, const float *th, uint16_t *wpk,
-                          uint16_t *a2, float *out, hipStream_t s)
+hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *phif, int64_t rs, int n, const float *th,
+                          uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s)
 {
     if (n < C3Y || n % C3Y || n % C3Z) return hipErrorInvalidValue;
     const int64_t M = (int64_t)n * n * n;
     hipLaunchKernelGGL(k_pack_w, dim3(1), dim3(256), 0, s, th, wpk);
-    hipLaunchKernelGGL(k_cnn12_inf, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, phif, rs, n,
-                       (float)(1.0 / Da), th, wpk, a2);
+    hipLaunchKernelGGL(k_cnn12_inf, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, q, qs, n, th, wpk, a2);
     hipLaunchKernelGGL(k_conv3_inf, dim3((unsigned)(M / (C3X * C3Y * C3Z))), dim3(256), 0, s, a2, n, th, wpk, phif,
-                       rs, (float)Da, out);
+                       rs, out);
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int n, double Da, float *out,
-                          hipStream_t s)
+hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int n, float *out, hipStream_t s)
 {
     const int64_t M = (int64_t)n * n * n;
-    hipLaunchKernelGGL(k_combine, dim3(grid_for(M, 256)), dim3(256), 0, s, phif, dpsi, rs, n, (float)Da, out);
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(M, 256)), dim3(256), 0, s, phif, dpsi, rs, n, out);
     return hipGetLastError();
 }
 
-hipError_t launch_cnn_bwd(const float *phif, const float *phibar, int64_t rs, int n, double Da, const float *th,
+hipError_t launch_cnn_bwd(const int64_t *q, double qs, const float *phibar, int64_t rs, int n, const float *th,
                           const float *z1, const uint16_t *a1, const float *z2, const uint16_t *a2, float *g1,
-                          float *g2, float *phibar_f, float *dth, hipStream_t s)
+                          float *g2, float *dth, hipStream_t s)
 {
     if (n < C2X || n % C2X) return hipErrorInvalidValue;
     const int64_t M = (int64_t)n * n * n;
     const int ntiles = (int)(M / (C2X * C2Y * C2Z));
     const unsigned gw = (unsigned)(ntiles < 2048 ? ntiles : 2048);
-    const float fDa = (float)Da, inv = (float)(1.0 / Da);
-    // conv3: dW3, db3 from a2 and D(a) phibar; g2 = dsilu(z2) W3^T dout
-    hipLaunchKernelGGL((k_conv_bwd_w<NET_C, 1, 1, 0>), dim3(gw), dim3(256), 0, s, (const void *)a2, (int64_t)0, 1.f,
-                       (const void *)phibar, rs, fDa, n, dth + NC3W, dth + NC3B);
-    hipLaunchKernelGGL(k_conv3_bwd_data, dim3(grid_for(M, 256)), dim3(256), 0, s, phibar, rs, n, fDa, th, z2, g2);
+    // conv3: dW3, db3 from a2 and phibar; g2 = dsilu(z2) W3^T phibar
+    hipLaunchKernelGGL((k_conv_bwd_w<NET_C, 1, 1, 0>), dim3(gw), dim3(256), 0, s, (const void *)a2, 0.0,
+                       (const void *)phibar, rs, n, dth + NC3W, dth + NC3B);
+    hipLaunchKernelGGL(k_conv3_bwd_data, dim3(grid_for(M, 256)), dim3(256), 0, s, phibar, rs, n, th, z2, g2);
     // conv2
-    hipLaunchKernelGGL((k_conv_bwd_w<NET_C, NET_C, 1, 1>), dim3(gw), dim3(256), 0, s, (const void *)a1, (int64_t)0,
-                       1.f, (const void *)g2, (int64_t)0, 1.f, n, dth + NC2W, dth + NC2B);
+    hipLaunchKernelGGL((k_conv_bwd_w<NET_C, NET_C, 1, 1>), dim3(gw), dim3(256), 0, s, (const void *)a1, 0.0,
+                       (const void *)g2, (int64_t)0, n, dth + NC2W, dth + NC2B);
     hipLaunchKernelGGL(k_conv2_bwd_data, dim3(grid_for(M, 256)), dim3(256), 0, s, g2, n, th, z1, g1);
-    // conv1: input psi = phif / D(a)
-    hipLaunchKernelGGL((k_conv_bwd_w<1, NET_C, 0, 1>), dim3(gw), dim3(256), 0, s, (const void *)phif, rs, inv,
-                       (const void *)g1, (int64_t)0, 1.f, n, dth + NC1W, dth + NC1B);
-    hipLaunchKernelGGL(k_conv1_bwd_data, dim3(grid_for(M, 256)), dim3(256), 0, s, g1, n, th, inv, phibar_f, rs);
+    // conv1 weights from delta; delta does not depend on the parameters
+    hipLaunchKernelGGL((k_conv_bwd_w<1, NET_C, 0, 1>), dim3(gw), dim3(256), 0, s, (const void *)q, qs,
+                       (const void *)g1, (int64_t)0, n, dth + NC1W, dth + NC1B);
     return hipGetLastError();
 }
 

@@ -215,18 +215,18 @@ hipError_t launch_spec_filter(const float2 *in, float2 *out, int64_t nhp, int n,
 hipError_t launch_spec_filter_bwd(const float2 *dk, const float2 *pf, int64_t nhp, int n, double coef, double *tbar,
                                   hipStream_t s);
 hipError_t launch_grad3(float2 *F, int64_t nhp, int64_t fs, int n, double scale, bool transpose, hipStream_t s);
-hipError_t launch_cnn_fwd(const float *phif, int64_t rs, int n, double inv_Da, const float *th, float *z1,
-                          uint16_t *a1, float *z2, uint16_t *a2, float *dpsi, hipStream_t s);
-hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int n, double Da, float *out,
-                          hipStream_t s);
-// Inference CNN fused with the combination: out = phi_f + D(a) cnn(phi_f / D(a))
-// on real rows; a2: BF16 [n^3][16] scratch, wpk: NET_WPK_BYTES scratch for the
+// CNN input: the int64 density mesh q with quantum qs (delta = q qs - 1).
+hipError_t launch_cnn_fwd(const int64_t *q, double qs, int n, const float *th, float *z1, uint16_t *a1, float *z2,
+                          uint16_t *a2, float *dpsi, hipStream_t s);
+hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int n, float *out, hipStream_t s);
+// Inference CNN fused with the combination: out = phi_f + cnn(delta) on real
+// rows; a2: BF16 [n^3][16] scratch, wpk: NET_WPK_BYTES scratch for the
 // repacked weights.  n a multiple of 16.
-hipError_t launch_cnn_inf(const float *phif, int64_t rs, int n, double Da, const float *th, uint16_t *wpk,
-                          uint16_t *a2, float *out, hipStream_t s);
-hipError_t launch_cnn_bwd(const float *phif, const float *phibar, int64_t rs, int n, double Da, const float *th,
+hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *phif, int64_t rs, int n, const float *th,
+                          uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s);
+hipError_t launch_cnn_bwd(const int64_t *q, double qs, const float *phibar, int64_t rs, int n, const float *th,
                           const float *z1, const uint16_t *a1, const float *z2, const uint16_t *a2, float *g1,
-                          float *g2, float *phibar_f, float *dth, hipStream_t s);
+                          float *g2, float *dth, hipStream_t s);
 hipError_t launch_force_loss(float *acc, const float *target, int64_t n3, double *red, hipStream_t s);
 hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t n, double lr, double b1, double b2,
                        double eps, int t, hipStream_t s);

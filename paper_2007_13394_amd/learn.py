@@ -20,7 +20,8 @@ the least-squares filter shrinks the force there and the runs lose power.
 `calibrate` therefore also fits the radial filter to the power spectra of the
 fine-mesh runs of the training seeds: repeated coarse learned runs, and a
 damped multiplicative update g <- g (P_fine / P_learned)^0.4 onto which the
-MLP is regressed with Adam (the CNN output stays zero).
+MLP is regressed with Adam, starting from the force-matched network (the CNN
+keeps its weights).
 """
 import time
 
@@ -246,11 +247,11 @@ def calibrate(cc, seeds, fine_x, theta, rounds=16, power=0.4, fit_steps=1000, de
 
 def judge(coarse_name, fine_name, train_seeds, test_seed, snap_every=5, iters=400, lr=2e-3, device="cuda",
           log=print, calib_rounds=16):
-    """Train the network on fine-mesh force pairs (force matching) and,
-    separately, calibrate the radial filter on the training seeds' fine-mesh
-    spectra; then compare both learned coarse models, plain coarse and plain
-    fine runs from a held-out seed.  "learned" in the result is the
-    calibrated model.  Returns a dict."""
+    """Train the network on fine-mesh force pairs (force matching), then
+    calibrate its radial filter on the training seeds' fine-mesh spectra;
+    compare the force-matched and the calibrated coarse models with plain
+    coarse and plain fine runs from a held-out seed.  "learned" in the result
+    is the calibrated model.  Returns a dict."""
     cc, cf = I.config(coarse_name), I.config(fine_name)
     ratio = cf["n_mesh"] // cc["n_mesh"]
     cf = dict(cf, coarse_mesh=cc["n_mesh"])
@@ -275,7 +276,7 @@ def judge(coarse_name, fine_name, train_seeds, test_seed, snap_every=5, iters=40
     t0 = time.perf_counter()
     ctx_f = pm.Ctx(pm.make_config(cf))
     fine_x = [simulate(ctx_f, cf, s, device, scale=ratio)[0] for s in train_seeds]
-    theta_cal = init_params(1, device)
+    theta_cal = theta.clone()   # the force-matched network; the calibration moves the filter only
     calib_hist = calibrate(cc, train_seeds, fine_x, theta_cal, rounds=calib_rounds, device=device, log=log)
     t_cal = time.perf_counter() - t0
     del fine_x
