@@ -133,6 +133,26 @@ def cpu_baseline(P_target, n_target):
     }
 
 
+def learned_speed(steps=10):
+    """Live speed half of the learned-vs-plain comparison (C4, 19 070 976
+    particles): learned steps on the 256^3 mesh against plain steps on the
+    256^3 and 1024^3 meshes, tile-sorted contexts.  The accuracy half needs
+    training and is measured by `python -m paper_2007_13394_amd.learn`."""
+    from paper_2007_13394_amd import learn
+    co = learn.time_steps("C4_coarse", steps)
+    fi = learn.time_steps("C4_fine", steps, which=("plain",))
+    return {"workload": "C4: 256^3 CDM + 32^3 sites x 70 neutrinos, L=256 Mpc/h; learned correction on a 256^3 "
+                        "mesh vs plain PM on a 1024^3 mesh",
+            "particles": co["particles"], "steps_timed": steps,
+            "learned_coarse_ms_per_step": round(co["learned_ms_per_step"], 3),
+            "plain_coarse_ms_per_step": round(co["plain_ms_per_step"], 3),
+            "plain_fine_ms_per_step": round(fi["plain_ms_per_step"], 3),
+            "learned_particle_steps_per_s": co["particles"] / (co["learned_ms_per_step"] * 1e-3),
+            "speedup_vs_fine": round(fi["plain_ms_per_step"] / co["learned_ms_per_step"], 2),
+            "accuracy": "measured by python -m paper_2007_13394_amd.learn (trains, then judges P(k) on held-out "
+                        "seeds); not run here"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +160,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain step timing (C4)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -242,10 +263,14 @@ def main():
                           "frac": round(step_bytes / (HBM_PEAK_GBS * 1e9) / (ms_per_step * 1e-3), 4)},
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in sorted(kernels.items())},
     }
+    del ctx, x, p
+    torch.cuda.empty_cache()
+    if not args.no_learned and args.config == "C3":
+        log("[bench] timing learned (256^3 mesh) and plain (256^3, 1024^3 meshes) steps on C4")
+        out["learned_vs_plain"] = learned_speed()
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
-        del ctx, x, p
-        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(P, n)
     print(json.dumps(out), flush=True)
 

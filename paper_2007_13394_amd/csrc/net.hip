@@ -17,6 +17,7 @@ namespace {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // sum + a.lo b.lo + a.hi b.hi for BF16 pairs, FP32 accumulation
 __device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float sum)
@@ -389,25 +390,33 @@ __global__ __launch_bounds__(256) void k_conv3_fwd(const uint16_t *__restrict__ 
 }
 
 // ---- inference path: no pre-activations kept, a1 never leaves LDS
-// conv1 + conv2.  The 16 x 8 x 4 output tile of conv2 needs a1 on the tile
-// and its one-voxel halo (C2HALO voxels); conv1 computes those on MFMA from
-// delta on a two-voxel halo, staged in LDS as BF16.  Per group of 16 halo
-// voxels: D[co][vox] = W1[co][tap] U[tap][vox] over 32 taps (27 real, 5 zero
-// weights and zero data), two 16x16x16 MFMAs.  conv2 as k_conv2_fwd with the
-// 27 weight fragments in registers; only a2 (BF16) is written.
+// conv1 + conv2 on v_mfma_f32_16x16x32_bf16 (K = 32; lane l holds
+// A[row l % 16][k 8 (l / 16) + j], B[k 8 (l / 16) + j][col l % 16] and
+// D[row 4 (l / 16) + r][col l % 16]).  The 16 x 8 x 4 output tile of conv2
+// needs a1 on the tile and its one-voxel halo (C2HALO voxels); conv1 computes
+// those from delta on a two-voxel halo staged in LDS as BF16, one MFMA per 16
+// halo voxels: D[co][vox] = W1[co][tap] U[tap][vox] over 32 taps (27 real,
+// weights zero past 26).  a1 sits in LDS as two planes of 8 channels (16 bytes
+// per voxel), so the 16 lanes of a K group read 256 contiguous bytes.  conv2
+// takes two taps per MFMA: k = 8 kg + j is tap 2 p + kg / 2, channel
+// 8 (kg % 2) + j, so 14 MFMAs cover 27 taps (the 28th has zero weights); the
+// 14 weight fragments live in registers.  Only a2 (BF16) is written.
 constexpr int U1X = C2X + 4, U1Y = C2Y + 4, U1Z = C2Z + 4, U1N = U1X * U1Y * U1Z;
-// Inference weights repacked once per call (byte offsets in wpk): conv2 BF16
-// [t][co][ci], conv1 BF16 [co][32 taps, zero past 27], conv3 BF16 [t][ci].
-constexpr int WPK_W2 = 0, WPK_W1 = 27 * NET_C * NET_C * 2, WPK_W3 = WPK_W1 + NET_C * 32 * 2,
+constexpr int NG1 = (C2HALO + 15) / 16, NPAIR = 14;
+// Inference weights repacked once per call (byte offsets in wpk): conv2 as
+// MFMA A fragments [pair][co][kg][8] BF16, conv1 [co][32 taps] BF16, conv3
+// [t][ci] BF16.
+constexpr int WPK_W2 = 0, WPK_W1 = NPAIR * NET_C * 4 * 8 * 2, WPK_W3 = WPK_W1 + NET_C * 32 * 2,
               WPK_END = WPK_W3 + 27 * NET_C * 2;
 static_assert(WPK_END <= NET_WPK_BYTES && WPK_W1 % 16 == 0 && WPK_W3 % 16 == 0, "packed weight layout");
 
 __global__ __launch_bounds__(256) void k_pack_w(const float *__restrict__ th, uint16_t *wpk)
 {
     uint16_t *w2 = wpk + WPK_W2 / 2, *w1 = wpk + WPK_W1 / 2, *w3 = wpk + WPK_W3 / 2;
-    for (int e = threadIdx.x; e < 27 * NET_C * NET_C; e += 256) {
-        const int co = e / (27 * NET_C), ci = (e / 27) % NET_C, t = e % 27;
-        w2[(t * NET_C + co) * NET_C + ci] = to_bf16(th[NC2W + e]);
+    for (int e = threadIdx.x; e < NPAIR * NET_C * 4 * 8; e += 256) {
+        const int pr = e / (NET_C * 32), co = (e / 32) % NET_C, kg = (e / 8) % 4, j = e % 8;
+        const int t = 2 * pr + kg / 2, ci = 8 * (kg % 2) + j;
+        w2[e] = t < 27 ? to_bf16(th[NC2W + (co * NET_C + ci) * 27 + t]) : (uint16_t)0;
     }
     for (int e = threadIdx.x; e < NET_C * 32; e += 256) {
         const int co = e / 32, t = e % 32;
@@ -418,91 +427,82 @@ __global__ __launch_bounds__(256) void k_pack_w(const float *__restrict__ th, ui
         w3[e] = to_bf16(th[NC3W + ci * 27 + t]);
     }
 }
-constexpr int NG1 = (C2HALO + 15) / 16;
 
 __device__ __forceinline__ int u1_off(int t) { return ((t / 9) * U1Y + (t / 3) % 3) * U1X + t % 3; }
+__device__ __forceinline__ int x_off(int t) { return ((t / 9) * C2HY + (t / 3) % 3) * C2HX + t % 3; }
 
 __global__ __launch_bounds__(256) void k_cnn12_inf(const int64_t *__restrict__ q, double qs, int n,
                                                    const float *__restrict__ th, const uint16_t *__restrict__ wpk,
                                                    uint16_t *a2)
 {
     __shared__ __align__(16) uint16_t U[U1N];
-    __shared__ __align__(16) uint16_t X[C2HALO * NET_C];
-    __shared__ __align__(16) uint16_t W2s[27 * NET_C * NET_C];
-    __shared__ __align__(16) uint16_t W1s[NET_C * 32];
-    __shared__ float B1[NET_C], B2[NET_C];
+    __shared__ __align__(16) uint4 X[2 * C2HALO];   // channel planes 0-7 and 8-15
     const int tid = threadIdx.x;
     const int ntx = n / C2X, nty = n / C2Y;
     const int tile = blockIdx.x;
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
     const int x0 = tx * C2X, y0 = ty * C2Y, z0 = tz * C2Z, m = n - 1;
-    for (int e = tid; e < WPK_W3 / 16; e += 256)   // conv2 then conv1 weights, adjacent in LDS and wpk
-        reinterpret_cast<uint4 *>(e < WPK_W1 / 16 ? W2s : W1s)[e < WPK_W1 / 16 ? e : e - WPK_W1 / 16] =
-            reinterpret_cast<const uint4 *>(wpk)[e];
-    if (tid < NET_C) {
-        B1[tid] = th[NC1B + tid];
-        B2[tid] = th[NC2B + tid];
-    }
+    const int lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, kg = lane >> 4;
+    // weight fragments straight from the packed buffer (L2-resident)
+    const v8bf w1 = *reinterpret_cast<const v8bf *>(wpk + WPK_W1 / 2 + col * 32 + 8 * kg);
+    v8bf wa[NPAIR];
+#pragma unroll
+    for (int pr = 0; pr < NPAIR; pr++)
+        wa[pr] = *reinterpret_cast<const v8bf *>(wpk + WPK_W2 / 2 + ((pr * NET_C + col) * 4 + kg) * 8);
     for (int e = tid; e < U1N; e += 256) {
         const int ux = e % U1X, uy = (e / U1X) % U1Y, uz = e / (U1X * U1Y);
         const int64_t row = (int64_t)((z0 + uz - 2) & m) * n + ((y0 + uy - 2) & m);
         U[e] = delta_bf16(q[row * n + ((x0 + ux - 2) & m)], qs);
     }
     __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6;
-    const int col = lane & 15, kg = lane >> 4;
     {
-        const v4s w1a = *reinterpret_cast<const v4s *>(W1s + col * 32 + 4 * kg);
-        const v4s w1b = *reinterpret_cast<const v4s *>(W1s + col * 32 + 16 + 4 * kg);
-        int oa[4], ob[4];
+        int ou[8];
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            oa[r] = u1_off(4 * kg + r);
-            ob[r] = 16 + 4 * kg + r < 27 ? u1_off(16 + 4 * kg + r) : -1;
-        }
+        for (int j = 0; j < 8; j++) ou[j] = 8 * kg + j < 27 ? u1_off(8 * kg + j) : -1;
         float bias[4];
 #pragma unroll
-        for (int r = 0; r < 4; r++) bias[r] = B1[4 * kg + r];
+        for (int r = 0; r < 4; r++) bias[r] = th[NC1B + 4 * kg + r];
         for (int g = wave; g < NG1; g += 4) {
             const int hv = g * 16 + col;
             const int hc = hv < C2HALO ? hv : C2HALO - 1;
             const int hx = hc % C2HX, hy = (hc / C2HX) % C2HY, hz = hc / (C2HX * C2HY);
             const int base = (hz * U1Y + hy) * U1X + hx;
-            v4s b0, b1;
+            v8bf b;
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                b0[r] = (short)U[base + oa[r]];
-                b1[r] = ob[r] >= 0 ? (short)U[base + ob[r]] : (short)0;
-            }
+            for (int j = 0; j < 8; j++)
+                b[j] = __builtin_bit_cast(__bf16, ou[j] >= 0 ? U[base + ou[j]] : (uint16_t)0);
             v4f acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1a, b0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1b, b1, acc, 0, 0, 0);
-            // lane holds D[co = 4 kg + r][vox = col]
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, b, acc, 0, 0, 0);
+            // lane holds D[co = 4 kg + r][vox = col]: channels 4 kg .. 4 kg + 3
             if (hv < C2HALO) {
                 uint16_t aa[4];
 #pragma unroll
                 for (int r = 0; r < 4; r++) aa[r] = to_bf16(silu(acc[r] + bias[r]));
-                *reinterpret_cast<uint2 *>(X + hv * NET_C + 4 * kg) =
+                reinterpret_cast<uint2 *>(X + (kg >> 1) * C2HALO + hv)[kg & 1] =
                     make_uint2((uint32_t)aa[0] | ((uint32_t)aa[1] << 16), (uint32_t)aa[2] | ((uint32_t)aa[3] << 16));
             }
         }
     }
     __syncthreads();
-    v4s wa[27];
+    int ox[NPAIR];
 #pragma unroll
-    for (int t = 0; t < 27; t++) wa[t] = *reinterpret_cast<const v4s *>(W2s + (t * NET_C + col) * NET_C + 4 * kg);
+    for (int pr = 0; pr < NPAIR; pr++) {
+        const int t = 2 * pr + (kg >> 1);
+        ox[pr] = x_off(t < 27 ? t : 26);   // the 28th tap reads real data against zero weights
+    }
+    const uint4 *Xp = X + (kg & 1) * C2HALO + col;
     float bias[4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) bias[r] = B2[4 * kg + r];
+    for (int r = 0; r < 4; r++) bias[r] = th[NC2B + 4 * kg + r];
     for (int row = wave; row < C2Y * C2Z; row += 4) {
         const int ry = row % C2Y, rz = row / C2Y;
+        const uint4 *xr = Xp + (rz * C2HY + ry) * C2HX;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < 27; t++) {
-            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const int hv = ((rz + dz) * C2HY + (ry + dy)) * C2HX + (col + dx);
-            const v4s xb = *reinterpret_cast<const v4s *>(X + hv * NET_C + 4 * kg);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], xb, acc, 0, 0, 0);
+        for (int pr = 0; pr < NPAIR; pr++) {
+            const v8bf xb = __builtin_bit_cast(v8bf, xr[ox[pr]]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[pr], xb, acc, 0, 0, 0);
         }
         const int64_t v = ((int64_t)(z0 + rz) * n + (y0 + ry)) * n + (x0 + col);
         uint16_t aa[4];

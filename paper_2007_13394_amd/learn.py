@@ -341,8 +341,8 @@ def judge(coarse_name, fine_name, train_seeds, test_seeds, snap_every=5, iters=4
     return out
 
 
-def time_steps(cfg_name, steps, device="cuda", seed=200):
-    """ms per learned and per plain step on a sorted context of `cfg_name`
+def time_steps(cfg_name, steps, device="cuda", seed=200, which=("learned", "plain")):
+    """ms per learned and/or plain step on a sorted context of `cfg_name`
     (parameters: the seeded initialisation with every entry perturbed by 1 %
     noise, so that every layer runs with non-zero weights), from the initial
     conditions of `seed`."""
@@ -353,6 +353,8 @@ def time_steps(cfg_name, steps, device="cuda", seed=200):
     calls = _calls(cfg)[:steps + 2]
     out = {}
     for name, learned in (("learned", True), ("plain", False)):
+        if name not in which:
+            continue
         ctx = make_ctx(cfg, learned=learned, sort=True)
         x, p = ctx.particles()
         w = torch.from_numpy(I.white_noise(seed, cfg["n_cdm"])).to(device)
