@@ -133,6 +133,56 @@ def cpu_baseline(P_target, n_target):
     }
 
 
+# Table 1 shapes: (name, CDM per side, mesh per side, N_fib, the paper's runtime increase on Cori CPU nodes)
+RUNTIME_SHAPES = [("NC512_NF3", 512, 1024, 3, 25.0), ("NC512_NF20", 512, 1024, 20, 115.0),
+                  ("NC1024_NF3", 1024, 2048, 3, 6.0)]
+
+
+def runtime_increase():
+    """Runtime-per-step increase from the neutrino particles (Sec. 4 and
+    Table 1): the whole 5 log + 20 linear step schedule from z = 99 with
+    neutrino particles (128^3 sites, 10 shells, 2 N_fib + 1 directions) and
+    without (same CDM, mesh and steps; no neutrino particles), timed on the
+    GPU after the initial conditions.  L = 1024 Mpc/h, M_nu = 0.1 eV
+    (degenerate) for the massive runs; the step cost does not depend on
+    either.  NC1024_NF20 (1.93e9 particles) needs about 280 GB in this
+    layout and does not fit one GPU's memory."""
+    import torch
+    from paper_2007_13394_amd import inputs as I
+    from paper_2007_13394_amd import pm
+    from paper_2007_13394_amd import run as R
+    rows = []
+    for name, nc, nmesh, nfib, paper in RUNTIME_SHAPES:
+        res = {"name": name, "n_cdm": nc, "mesh": nmesh, "n_fib": nfib, "paper_increase_pct": paper}
+        for kind in ("massive", "massless"):
+            cfg = I.config("C3", n_cdm=nc, n_mesh=nmesh, n_fib=nfib, box=1024.0, m_nu=(0.1 / 3,) * 3)
+            if kind == "massless":
+                cfg = dict(cfg, n_sites=0, m_nu=(0.0, 0.0, 0.0))
+            ctx = pm.Ctx(pm.make_config(cfg))
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(cfg["seed"])
+            white = torch.randn((nc, nc, nc), generator=gen, device="cuda", dtype=torch.float32)
+            x, p = ctx.particles()
+            pm.pm_ic(ctx, white, x, p)
+            del white
+            calls = R.kdk_calls(*R.schedule(cfg["a0"], cfg["n_lin"], cfg["n_log"], cfg["a_mid"]))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in calls:
+                pm.pm_step(ctx, x, p, *c)
+            torch.cuda.synchronize()
+            res[kind + "_particles"] = ctx.P
+            res[kind + "_ms_per_step"] = round((time.perf_counter() - t0) / len(calls) * 1e3, 3)
+            log(f"[bench] {name} {kind}: {ctx.P} particles, {res[kind + '_ms_per_step']:.2f} ms/step")
+            del ctx, x, p
+            torch.cuda.empty_cache()
+        res["increase_pct"] = round(100.0 * (res["massive_ms_per_step"] / res["massless_ms_per_step"] - 1.0), 1)
+        rows.append(res)
+    return {"experiment": "runtime-per-step increase from neutrino particles (Table 1 shapes), 26 pm_step calls "
+                          "(5 log + 20 linear steps) from z=99, one MI355X",
+            "shapes": rows, "not_run": {"NC1024_NF20": "1.93e9 particles need about 280 GB here"}}
+
+
 def learned_speed(steps=10):
     """Live speed half of the learned-vs-plain comparison (C4, 19 070 976
     particles): learned steps on the 256^3 mesh against plain steps on the
@@ -161,6 +211,8 @@ def main():
     ap.add_argument("--config", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain step timing (C4)")
+    ap.add_argument("--runtime-increase", action="store_true",
+                    help="only run the runtime-increase experiment (massive vs massless neutrinos, Table 1 shapes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -170,6 +222,9 @@ def main():
         sys.exit(2)
 
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    if args.runtime_increase:
+        print(json.dumps(runtime_increase()), flush=True)
+        return
     import numpy as np
     import torch
     from paper_2007_13394_amd import inputs as I
