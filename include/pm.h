@@ -69,6 +69,9 @@ enum {
                               global atomics and gathers the force: slower) */
     PM_FLAG_LEARNED = 8,   /* reserve the workspace of the learned force correction
                               (pm_learned_*; N a power of two >= 16) */
+    PM_FLAG_NU_PSEUDO = 16 /* pseudo-random neutrino velocities, one particle per
+                              site (n_shell 1, n_fib 0): initial conditions by
+                              pm_ic_pseudo instead of pm_ic */
 };
 
 /* Simulation parameters (Table 1 of the paper names the counts).  All
@@ -149,6 +152,17 @@ pm_status pm_kdk_factors(const pm_ctx *ctx, double a_force, double a_kick0, doub
  * reversed on odd sites unless PM_FLAG_NO_FLIP), bulk displacement from the
  * same noise with free-streaming suppression. */
 pm_status pm_ic(pm_ctx *ctx, const float *white, float *x, float *p, void *stream);
+
+/* The same initial conditions with pseudo-random thermal velocities, the
+ * sampling the paper compares its quasi-random shells with (Sec. 3, the
+ * neutrino power spectrum figure): one neutrino per site at the site plus the
+ * bulk displacement; speed q = C^-1(u0), C the cumulative of q^2 f~(q) on
+ * [0, 30 / min alpha] (tabulated at 4097 points of q, inverted by search and
+ * linear interpolation); direction cos(theta) = 2 u1 - 1, phi = 2 pi u2 about
+ * mesh axis 2.  u: device float32 [3][n_sites^3] uniforms in [0, 1), drawn by
+ * the caller.  Needs PM_FLAG_NU_PSEUDO (PM_ERR_STATE otherwise; pm_ic returns
+ * PM_ERR_STATE for such a context). */
+pm_status pm_ic_pseudo(pm_ctx *ctx, const float *white, const float *u, float *x, float *p, void *stream);
 
 /* Cloud-in-cell assignment of particles [first, first + count) with one mass
  * quantum, ADDED to the int64 mesh (caller zeroes it).

@@ -173,8 +173,8 @@ static void displacement(const orc_sim *s, const cplx *W, long n, int d, int kin
 
 /* x, p: [3][P] in mesh units.  disp_cdm [3][N_c], disp_nu [3][N_sites] (mesh
  * units) are optional outputs of the displacement fields used. */
-static int ic_impl(const orc_sim *s, const float *white32, const double *white64, double *x, double *p,
-                   double *disp_cdm, double *disp_nu)
+static int ic_impl(const orc_sim *s, const float *white32, const double *white64, const double *uni, double *x,
+                   double *p, double *disp_cdm, double *disp_nu)
 {
     long n = s->n_cdm, m = n * n * n, nc, nn;
     long P = orc_num_particles(s, &nc, &nn);
@@ -224,6 +224,28 @@ static int ic_impl(const orc_sim *s, const float *white32, const double *white64
                 if (disp_nu) disp_nu[d * nsites + j] = snu[d * nsites + j];
             }
         }
+        if (uni) {
+            /* pseudo-random: one particle per site at the site, random speed and direction */
+            double alpha[3];
+            for (int j = 0; j < c->n_nu; j++) alpha[j] = c->m_nu[j] / m1;
+            for (long j = 0; j < nsites; j++) {
+                long jj[3] = {j / (ns * ns), (j / ns) % ns, j % ns};
+                double q = orc_fd_qinv(c->n_nu, alpha, uni[j]);
+                double ct = 2.0 * uni[nsites + j] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+                double ph = 2.0 * M_PI * uni[2 * nsites + j];
+                double v[3] = {st * cos(ph), st * sin(ph), ct};
+                for (int d = 0; d < 3; d++) {
+                    double site = (jj[d] * R + R / 2 + 0.5) * dc;
+                    x[d * P + nc + j] = wrap(site + snu[d * nsites + j], s->n_mesh);
+                    p[d * P + nc + j] = q * pth_unit * v[d] + vfac * snu[d * nsites + j];
+                }
+            }
+            free(snu);
+            free(dirs);
+            free(W);
+            free(S);
+            return 0;
+        }
         long per = nsites * nd;
         for (int sh = 0; sh < s->n_shell; sh++) {
             double r = 0.4 * spacing * q_shell[sh] / q_shell[s->n_shell - 1];
@@ -252,13 +274,19 @@ static int ic_impl(const orc_sim *s, const float *white32, const double *white64
 
 int orc_ic(const orc_sim *s, const float *white, double *x, double *p, double *disp_cdm, double *disp_nu)
 {
-    return ic_impl(s, white, NULL, x, p, disp_cdm, disp_nu);
+    return ic_impl(s, white, NULL, NULL, x, p, disp_cdm, disp_nu);
 }
 
 /* The same initial conditions from FP64 white noise (for derivative checks). */
 int orc_ic_w64(const orc_sim *s, const double *white, double *x, double *p)
 {
-    return ic_impl(s, NULL, white, x, p, NULL, NULL);
+    return ic_impl(s, NULL, white, NULL, x, p, NULL, NULL);
+}
+
+int orc_ic_pseudo(const orc_sim *s, const float *white, const double *u, double *x, double *p)
+{
+    if (s->n_shell != 1 || s->n_fib != 0 || s->n_sites < 1) return -1;
+    return ic_impl(s, white, NULL, u, x, p, NULL, NULL);
 }
 
 /* Vector-Jacobian product of the initial conditions with respect to the white

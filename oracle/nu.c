@@ -148,6 +148,27 @@ int orc_fd_shells(int n_nu, const double *alpha, int n_shell, double q_max,
     return 0;
 }
 
+/* Inverse of the cumulative number distribution of the neutrino momenta,
+ * C(q) = int_0^q q'^2 f~ dq' / int_0^q_max q'^2 f~ dq' (q_max = 30 / min alpha):
+ * the q with C(q) = u, by bisection with the integral carried along (the
+ * pseudo-random sampling of thermal speeds that the paper compares against). */
+double orc_fd_qinv(int n_nu, const double *alpha, double u)
+{
+    double amin = alpha[0];
+    for (int j = 1; j < n_nu; j++) if (alpha[j] < amin) amin = alpha[j];
+    double q_max = 30.0 / amin;
+    if (u <= 0.0) return 0.0;
+    if (u >= 1.0) return q_max;
+    double target = u * moment(n_nu, alpha, 2, 0.0, q_max);
+    double lo = 0.0, hi = q_max, below = 0.0;   /* below = int_0^lo */
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * q_max; it++) {
+        double mid = 0.5 * (lo + hi);
+        double piece = moment(n_nu, alpha, 2, lo, mid);
+        if (below + piece < target) { lo = mid; below += piece; } else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* dirs[(i + n_fib) * 3 + d], i = -n_fib..n_fib: unit vectors (axis 0, 1, 2). */
 void orc_fibonacci(int n_fib, double *dirs)
 {

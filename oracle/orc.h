@@ -71,6 +71,7 @@ double orc_integrate(double (*f)(double, void *), void *ctx, double a, double b,
 int    orc_fd_shells(int n_nu, const double *alpha, int n_shell, double q_max,
                      double *edges, double *q_shell, double *m_shell);
 void   orc_fibonacci(int n_fib, double *dirs);
+double orc_fd_qinv(int n_nu, const double *alpha, double u);
 
 /* ---------------- simulation set-up (ic.c) ---------------- */
 typedef struct {
@@ -96,6 +97,10 @@ double orc_sigma_R(const orc_sim *s, double amp, double R);
 double orc_pk_amplitude(const orc_sim *s);
 int    orc_ic(const orc_sim *s, const float *white, double *x, double *p, double *disp_cdm, double *disp_nu);
 int    orc_ic_w64(const orc_sim *s, const double *white, double *x, double *p);
+/* Pseudo-random neutrino velocities (one particle per site: n_shell 1,
+ * n_fib 0): u [3][n_sites^3] uniforms in [0, 1) give the speed q = C^-1(u0)
+ * and the direction cos(theta) = 2 u1 - 1, phi = 2 pi u2 about mesh axis 2. */
+int    orc_ic_pseudo(const orc_sim *s, const float *white, const double *u, double *x, double *p);
 int    orc_ic_vjp(const orc_sim *s, const double *xbar, const double *pbar, double *wbar);
 
 /* ---------------- PM force and step (pm.c) ---------------- */

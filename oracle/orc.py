@@ -24,7 +24,8 @@ def build():
 
 
 def _load():
-    if not os.path.exists(_SO):
+    srcs = [os.path.join(_HERE, s) for s in _SRC] + [os.path.join(_HERE, "orc.h")]
+    if not os.path.exists(_SO) or max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(_SO):
         build()
     return C.CDLL(_SO)
 
@@ -90,6 +91,8 @@ _sig("orc_force", C.c_int, [C.POINTER(Sim), _dp, _dp])
 _sig("orc_step", C.c_int, [C.POINTER(Sim), _dp, _dp, C.c_double, C.c_double, C.c_void_p])
 _sig("orc_power", None, [_dp, _dp, C.c_int, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp])
 _sig("orc_ic_w64", C.c_int, [C.POINTER(Sim), _dp, _dp, _dp])
+_sig("orc_ic_pseudo", C.c_int, [C.POINTER(Sim), _fp, _dp, _dp, _dp])
+_sig("orc_fd_qinv", C.c_double, [C.c_int, _dp, C.c_double])
 _sig("orc_ic_vjp", C.c_int, [C.POINTER(Sim), _dp, _dp, _dp])
 _sig("orc_density_cont", C.c_int, [C.POINTER(Sim), _dp, _dp])
 _sig("orc_force_cont", C.c_int, [C.POINTER(Sim), _dp, _dp])
@@ -255,6 +258,27 @@ def sigma_R(sim, amp, R):
 
 def pk_amplitude(sim):
     return _lib.orc_pk_amplitude(C.byref(sim))
+
+
+def fd_qinv(n_nu, alpha, u):
+    """Inverse cumulative number distribution of the neutrino momenta."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    return _lib.orc_fd_qinv(int(n_nu), a, float(u))
+
+
+def ic_pseudo(sim, white, u):
+    """Initial conditions with pseudo-random neutrino velocities (one per site);
+    u: [3, n_sites^3] uniforms."""
+    white = np.ascontiguousarray(white, dtype=np.float32).reshape(-1)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    P, nc, nn = num_particles(sim)
+    if u.size != 3 * nn:
+        raise ValueError("u must hold 3 uniforms per neutrino particle")
+    x = np.empty(3 * P)
+    p = np.empty(3 * P)
+    if _lib.orc_ic_pseudo(C.byref(sim), white, u, x, p) != 0:
+        raise ValueError("ic_pseudo needs n_shell = 1 and n_fib = 0")
+    return x.reshape(3, P), p.reshape(3, P)
 
 
 def ic(sim, white, want_disp=False):

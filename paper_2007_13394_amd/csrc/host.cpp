@@ -94,7 +94,7 @@ Layout layout(const pm_config &c)
     L.partial = off;
     off = align256(off + (size_t)(pm::POWER_BLOCKS + 1) * 3 * pm::MAX_BINS * 8);
     L.tables = off;
-    off = align256(off + (size_t)(3 * (2 * c.n_fib + 1) + 2 * c.n_shell) * 4);
+    off = align256(off + (size_t)(3 * (2 * c.n_fib + 1) + 2 * c.n_shell + ((c.flags & PM_FLAG_NU_PSEUDO) ? 4097 : 0)) * 4);
     L.segtab = off;
     off = align256(off + (size_t)(2 * pm::MAX_SEG + 1) * 8);
     L.xs = L.ps = L.tags = L.ids = L.koff = L.key = L.rank = L.cnt = L.bsum = 0;
@@ -159,6 +159,8 @@ pm_status check_config(const pm_config *c)
     if (c->n_shell < 1 || c->n_shell > pm::MAX_SEG - 1)
         return fail(PM_ERR_ARG, "n_shell must be in [1, %d]", pm::MAX_SEG - 1);
     if (c->n_fib < 0 || c->n_fib > 1000) return fail(PM_ERR_ARG, "n_fib must be in [0, 1000]");
+    if ((c->flags & PM_FLAG_NU_PSEUDO) && (c->n_sites < 1 || c->n_shell != 1 || c->n_fib != 0))
+        return fail(PM_ERR_ARG, "PM_FLAG_NU_PSEUDO needs neutrino sites, n_shell = 1 and n_fib = 0");
     if (c->n_nu < 0 || c->n_nu > 3) return fail(PM_ERR_ARG, "n_nu must be in [0, 3]");
     if (c->shift < 16 || c->shift > 52) return fail(PM_ERR_ARG, "shift must be in [16, 52]");
     if (!(c->box > 0) || !(c->omega_m > 0) || !(c->h > 0) || !(c->a0 > 1.0 / 160.0) || !(c->a0 <= 1.0))
@@ -481,6 +483,7 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
         const double pth_unit = c->kT_nu / c->m1 * 299792.458 / 100.0 * n / cfg->box;
         for (int s2 = 0; s2 < cfg->n_shell; s2++) tables.push_back((float)(0.4 * spacing * c->q_shell[s2] / qlast));
         for (int s2 = 0; s2 < cfg->n_shell; s2++) tables.push_back((float)(c->q_shell[s2] * pth_unit));
+        for (double v : c->q_cdf) tables.push_back((float)v);   // pseudo-random sampling only
     }
     hipError_t e = hipMemcpyAsync(c->ws.tw, c->tw_host.data(), sizeof(float2) * c->tw_host.size(),
                                   hipMemcpyHostToDevice, s);
@@ -604,9 +607,8 @@ pm_status pm_kdk_factors(const pm_ctx *c, double a_force, double a_kick0, double
     return PM_OK;
 }
 
-pm_status pm_ic(pm_ctx *c, const float *white, float *x, float *p, void *stream)
+static pm_status ic_impl(pm_ctx *c, const float *white, const float *u, float *x, float *p, void *stream)
 {
-    if (!c || !white || !x || !p) return fail(PM_ERR_ARG, "NULL argument to pm_ic");
     c->permuted = false;
     hipStream_t s = S(stream);
     const pm_config &g = c->cfg;
@@ -644,11 +646,33 @@ pm_status pm_ic(pm_ctx *c, const float *white, float *x, float *p, void *stream)
         }
         if (pass == 0)
             LAUNCH(pm::K_IC_PARTICLES, pm::launch_ic_cdm(F, nhp, cs, nic, n, vfac, x, p, c->P, s));
-        else
+        else if (u) {
+            const double pth_unit = c->kT_nu / c->m1 * 299792.458 / 100.0 * n / g.box;
+            const float *cdf = c->ws.tables + 3 + 2;   // after one direction, one radius, one speed
+            LAUNCH(pm::K_IC_PARTICLES,
+                   pm::launch_ic_nu_pseudo(F, nhp, cs, nic, n, g.n_sites, cdf, (int)c->q_cdf.size() - 1, c->q_cdf_h,
+                                           pth_unit, vfac, u, x, p, c->P, c->nc, s));
+        } else
             LAUNCH(pm::K_IC_PARTICLES, pm::launch_ic_nu(F, nhp, cs, nic, n, g.n_sites, 2 * g.n_fib + 1, g.n_shell, c->ws.tables, vfac,
                                     (g.flags & PM_FLAG_NO_FLIP) ? 0 : 1, x, p, c->P, c->nc, s));
     }
     return PM_OK;
+}
+
+pm_status pm_ic(pm_ctx *c, const float *white, float *x, float *p, void *stream)
+{
+    if (!c || !white || !x || !p) return fail(PM_ERR_ARG, "NULL argument to pm_ic");
+    if (c->cfg.flags & PM_FLAG_NU_PSEUDO)
+        return fail(PM_ERR_STATE, "a PM_FLAG_NU_PSEUDO context takes its initial conditions from pm_ic_pseudo");
+    return ic_impl(c, white, nullptr, x, p, stream);
+}
+
+pm_status pm_ic_pseudo(pm_ctx *c, const float *white, const float *u, float *x, float *p, void *stream)
+{
+    if (!c || !white || !u || !x || !p) return fail(PM_ERR_ARG, "NULL argument to pm_ic_pseudo");
+    if (!(c->cfg.flags & PM_FLAG_NU_PSEUDO) || c->q_cdf.size() < 2)
+        return fail(PM_ERR_STATE, "pm_ic_pseudo needs a context configured with PM_FLAG_NU_PSEUDO");
+    return ic_impl(c, white, u, x, p, stream);
 }
 
 pm_status pm_paint_q(pm_ctx *c, const float *x, int64_t stride, int64_t first, int64_t count, int64_t quantum,

@@ -313,6 +313,16 @@ void cosmo_setup(Ctx &c)
             c.q_shell.push_back(sqrt(m4[s] / m2[s]));
             c.m_shell.push_back(m2[s] / ntot);
         }
+        // pseudo-random sampling: cumulative number distribution C(q) on the same grid
+        c.q_cdf.clear();
+        if (g.flags & PM_FLAG_NU_PSEUDO) {
+            auto f2 = [&](double q) { return q * q * ftilde(alpha, q); };
+            c.q_cdf.assign(ng + 1, 0.0);
+            for (int i = 0; i < ng; i++) c.q_cdf[i + 1] = c.q_cdf[i] + simpson(f2, i * hq, (i + 1) * hq, 16);
+            const double tot = c.q_cdf[ng];
+            for (double &v : c.q_cdf) v /= tot;
+            c.q_cdf_h = hq;
+        }
         // Fibonacci sphere: latitude asin(2i/(2 n_fib + 1)), longitude 2 pi i / golden ratio
         const double phi = 0.5 * (1.0 + sqrt(5.0));
         for (int i = -g.n_fib; i <= g.n_fib; i++) {

@@ -319,6 +319,42 @@ __global__ void k_ic_nu(const float *__restrict__ F, int64_t rs, int64_t cs, int
     }
 }
 
+// Pseudo-random neutrinos (one per site): x = site + s, p = q pth_unit n + vfac s,
+// q = C^-1(u0) from the cumulative table cdf[0..nq] at q = i hq (search, then
+// linear interpolation inside the cell), n = (sin t cos f, sin t sin f, cos t)
+// with cos t = 2 u1 - 1, f = 2 pi u2.
+__global__ void k_ic_nu_pseudo(const float *__restrict__ F, int64_t rs, int64_t cs, int nic, int n, int ns,
+                               const float *__restrict__ cdf, int nq, double hq, double pth_unit, double vfac,
+                               const float *__restrict__ u, float *x, float *p, int64_t P, int64_t nc)
+{
+    const int64_t nsites = (int64_t)ns * ns * ns;
+    const int R = nic / ns;
+    const double dc = (double)n / nic;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nsites; t += (int64_t)gridDim.x * blockDim.x) {
+        const int j0 = (int)(t / ((int64_t)ns * ns)), j1 = (int)((t / ns) % ns), j2 = (int)(t % ns);
+        const int jj[3] = {j0, j1, j2};
+        const int64_t g = ((int64_t)(j0 * R + R / 2) * nic + (j1 * R + R / 2)) * rs + (j2 * R + R / 2);
+        const float u0 = u[t];
+        int lo = 0, hi = nq;   // cdf[lo] <= u0 < cdf[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cdf[mid] <= u0) lo = mid; else hi = mid;
+        }
+        const double c0 = cdf[lo], c1 = cdf[lo + 1];
+        const double q = hq * (lo + (c1 > c0 ? ((double)u0 - c0) / (c1 - c0) : 0.0));
+        const double ct = 2.0 * (double)u[nsites + t] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        const double ph = 6.283185307179586 * (double)u[2 * nsites + t];
+        const double v[3] = {st * cos(ph), st * sin(ph), ct};
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const double s = F[d * cs + g];
+            const double centre = (jj[d] * R + R / 2 + 0.5) * dc;
+            x[d * P + nc + t] = wrap_to_float(centre + s, n);
+            p[d * P + nc + t] = (float)(q * pth_unit * v[d] + vfac * s);
+        }
+    }
+}
+
 __device__ __forceinline__ int isqrt_i(int64_t v)
 {
     int64_t b = (int64_t)sqrt((double)v);
@@ -468,6 +504,17 @@ hipError_t launch_ic_nu(const float2 *f, int64_t rs, int64_t comp_stride, int ni
     const int64_t total = (int64_t)ns * ns * ns * n_dir * n_shell;
     hipLaunchKernelGGL(k_ic_nu, dim3(grid_for(total, 256)), dim3(256), 0, s, reinterpret_cast<const float *>(f),
                        2 * rs, 2 * comp_stride, nic, n, ns, n_dir, n_shell, tables, vfac, flip, x, p, P, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_nu_pseudo(const float2 *f, int64_t rs, int64_t comp_stride, int nic, int n, int ns,
+                               const float *cdf, int nq, double hq, double pth_unit, double vfac, const float *u,
+                               float *x, float *p, int64_t P, int64_t nc, hipStream_t s)
+{
+    if (nq < 1 || ns < 1 || nic % ns) return hipErrorInvalidValue;
+    const int64_t nsites = (int64_t)ns * ns * ns;
+    hipLaunchKernelGGL(k_ic_nu_pseudo, dim3(grid_for(nsites, 256)), dim3(256), 0, s, reinterpret_cast<const float *>(f),
+                       2 * rs, 2 * comp_stride, nic, n, ns, cdf, nq, hq, pth_unit, vfac, u, x, p, P, nc);
     return hipGetLastError();
 }
 

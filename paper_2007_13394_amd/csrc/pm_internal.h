@@ -126,6 +126,8 @@ struct Ctx {
     // neutrino shells
     std::vector<double> edges, q_shell, m_shell;
     std::vector<float> dirs;      // (2 n_fib + 1) x 3
+    std::vector<double> q_cdf;    // pseudo-random sampling: cumulative of q^2 f~ at q = i q_cdf_h
+    double q_cdf_h = 0;
     Workspace ws;
     std::vector<float2> tw_host;
     // particle order: canonical (segments at seg_off) or permuted by the last
@@ -268,6 +270,11 @@ hipError_t launch_ic_cdm(const float2 *f, int64_t rs, int64_t comp_stride, int n
 hipError_t launch_ic_nu(const float2 *f, int64_t rs, int64_t comp_stride, int nic, int n, int ns,
                         int n_dir, int n_shell, const float *tables, double vfac, int flip, float *x,
                         float *p, int64_t P, int64_t nc, hipStream_t s);
+// Pseudo-random neutrinos: one per site, speed from the cumulative table cdf
+// [nq + 1] at q = i hq, direction from the uniforms u [3][ns^3].
+hipError_t launch_ic_nu_pseudo(const float2 *f, int64_t rs, int64_t comp_stride, int nic, int n, int ns,
+                               const float *cdf, int nq, double hq, double pth_unit, double vfac, const float *u,
+                               float *x, float *p, int64_t P, int64_t nc, hipStream_t s);
 hipError_t launch_power_bin(const float2 *A, const float2 *B, int64_t rs, int n, int nbins, int compensate,
                             double norm, double kf, double *partial, hipStream_t s);
 hipError_t launch_power_reduce(const double *partial, int nbins, double *out, hipStream_t s);

@@ -19,6 +19,10 @@ count)^(1/3) / 4, 10 shells, N_fib = 3, i.e. 70 particles per site):
       power from lattice discreteness, so the fine-mesh truth of the learned
       correction starts later (coarse and fine runs alike)
   C5  256^3 mesh, L = 256 Mpc/h, 128^3 CDM, 16^3 sites, M_nu = 0.1 eV, 10 linear steps
+  E7  quasi-random (64^3 sites x 10 shells x 51 directions) against pseudo-random
+      (512^3 sites x 1) neutrino sampling at 512^3 CDM, 1024^3 mesh,
+      L = 1024 Mpc/h, M_nu = 0.2 eV, 5 log + 20 linear steps (C1p: a small
+      pseudo-random instance)
 """
 import numpy as np
 
@@ -50,6 +54,14 @@ CONFIGS = {
                        n_lin=10, n_log=0, a_mid=None, seed=150, a0=0.05),
     "C4s_fine": dict(_COMMON, box=256.0, n_mesh=256, n_cdm=64, n_sites=8, m_nu=_deg(0.1),
                      n_lin=10, n_log=0, a_mid=None, seed=150, a0=0.05),
+    # pseudo-random neutrino velocities, one neutrino per site (PM_FLAG_NU_PSEUDO)
+    "C1p": dict(_COMMON, box=256.0, n_mesh=64, n_cdm=32, n_sites=32, n_shell=1, n_fib=0, m_nu=_deg(0.1),
+                n_lin=10, n_log=0, a_mid=None, seed=11),
+    # quasi-random vs pseudo-random sampling at equal neutrino counts (64^3 x 10 x 51 vs 512^3, ratio 0.996)
+    "E7_qr": dict(_COMMON, box=1024.0, n_mesh=1024, n_cdm=512, n_sites=64, n_shell=10, n_fib=25, m_nu=_deg(0.2),
+                  n_lin=20, n_log=5, a_mid=0.05, seed=700),
+    "E7_pr": dict(_COMMON, box=1024.0, n_mesh=1024, n_cdm=512, n_sites=512, n_shell=1, n_fib=0, m_nu=_deg(0.2),
+                  n_lin=20, n_log=5, a_mid=0.05, seed=700),
     "C5": dict(_COMMON, box=256.0, n_mesh=256, n_cdm=128, n_sites=16, m_nu=_deg(0.1),
                n_lin=10, n_log=0, a_mid=None, seed=301),
     "C5_fd16": dict(_COMMON, box=256.0, n_mesh=16, n_cdm=8, n_sites=2, m_nu=_deg(0.1),

@@ -72,6 +72,7 @@ _sig("pm_shells", [_vp, _vp, _vp, _vp])
 _sig("pm_growth", [_vp, _i32, _vp, _vp, _vp])
 _sig("pm_kdk_factors", [_vp, _dbl, _dbl, _dbl, _dbl, C.POINTER(_dbl), C.POINTER(_dbl)])
 _sig("pm_ic", [_vp, _vp, _vp, _vp, _vp])
+_sig("pm_ic_pseudo", [_vp, _vp, _vp, _vp, _vp, _vp])
 _sig("pm_paint_q", [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp])
 _sig("pm_paint", [_vp, _vp, _i32, _i32, _vp, _vp])
 _sig("pm_fft_r2c", [_vp, _vp, _vp, _vp])
@@ -107,7 +108,7 @@ EXPORTS = ["pm_sizes", "pm_init", "pm_free", "pm_last_error", "pm_segments", "pm
            "pm_force", "pm_step", "pm_power", "pm_trace_begin", "pm_trace_end", "pm_kernel_name", "pm_attach_ids",
            "pm_segment_tags", "pm_reset_order", "pm_density", "pm_density_vjp", "pm_force_vjp", "pm_step_vjp",
            "pm_ic_vjp", "pm_net_nparam", "pm_learned_force", "pm_learned_step", "pm_learned_loss", "pm_adam",
-           "pm_power_mesh", "pm_net_table", "pm_net_table_vjp"]
+           "pm_power_mesh", "pm_net_table", "pm_net_table_vjp", "pm_ic_pseudo"]
 
 
 def _check(st):
@@ -210,6 +211,15 @@ def pm_ic(ctx, white, x, p, stream=None):
     nc = ctx.cfg.n_cdm ** 3
     _check(_lib.pm_ic(ctx.h, _dev(white, torch.float32, nc, "white"), _dev(x, torch.float32, 3 * ctx.P, "x"),
                       _dev(p, torch.float32, 3 * ctx.P, "p"), _stream(stream)))
+
+
+def pm_ic_pseudo(ctx, white, u, x, p, stream=None):
+    """Initial conditions with pseudo-random neutrino velocities; u: float32
+    [3, n_sites^3] device uniforms in [0, 1)."""
+    nc, ns = ctx.cfg.n_cdm ** 3, ctx.cfg.n_sites ** 3
+    _check(_lib.pm_ic_pseudo(ctx.h, _dev(white, torch.float32, nc, "white"), _dev(u, torch.float32, 3 * ns, "u"),
+                             _dev(x, torch.float32, 3 * ctx.P, "x"), _dev(p, torch.float32, 3 * ctx.P, "p"),
+                             _stream(stream)))
 
 
 def pm_paint_q(ctx, x, first, count, quantum, mesh, stream=None):
@@ -336,6 +346,7 @@ def pm_ic_vjp(ctx, xbar, pbar, wbar, stream=None):
 
 # ---- learned force correction (PM_FLAG_LEARNED contexts)
 PM_FLAG_LEARNED = 8
+PM_FLAG_NU_PSEUDO = 16
 
 
 def pm_net_nparam():
