@@ -62,6 +62,10 @@ CONFIGS = {
                   n_lin=20, n_log=5, a_mid=0.05, seed=700),
     "E7_pr": dict(_COMMON, box=1024.0, n_mesh=1024, n_cdm=512, n_sites=512, n_shell=1, n_fib=0, m_nu=_deg(0.2),
                   n_lin=20, n_log=5, a_mid=0.05, seed=700),
+    "E7s_qr": dict(_COMMON, box=256.0, n_mesh=128, n_cdm=64, n_sites=8, n_shell=10, n_fib=25, m_nu=_deg(0.2),
+                   n_lin=10, n_log=0, a_mid=None, seed=710),
+    "E7s_pr": dict(_COMMON, box=256.0, n_mesh=128, n_cdm=64, n_sites=64, n_shell=1, n_fib=0, m_nu=_deg(0.2),
+                   n_lin=10, n_log=0, a_mid=None, seed=710),
     "C5": dict(_COMMON, box=256.0, n_mesh=256, n_cdm=128, n_sites=16, m_nu=_deg(0.1),
                n_lin=10, n_log=0, a_mid=None, seed=301),
     "C5_fd16": dict(_COMMON, box=256.0, n_mesh=16, n_cdm=8, n_sites=2, m_nu=_deg(0.1),

@@ -89,3 +89,25 @@ def test_pseudo_run_steps(dev):
     k, pnu, nm = pm.pm_power(ctx, x, 1, ctx.nseg, 1, ctx.nseg, nbins=n // 2)
     say("P_nu at the lowest and highest bins", pnu[1:3], pnu[-2:])
     assert np.all(np.isfinite(pnu)) and np.all(pnu[nm > 0] > 0)
+
+
+def test_sampling_comparison_small(dev):
+    """The quasi- vs pseudo-random comparison on a small instance (8^3 sites x
+    510 against 64^3 x 1 neutrinos, ratio 0.996): the pseudo-random spectrum
+    sits near its shot-noise level V / N at high k, the quasi-random one lies
+    below it between the largest scales and the grid wavenumber, and only the
+    quasi-random run shows an excess at the grid wavenumber at z = 2."""
+    from paper_2007_13394_amd import sampling
+    import numpy as np
+    res = sampling.compare("E7s_qr", "E7s_pr", z_out=(2.0, 0.0))
+    assert abs(res["n_nu_ratio_qr_over_pr"] - 0.99609375) < 1e-12
+    kn = res["k_n_hMpc"]
+    for row in res["rows"]:
+        say("z", row["z"], "high-k QR", row["p_nu_high_k_qr"], "PR", row["p_nu_high_k_pr"], "shot", row["shot_noise_pr"],
+            "grid excess QR", row["grid_excess_qr"].get("k_n"), "PR", row["grid_excess_pr"].get("k_n"))
+        assert 0.7 < row["p_nu_high_k_pr"] / row["shot_noise_pr"] < 1.6
+    s = res["spectra"]["2.0"]
+    k, q, p = (np.array(s[x]) for x in ("k", "p_nu_qr", "p_nu_pr"))
+    m = (k > 0.3 * kn) & (k < 0.8 * kn) & (q > 0)
+    assert np.median(q[m]) < np.median(p[m])
+    assert res["rows"][0]["grid_excess_qr"]["k_n"] > 2.0 > res["rows"][0]["grid_excess_pr"]["k_n"]
