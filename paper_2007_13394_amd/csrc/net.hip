@@ -517,35 +517,38 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const int64_t *__restrict__ q
 // real rows of stride rs.  Tile 16 x 16 x 4 with a2's one-voxel halo in LDS;
 // a thread owns a column of 4 voxels along axis 0, so each halo voxel it reads
 // feeds up to three taps.
-constexpr int C3X = 16, C3Y = 16, C3Z = 4, C3HX = C3X + 2, C3HY = C3Y + 2, C3HZ = C3Z + 2;
-constexpr int C3HALO = C3HX * C3HY * C3HZ;
-
+// Tile 16 x TY x TZ with a2's one-voxel halo in LDS; 256 threads, each owning
+// ZPT consecutive voxels along axis 0 of one (axis 1, axis 2) column, so each
+// halo voxel it reads feeds up to three taps.
+template <int TY, int TZ, int ZPT>
 __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ a2, int n,
                                                    const float *__restrict__ th, const uint16_t *__restrict__ wpk,
                                                    const float *__restrict__ phif, int64_t rs, float *out)
 {
+    static_assert(16 * TY * (TZ / ZPT) == 256 && TZ % ZPT == 0, "conv3 tile shape");
+    constexpr int HX = 18, HY = TY + 2, HZ = TZ + 2, HALO = HX * HY * HZ;
     // channel halves of each halo voxel in two planes: 16-byte rows, no bank conflicts
-    __shared__ __align__(16) uint4 X[2 * C3HALO];
+    __shared__ __align__(16) uint4 X[2 * HALO];
     __shared__ __align__(16) uint32_t W[27 * NET_C / 2];   // BF16 pairs [t][ci / 2]
     const int tid = threadIdx.x;
-    const int ntx = n / C3X, nty = n / C3Y;
+    const int ntx = n / 16, nty = n / TY;
     const int tile = blockIdx.x;
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-    const int x0 = tx * C3X, y0 = ty * C3Y, z0 = tz * C3Z, m = n - 1;
+    const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ, m = n - 1;
     for (int e = tid; e < 27 * NET_C / 8; e += 256)
         reinterpret_cast<uint4 *>(W)[e] = reinterpret_cast<const uint4 *>(wpk + WPK_W3 / 2)[e];
-    for (int e = tid; e < C3HALO * 2; e += 256) {
+    for (int e = tid; e < HALO * 2; e += 256) {
         const int hv = e >> 1, half = e & 1;
-        const int hx = hv % C3HX, hy = (hv / C3HX) % C3HY, hz = hv / (C3HX * C3HY);
+        const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
         const int64_t g = ((int64_t)((z0 + hz - 1) & m) * n + ((y0 + hy - 1) & m)) * n + ((x0 + hx - 1) & m);
-        X[half * C3HALO + hv] = reinterpret_cast<const uint4 *>(a2 + g * NET_C)[half];
+        X[half * HALO + hv] = reinterpret_cast<const uint4 *>(a2 + g * NET_C)[half];
     }
     __syncthreads();
-    const int lx = tid % C3X, ly = tid / C3X;
+    const int lx = tid % 16, ly = (tid / 16) % TY, zg = tid / (16 * TY);
     const float b = th[NC3B];
-    float acc[C3Z];
+    float acc[ZPT];
 #pragma unroll
-    for (int z = 0; z < C3Z; z++) acc[z] = b;
+    for (int z = 0; z < ZPT; z++) acc[z] = b;
 #pragma unroll 1
     for (int t2 = 0; t2 < 9; t2++) {
         const int dy = t2 / 3, dx = t2 % 3;
@@ -554,16 +557,16 @@ __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ 
         for (int dz = 0; dz < 3; dz++)
 #pragma unroll
             for (int k = 0; k < NET_C / 2; k++) w[dz][k] = W[(dz * 9 + t2) * (NET_C / 2) + k];
-        const int h0 = (ly + dy) * C3HX + lx + dx;
+        const int h0 = (zg * ZPT * HY + ly + dy) * HX + lx + dx;
 #pragma unroll
-        for (int hz = 0; hz < C3HZ; hz++) {
-            const int hv = h0 + hz * C3HY * C3HX;
-            const uint4 q0 = X[hv], q1 = X[C3HALO + hv];
+        for (int j = 0; j < ZPT + 2; j++) {
+            const int hv = h0 + j * HY * HX;
+            const uint4 q0 = X[hv], q1 = X[HALO + hv];
             const uint32_t xv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
             for (int dz = 0; dz < 3; dz++) {
-                const int lz = hz - dz;
-                if (lz < 0 || lz >= C3Z) continue;
+                const int lz = j - dz;
+                if (lz < 0 || lz >= ZPT) continue;
                 float sum = acc[lz];
 #pragma unroll
                 for (int k = 0; k < NET_C / 2; k++) sum = dot2_bf16(w[dz][k], xv[k], sum);
@@ -572,11 +575,16 @@ __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ 
         }
     }
 #pragma unroll
-    for (int z = 0; z < C3Z; z++) {
-        const int64_t o = ((int64_t)(z0 + z) * n + (y0 + ly)) * rs + (x0 + lx);
+    for (int z = 0; z < ZPT; z++) {
+        const int64_t o = ((int64_t)(z0 + zg * ZPT + z) * n + (y0 + ly)) * rs + (x0 + lx);
         out[o] = phif[o] + acc[z];
     }
 }
+
+// Measured at 256^3 (one MI355X): 16 x 8 x 4 with two voxels per thread
+// (35 KB of LDS, four workgroups per CU) 306 us; 16 x 16 x 4 with four per
+// thread (63 KB, two per CU) 418 us; one voxel per thread 360 us.
+constexpr int C3TY = 8, C3TZ = 4, C3ZPT = 2;
 
 // phi = phi_f + dpsi on real rows of stride rs.
 __global__ void k_combine(const float *phif, const float *dpsi, int64_t rs, int n, float *out)
@@ -844,12 +852,12 @@ hipError_t launch_cnn_fwd(const int64_t *q, double qs, int n, const float *th, f
 hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *phif, int64_t rs, int n, const float *th,
                           uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s)
 {
-    if (n < C3Y || n % C3Y || n % C3Z) return hipErrorInvalidValue;
+    if (n < 16 || n % 16) return hipErrorInvalidValue;
     const int64_t M = (int64_t)n * n * n;
     hipLaunchKernelGGL(k_pack_w, dim3(1), dim3(256), 0, s, th, wpk);
     hipLaunchKernelGGL(k_cnn12_inf, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, q, qs, n, th, wpk, a2);
-    hipLaunchKernelGGL(k_conv3_inf, dim3((unsigned)(M / (C3X * C3Y * C3Z))), dim3(256), 0, s, a2, n, th, wpk, phif,
-                       rs, out);
+    hipLaunchKernelGGL((k_conv3_inf<C3TY, C3TZ, C3ZPT>), dim3((unsigned)(M / (16 * C3TY * C3TZ))), dim3(256), 0, s, a2,
+                       n, th, wpk, phif, rs, out);
     return hipGetLastError();
 }
 
