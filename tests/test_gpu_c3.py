@@ -1,0 +1,82 @@
+"""The hot path at the benchmark's full size (C3: 1024^3 CDM + 128^3 x 70
+neutrinos on a 2048^3 mesh, 1.22e9 particles), in the launch configuration
+the benchmark times (tile sort, tile paint, fused transforms, tile readout
+with kick and drift), checked on a million sampled particles against the
+library's unsorted path (global-atomic paint, gather readout).  The int64
+paint is bit-exact under any particle order, so both paths see the same
+force meshes: the step's momentum change over the kick factor must equal the
+unsorted force up to float32 rounding, and the drift must follow.  (The FP64
+oracle cannot run a 2048^3 mesh in test time; the transforms themselves are
+checked at 2048^3 by closed forms in test_gpu_large.py.)  Peak device memory
+is about 262 GB."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2007_13394_amd import inputs as I
+from paper_2007_13394_amd import run as R
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_c3_sorted_step_matches_unsorted_force(dev):
+    from paper_2007_13394_amd import pm
+    cfg = I.config("C3")
+    ctx = pm.Ctx(pm.make_config(cfg))
+    assert ctx.sorts
+    P, n, nc = ctx.P, cfg["n_mesh"], cfg["n_cdm"]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(cfg["seed"])
+    white = torch.randn((nc, nc, nc), generator=gen, device=dev, dtype=torch.float32)
+    x, p = ctx.particles()
+    pm.pm_ic(ctx, white, x, p)
+    del white
+    say("C3 initial conditions done,", P, "particles")
+    rng = np.random.default_rng(3)
+    sample = torch.from_numpy(np.sort(rng.choice(P, 1_000_000, replace=False))).to(dev)
+    acc = torch.empty_like(x)
+    pm.pm_force(ctx, x, acc)
+    acc_s, p_s, x_s = acc[:, sample].double(), p[:, sample].double(), x[:, sample].double()
+    del acc
+    torch.cuda.empty_cache()
+    call = R.kdk_calls(*R.schedule(cfg["a0"], cfg["n_lin"], cfg["n_log"], cfg["a_mid"]))[0]
+    kick, drift = pm.pm_kdk_factors(ctx, *call)
+    ids = torch.arange(P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(ctx, ids)
+    pm.pm_step(ctx, x, p, *call)
+    pm.pm_attach_ids(ctx, None)
+    say("C3 sorted step done")
+    assert bool(torch.isfinite(x).all()) and bool(torch.isfinite(p).all())
+    assert bool(((x >= 0) & (x < n)).all())
+    assert int(ids.sum(dtype=torch.int64)) == P * (P - 1) // 2
+    # slot of every original particle, built in chunks (no P-sized int64 temporary)
+    inv = torch.empty_like(ids)
+    step = 1 << 26
+    for lo in range(0, P, step):
+        hi = min(P, lo + step)
+        inv[ids[lo:hi].long()] = torch.arange(lo, hi, dtype=torch.int32, device=dev)
+    slots = inv[sample].long()
+    del inv, ids
+    p_new, x_new = p[:, slots].double(), x[:, slots].double()
+    # CDM: the force itself, from the momentum change over the kick factor
+    cdm = sample < nc ** 3
+    f_step = (p_new[:, cdm] - p_s[:, cdm]) / kick
+    e_f = float(torch.linalg.vector_norm(f_step - acc_s[:, cdm]) / torch.linalg.vector_norm(acc_s[:, cdm]))
+    # neutrinos: thermal momenta at z = 99 dwarf the kick, so check the update to float32 rounding of |p|
+    nu = ~cdm
+    pred = p_s[:, nu] + kick * acc_s[:, nu]
+    e_nu = float(((p_new[:, nu] - pred).abs().amax(dim=0) / pred.abs().amax(dim=0).clamp_min(1e-30)).max())
+    dx = torch.remainder(x_s + drift * p_new - x_new + n / 2, n) - n / 2
+    e_x = float(dx.abs().max())
+    say("C3 sampled:", int(cdm.sum()), "CDM, force from the sorted step vs unsorted force rel L2", e_f, ";",
+        int(nu.sum()), "neutrinos, max momentum deviation / |p|", e_nu, "; drift max |dx|", e_x, "cells")
+    assert e_f < 1e-5
+    assert e_nu < 1e-6
+    assert e_x < 2e-3
