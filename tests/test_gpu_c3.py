@@ -9,6 +9,7 @@ unsorted force up to float32 rounding, and the drift must follow.  (The FP64
 oracle cannot run a 2048^3 mesh in test time; the transforms themselves are
 checked at 2048^3 by closed forms in test_gpu_large.py.)  Peak device memory
 is about 262 GB."""
+import gc
 import sys
 
 import numpy as np
@@ -26,7 +27,16 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_c3_sorted_step_matches_unsorted_force(dev):
+@pytest.fixture
+def free_device_memory():
+    gc.collect()
+    torch.cuda.empty_cache()
+    yield
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_c3_sorted_step_matches_unsorted_force(dev, free_device_memory):
     from paper_2007_13394_amd import pm
     cfg = I.config("C3")
     ctx = pm.Ctx(pm.make_config(cfg))
@@ -77,6 +87,7 @@ def test_c3_sorted_step_matches_unsorted_force(dev):
     e_x = float(dx.abs().max())
     say("C3 sampled:", int(cdm.sum()), "CDM, force from the sorted step vs unsorted force rel L2", e_f, ";",
         int(nu.sum()), "neutrinos, max momentum deviation / |p|", e_nu, "; drift max |dx|", e_x, "cells")
+    del x, p, ctx
     assert e_f < 1e-5
     assert e_nu < 1e-6
     assert e_x < 2e-3
