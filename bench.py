@@ -135,7 +135,7 @@ def cpu_baseline(P_target, n_target):
 
 # Table 1 shapes: (name, CDM per side, mesh per side, N_fib, the paper's runtime increase on Cori CPU nodes)
 RUNTIME_SHAPES = [("NC512_NF3", 512, 1024, 3, 25.0), ("NC512_NF20", 512, 1024, 20, 115.0),
-                  ("NC1024_NF3", 1024, 2048, 3, 6.0)]
+                  ("NC1024_NF3", 1024, 2048, 3, 6.0), ("NC1024_NF20", 1024, 2048, 20, 20.0)]
 
 
 def runtime_increase():
@@ -145,20 +145,30 @@ def runtime_increase():
     without (same CDM, mesh and steps; no neutrino particles), timed on the
     GPU after the initial conditions.  L = 1024 Mpc/h, M_nu = 0.1 eV
     (degenerate) for the massive runs; the step cost does not depend on
-    either.  NC1024_NF20 (1.93e9 particles) needs about 280 GB in this
-    layout and does not fit one GPU's memory."""
+    either.  A shape whose workspace, particles and white noise do not fit in
+    the free device memory (with 2 GiB to spare) is reported as not run;
+    NC1024_NF20 (1.93e9 particles) needs about 275 GiB."""
     import torch
     from paper_2007_13394_amd import inputs as I
     from paper_2007_13394_amd import pm
     from paper_2007_13394_amd import run as R
-    rows = []
+    rows, not_run = [], {}
     for name, nc, nmesh, nfib, paper in RUNTIME_SHAPES:
         res = {"name": name, "n_cdm": nc, "mesh": nmesh, "n_fib": nfib, "paper_increase_pct": paper}
         for kind in ("massive", "massless"):
             cfg = I.config("C3", n_cdm=nc, n_mesh=nmesh, n_fib=nfib, box=1024.0, m_nu=(0.1 / 3,) * 3)
             if kind == "massless":
                 cfg = dict(cfg, n_sites=0, m_nu=(0.0, 0.0, 0.0))
-            ctx = pm.Ctx(pm.make_config(cfg))
+            c = pm.make_config(cfg)
+            P, _, ws = pm.pm_sizes(c)
+            need = ws + 24 * P + 4 * nc ** 3 + (2 << 30)
+            torch.cuda.empty_cache()
+            free = torch.cuda.mem_get_info()[0]
+            if need > free:
+                not_run[name] = f"{kind} run needs {need / 2**30:.1f} GiB, {free / 2**30:.1f} GiB free"
+                log(f"[bench] {name}: {not_run[name]}")
+                break
+            ctx = pm.Ctx(c)
             gen = torch.Generator(device="cuda")
             gen.manual_seed(cfg["seed"])
             white = torch.randn((nc, nc, nc), generator=gen, device="cuda", dtype=torch.float32)
@@ -176,11 +186,13 @@ def runtime_increase():
             log(f"[bench] {name} {kind}: {ctx.P} particles, {res[kind + '_ms_per_step']:.2f} ms/step")
             del ctx, x, p
             torch.cuda.empty_cache()
+        if name in not_run:
+            continue
         res["increase_pct"] = round(100.0 * (res["massive_ms_per_step"] / res["massless_ms_per_step"] - 1.0), 1)
         rows.append(res)
     return {"experiment": "runtime-per-step increase from neutrino particles (Table 1 shapes), 26 pm_step calls "
                           "(5 log + 20 linear steps) from z=99, one MI355X",
-            "shapes": rows, "not_run": {"NC1024_NF20": "1.93e9 particles need about 280 GB here"}}
+            "shapes": rows, "not_run": not_run}
 
 
 def learned_speed(steps=10):
