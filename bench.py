@@ -314,6 +314,7 @@ def main():
         "steps": K,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "cdm_only_particle_steps_per_s": cfg["n_cdm"] ** 3 * K / elapsed,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
