@@ -106,15 +106,22 @@ struct Dft<1, INV> {
     __device__ __forceinline__ static void run(float2 *) {}
 };
 
-// LDS index with one pad slot per 2^PS elements (PS = 0: none).  A Stockham
-// stage writes its outputs R elements apart; with 8-byte elements and a
-// stride of 16 every lane of a wavefront would hit the same bank pair.
+// LDS index of element i.  PS > 0: one pad slot per 2^PS elements.  A
+// Stockham stage writes its outputs R elements apart; with 8-byte elements
+// and a stride of 16 every lane of a wavefront would hit the same bank pair.
+// PS < 0 (tiles of 8 columns, element (c, l) at 8 l + c): bits 0-1 of the row
+// l are XORed with bits -PS-3 .. -PS-2 of it.  The first stage's writes, rows
+// R apart (-PS = 3 + log2 R), then spread over four groups of eight bank
+// pairs, and aligned groups of four rows only permute, so consecutive
+// accesses stay conflict-free; no extra LDS.
 template <int PS>
 __device__ __forceinline__ int pad(int i)
 {
-    return PS ? i + (i >> PS) : i;
+    if constexpr (PS > 0) return i + (i >> PS);
+    else if constexpr (PS < 0) return i ^ (((i >> (-PS)) & 3) << 3);
+    else return i;
 }
-constexpr int padded(int n, int ps) { return ps ? n + (n >> ps) + 1 : n; }
+constexpr int padded(int n, int ps) { return ps > 0 ? n + (n >> ps) + 1 : n; }
 
 // One Stockham stage of radix R over NC independent transforms of length L
 // held in LDS: element (c, l) at buf[c * SC + l * SL].  NS = product of the
@@ -195,6 +202,8 @@ struct ColCfg {
     // register footprint below the 128-VGPR budget of 16 waves per CU.
     static constexpr int T = (E / 16) > 64 ? ((E / 16) < 1024 ? (E / 16) : 1024) : 64;
     static constexpr int PER = E / T;
+    // log2 of the first stage's radix (stages of at most 2^4, bits split evenly)
+    static constexpr int R1 = (LOGN + (LOGN + 3) / 4 - 1) / ((LOGN + 3) / 4);
 };
 
 // The axis-0 pass keeps part of a spectrum in registers across an inverse
@@ -297,18 +306,23 @@ __global__ __launch_bounds__((ColCfg<LOGN, WW>::T)) void k_cols(float2 *base, in
     using C = ColCfg<LOGN, WW>;
     constexpr int N = C::N, W = C::W, E = C::E, T = C::T;
     __shared__ float2 buf[E];
+    // the stages' twiddles, staged once: read from global memory after each
+    // stage's barrier, their latency would stall every wave at once
+    __shared__ float2 twl[N];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int o = tile / n_cb, cb = tile % n_cb;
     const int tid = threadIdx.x;
     // thread owns column tid % W and rows tid / W + i T / W (T is a multiple of W)
     float2 *p = base + (int64_t)o * stride_o + cb * W + (tid % W) + (int64_t)(tid / W) * stride_l;
     const int64_t step = (int64_t)(T / W) * stride_l;
+    constexpr int SW = W == 8 ? -(3 + ColCfg<LOGN, WW>::R1) : 0;
+    for (int i = tid; i < N; i += T) twl[i] = tw[N + i];
 #pragma unroll
-    for (int i = 0; i < C::PER; i++) buf[tid + i * T] = p[i * step];
+    for (int i = 0; i < C::PER; i++) buf[pad<SW>(tid + i * T)] = p[i * step];
     __syncthreads();
-    fft_from<N, 1, W, T, true, W, 1, INV, 4>(buf, tw + N);
+    fft_from<N, 1, W, T, true, W, 1, INV, 4, SW>(buf, twl);
 #pragma unroll
-    for (int i = 0; i < C::PER; i++) p[i * step] = buf[tid + i * T];
+    for (int i = 0; i < C::PER; i++) p[i * step] = buf[pad<SW>(tid + i * T)];
 }
 
 // ---------------------------------------------------------------- axis 0 + multiplier
@@ -626,9 +640,17 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const int64_t *src, 
 {
     constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, PS = 4;
     __shared__ float2 buf[padded(RB * L, PS)];
+    __shared__ float2 twl[L];   // the row stages' twiddles (one per thread)
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int j1 = tile / N, x1 = tile % N;
     const int tid = threadIdx.x;
+    twl[tid] = tw[L + tid];
+    // the split's twiddles for column k = tid and (thread 0) k = L, loaded
+    // with the rows rather than after the last barrier
+    const float2 wk = tw[N + tid], wl = tw[N + L];
+    float2 tj[16];
+#pragma unroll
+    for (int m = 1; m < 16; m++) tj[m] = tw[N + j1 * m];
     bool bad = false;
 #pragma unroll 4
     for (int e = tid; e < RB * L; e += T) {
@@ -640,12 +662,11 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const int64_t *src, 
     }
     if (bad) atomicOr(flag, FLAG_OVERFLOW);
     __syncthreads();
-    fft_from<L, 1, RB, T, false, 1, L, false, 4, PS>(buf, tw + L);
-    const float2 *twN = tw + N;
+    fft_from<L, 1, RB, T, false, 1, L, false, 4, PS>(buf, twl);
     float2 *d0 = dst + (int64_t)j1 * plane + (int64_t)x1 * nhp;
     const int64_t pstep = (int64_t)N2 * plane;
     for (int k = tid; k <= L; k += T) {
-        const float2 w = twN[k];
+        const float2 w = k == tid ? wk : wl;
         float2 v[16];
 #pragma unroll
         for (int r = 0; r < 16; r++) {
@@ -657,7 +678,7 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const int64_t *src, 
         }
         Dft<16, false>::run(v);
 #pragma unroll
-        for (int m = 1; m < 16; m++) v[m] = cmul(v[m], twN[j1 * m]);
+        for (int m = 1; m < 16; m++) v[m] = cmul(v[m], tj[m]);
 #pragma unroll
         for (int m = 0; m < 16; m++) d0[m * pstep + k] = v[m];
     }
@@ -674,12 +695,19 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, f
 {
     constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, LS = L + 1, PS = 4;
     __shared__ float2 buf[padded(RB * LS, PS)];
+    __shared__ float2 twl[L];   // the row stages' twiddles (one per thread)
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int j1 = tile / N, x1 = tile % N;
     const int tid = threadIdx.x;
     const float2 *twN = tw + N;
     const float2 *s0 = src + (int64_t)j1 * plane + (int64_t)x1 * nhp;
     const int64_t pstep = (int64_t)N2 * plane;
+    // the Hermitian pre-step below: thread tid takes k = 1 + tid % (L/2) on
+    // rows (tid / (L/2)) RB/2 .. + RB/2 - 1, with one twiddle, loaded here
+    // with the columns
+    const int hk = 1 + tid % (L / 2), hr = (tid / (L / 2)) * (RB / 2);
+    const float2 hw = cconj(twN[hk]);
+    twl[tid] = tw[L + tid];
     {
         // column k = tid, and the Nyquist column k = L on thread 0, whose
         // loads are issued with the others (a second round would leave the
@@ -706,16 +734,23 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, f
     }
     __syncthreads();
     // Z_k = A + i B, A = X_k + conj X_{L-k}, B = (X_k - conj X_{L-k}) exp(+2 pi i k / N);
-    // Z_{L-k} = conj A + i conj B.
-    for (int e = tid; e < RB * (L / 2 + 1); e += T) {
-        const int r = e / (L / 2 + 1), k = e % (L / 2 + 1);
-        const float2 X = buf[pad<PS>(r * LS + k)], Y = cconj(buf[pad<PS>(r * LS + L - k)]);
-        const float2 A = cadd(X, Y), B = cmul(cconj(twN[k]), csub(X, Y));
-        buf[pad<PS>(r * LS + k)] = make_float2(A.x - B.y, A.y + B.x);
-        if (k != 0 && k != L / 2) buf[pad<PS>(r * LS + L - k)] = make_float2(A.x + B.y, B.x - A.y);
+    // Z_{L-k} = conj A + i conj B.  k = 1 .. L/2 here (T = L threads), k = 0
+    // (B = X_0 - conj X_L, no twiddle) on threads 0 .. RB-1, one row each.
+#pragma unroll
+    for (int i = 0; i < RB / 2; i++) {
+        const int r = hr + i;
+        const float2 X = buf[pad<PS>(r * LS + hk)], Y = cconj(buf[pad<PS>(r * LS + L - hk)]);
+        const float2 A = cadd(X, Y), B = cmul(hw, csub(X, Y));
+        buf[pad<PS>(r * LS + hk)] = make_float2(A.x - B.y, A.y + B.x);
+        if (hk != L / 2) buf[pad<PS>(r * LS + L - hk)] = make_float2(A.x + B.y, B.x - A.y);
+    }
+    if (tid < RB) {
+        const float2 X = buf[pad<PS>(tid * LS)], Y = cconj(buf[pad<PS>(tid * LS + L)]);
+        const float2 A = cadd(X, Y), B = csub(X, Y);
+        buf[pad<PS>(tid * LS)] = make_float2(A.x - B.y, A.y + B.x);
     }
     __syncthreads();
-    fft_from<L, 1, RB, T, false, 1, LS, true, 4, PS>(buf, tw + L);
+    fft_from<L, 1, RB, T, false, 1, LS, true, 4, PS>(buf, twl);
 #pragma unroll 4
     for (int e = tid; e < RB * L; e += T) {
         const int r = e / L, m = e % L;

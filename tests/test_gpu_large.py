@@ -4,6 +4,7 @@ size (the oracle cannot run 1024^3 or 2048^3 meshes in test time).
 A single real Fourier mode cos(2 pi n.u / N) has a half spectrum with one
 nonzero entry, N^3 / 2, and its force mesh is -1.5 Omega_m A (k / k^2)
 sin(k.u) (the single-mode pin of the oracle)."""
+import gc
 import sys
 
 import numpy as np
@@ -86,3 +87,93 @@ def test_single_mode_fft_2048(dev):
         err = max(err, float((real[a].double() / n ** 3 - torch.cos(ph)).abs().max()))
     say("fft 2048 round trip max error", err)
     assert err < 2e-6
+
+
+def _modes(n, rng):
+    """About 16 real Fourier modes per 8-column block of the half spectrum,
+    with the 16 residues of n0 mod 16 in each block: after the forward rows
+    every tile of every pass holds data, a skipped or misplaced tile shows.
+    Column blocks 0 and the last carry k2 = 0 and k2 = N/2, which the inverse
+    real transform treats apart (the k = 0 / Nyquist pair of each row)."""
+    ncb = (n // 2 + 1 + 7) // 8
+    seen, modes = set(), []
+    for cb in range(ncb):
+        for c in range(16):
+            for _ in range(100):
+                k2 = 0 if cb == 0 else (n // 2 if cb == ncb - 1 else min(8 * cb + int(rng.integers(0, 8)), n // 2))
+                n0 = c + 16 * int(rng.integers(-(n // 32), n // 32))
+                n1 = int(rng.integers(-(n // 2) + 1, n // 2))
+                if n0 <= -(n // 2) or n0 >= n // 2:
+                    continue
+                key = (n0, n1, k2)
+                if k2 in (0, n // 2):   # (n0, n1) and (-n0, -n1) are one real mode there
+                    key = max(key, (-n0, -n1, k2))
+                if key in seen or (n0, n1, k2) == (0, 0, 0):
+                    continue
+                seen.add(key)
+                modes.append((n0, n1, k2))
+                break
+    return np.array(modes, dtype=np.int64)
+
+
+@pytest.mark.parametrize("n", [512, 2048])
+def test_multi_mode_force_mesh(dev, n):
+    """Force mesh of a sum of ~16 (N/16 + 1) random-phase modes against the
+    sum of their closed forms -1.5 Omega_m A_m (k_d / k^2) sin(k.u + psi_m),
+    the component along an axis at its Nyquist frequency being zero, on one
+    output plane of every group of 16 planes the axis-0 passes combine."""
+    from paper_2007_13394_amd import pm
+    # the context (mesh + three spectra) and `out` take ~257 GiB at 2048^3:
+    # cached segments of earlier tests would not merge into them
+    gc.collect()
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(2048 + n)
+    cfg = I.config("C1", n_mesh=n, n_cdm=8, n_sites=0)
+    ctx = pm.Ctx(pm.make_config(cfg))
+    modes = _modes(n, rng)
+    M = len(modes)
+    amp = 0.005
+    psi = torch.from_numpy(rng.uniform(0, 2 * np.pi, M)).to(dev)
+    kv = torch.from_numpy(2 * np.pi * modes / n).to(dev)                      # (M, 3)
+    k2 = (kv ** 2).sum(1)
+    idx = torch.arange(n, device=dev, dtype=torch.float64)
+    V1 = torch.exp(1j * idx[:, None] * kv[None, :, 1])                         # (n, M): axis 1
+    V2 = torch.exp(1j * kv[:, 2, None] * idx[None, :]).contiguous()           # (M, n): axis 2
+    say("multi-mode force", n, M, "modes")
+
+    def field(planes, coef):
+        # Re sum_m coef_m exp(i (psi_m + k0_m a)) exp(i k1_m i) exp(i k2_m j) on planes a
+        a = torch.as_tensor(planes, device=dev, dtype=torch.float64)
+        c = coef[None, :] * torch.exp(1j * (psi[None, :] + a[:, None] * kv[None, :, 0]))   # (B, M)
+        return torch.matmul((V1[None] * c[:, None, :]).contiguous(), V2).real
+
+    out = torch.empty(3 * n ** 3, dtype=torch.float32, device=dev)
+    q = out[:2 * n ** 3].view(torch.int64).view(n, n, n)
+    ones = torch.full((M,), amp, dtype=torch.complex128, device=dev)
+    B = 8
+    for a0 in range(0, n, B):
+        q[a0:a0 + B] = torch.round((1.0 + field(range(a0, a0 + B), ones)) * 2.0 ** 40).to(torch.int64)
+    say("multi-mode force", n, "mesh built")
+    pm.pm_force_mesh(ctx, q.reshape(-1), out)
+    o = out.view(3, n, n, n)
+    n2 = n // 16
+    planes = [j + n2 * (j % 16) for j in range(n2)]
+    nyq = torch.from_numpy(np.abs(modes) == n // 2).to(dev)
+    err, ss, cnt = [0.0] * 3, 0.0, 0
+    for d in range(3):
+        # F_d = Re[-1.5 Omega_m A (k_d / k^2) (-i) e^{i theta}]
+        g = torch.where(nyq[:, d], torch.zeros_like(k2), -1.5 * 0.3 * amp * kv[:, d] / k2)
+        coef = (-1j) * g.to(torch.complex128)
+        for b0 in range(0, len(planes), B):
+            pl = planes[b0:b0 + B]
+            ref = field(pl, coef)
+            got = o[d, pl].double()
+            err[d] = max(err[d], float((got - ref).abs().max()))
+            ss += float((ref ** 2).sum())
+            cnt += ref.numel()
+    rms = (ss / cnt * 3) ** 0.5     # rms of the force vector
+    say("multi-mode force", n, "max error / rms |F| per component", [e / rms for e in err])
+    del out, q, o, ctx
+    gc.collect()
+    torch.cuda.empty_cache()
+    assert max(err) / rms < 5e-5
