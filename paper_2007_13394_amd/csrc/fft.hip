@@ -550,7 +550,11 @@ __global__ __launch_bounds__(X0Cfg<N>::T, 4) void k_x0_green(const float2 *src, 
     constexpr int N2 = X::N2, R2 = X::R2, C = X::C, SPT = X::SPT;
     __shared__ float2 lds[16 * R2 * C];
     const int m = blockIdx.y;
-    const int c = threadIdx.x % C, g = threadIdx.x / C;   // step 1: g; step 2: q = g
+    static_assert(C == 64, "one wavefront per g: g and the twiddles it selects are wave-uniform");
+    // step 1: g; step 2: q = g.  Uniform per wavefront, so the twiddles
+    // twN2[g a] come through the scalar cache instead of the vector loads
+    // that carry the spectrum.
+    const int c = threadIdx.x % C, g = __builtin_amdgcn_readfirstlane((int)threadIdx.x / C);
     const int64_t e = (int64_t)blockIdx.x * C + c;
     const int64_t pbase = (int64_t)(N2 * m + g) * plane + e;
     const int64_t pstep = (int64_t)R2 * plane;

@@ -169,21 +169,16 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
                 if (r + step < NRANGE && rpre[r + step] <= k) r += step;
             idx[u] = ok[u] ? rbeg[r] + (k - rpre[r]) : 0;
         }
-        float u0[2], u1[2], u2[2];
-        int g[2];
-#pragma unroll
-        for (int u = 0; u < 2; u++) {
-            if (ok[u]) {
-                const float4 r = xs[idx[u]];   // position and segment tag
-                u0[u] = r.x;
-                u1[u] = r.y;
-                u2[u] = r.z;
-                g[u] = __float_as_int(r.w);
-            } else {
-                u0[u] = u1[u] = u2[u] = 0.f;
-                g[u] = -1;
-            }
-        }
+        // Both loads unconditional (idx 0, a valid particle whenever the loop
+        // runs, stands in past the end) and issued back to back: a load under
+        // a branch is joined with the other path's value, and the join waits
+        // for it.  The empty asm takes all eight values, so neither load can
+        // be sunk into the branch that uses it (one memory round trip).
+        float4 r0 = xs[idx[0]], r1 = xs[idx[1]];   // position and segment tag
+        asm volatile("" : "+v"(r0.x), "+v"(r0.y), "+v"(r0.z), "+v"(r0.w), "+v"(r1.x), "+v"(r1.y), "+v"(r1.z),
+                     "+v"(r1.w));
+        const float u0[2] = {r0.x, r1.x}, u1[2] = {r0.y, r1.y}, u2[2] = {r0.z, r1.z};
+        const int g[2] = {ok[0] ? __float_as_int(r0.w) : -1, ok[1] ? __float_as_int(r1.w) : -1};
 #pragma unroll
         for (int u = 0; u < 2; u++) {
             if (!ok[u] || g[u] < lo || g[u] >= hi) continue;

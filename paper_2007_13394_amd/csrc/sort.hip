@@ -43,10 +43,31 @@ __global__ __launch_bounds__(SORT_T) void k_sort_count(const float *__restrict__
 {
     const int lane = threadIdx.x & 63;
     const int64_t c0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * SORT_CH;
-    for (int64_t base = c0; base < c0 + SORT_CH && base < P; base += SORT_T) {
-        const int64_t i = base + threadIdx.x;
-        const bool live = i < P;
-        const int k = live ? tile_key(x[i], x[P + i], x[2 * P + i], n) : -1;
+    const int64_t c1 = c0 + SORT_CH < P ? c0 + SORT_CH : P;
+    if (c0 >= c1) return;
+    // The next round's position is loaded before this round's atomic, so the
+    // two memory round trips of a round overlap.  Indices past the chunk are
+    // clamped to c0, a valid particle.
+    int64_t i = c0 + threadIdx.x;
+    float a0, a1, a2;
+    {
+        const int64_t ic = i < c1 ? i : c0;
+        a0 = x[ic];
+        a1 = x[P + ic];
+        a2 = x[2 * P + ic];
+        // taken here, the first loads leave nothing for the loop head to wait
+        // on (a wait there would also hold for the previous round's stores)
+        asm volatile("" : "+v"(a0), "+v"(a1), "+v"(a2));
+    }
+    for (int64_t base = c0; base < c1; base += SORT_T, i += SORT_T) {
+        const bool live = i < c1;
+        const int k = live ? tile_key(a0, a1, a2, n) : -1;
+        {
+            const int64_t in = i + SORT_T, ic = in < c1 ? in : c0;
+            a0 = x[ic];
+            a1 = x[P + ic];
+            a2 = x[2 * P + ic];
+        }
         // group lanes with equal keys (ballot loop: no memory traffic), then
         // the leader of every group issues its atomic in one instruction
         uint64_t todo = __ballot(live);
@@ -149,7 +170,45 @@ __global__ void k_scan_add(int *out, int64_t n, const int *sums)
 
 // Scatter into float4 records: one 16-byte store for the position and the
 // segment tag, one for the momentum, so a particle that moves far in the
-// order costs two stores instead of seven partial ones.
+// order costs two stores instead of seven partial ones.  The optional arrays
+// are template flags, so every load of a particle is issued at once (one
+// round trip, then the dependent offset lookup); the pointers do not alias
+// (caller arrays in, workspace records out), which lets unrolled iterations
+// overlap.
+template <bool HP, bool HT, bool HI>
+__device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const float *__restrict__ x,
+                                              const float *__restrict__ p, const uint8_t *__restrict__ tag_in,
+                                              int64_t P, int nseg, const int64_t *__restrict__ seg_off,
+                                              const int *__restrict__ key, const int *__restrict__ rank,
+                                              const int *__restrict__ off, float4 *__restrict__ xs,
+                                              float4 *__restrict__ ps, const uint32_t *__restrict__ ids_in,
+                                              uint32_t *__restrict__ ids_out)
+{
+#pragma unroll 2
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += SORT_T) {
+        const int k = key[i], r = rank[i];
+        const float a0 = x[i], a1 = x[P + i], a2 = x[2 * P + i];
+        float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+        if constexpr (HP) {
+            b0 = p[i];
+            b1 = p[P + i];
+            b2 = p[2 * P + i];
+        }
+        int t = 0;
+        if constexpr (HT) {
+            t = tag_in[i];
+        } else {   // canonical order: segment from the offsets
+            for (int g = 1; g < nseg; g++) t += (i >= seg_off[g]) ? 1 : 0;
+        }
+        uint32_t id = 0;
+        if constexpr (HI) id = ids_in[i];
+        const int64_t d = (int64_t)off[k] + r;
+        xs[d] = make_float4(a0, a1, a2, __int_as_float(t));
+        if constexpr (HP) ps[d] = make_float4(b0, b1, b2, 0.f);
+        if constexpr (HI) ids_out[d] = id;
+    }
+}
+
 __global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict__ x, const float *__restrict__ p,
                                                          const uint8_t *__restrict__ tag_in, int64_t P, int nseg,
                                                          const int64_t *__restrict__ seg_off, const int *key,
@@ -158,19 +217,26 @@ __global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict
 {
     const int64_t c0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * SORT_CH;
     const int64_t c1 = c0 + SORT_CH < P ? c0 + SORT_CH : P;
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += SORT_T) {
-        const int64_t d = (int64_t)off[key[i]] + rank[i];
-        int t;
+#define SCATTER(HP, HT, HI) \
+    scatter_chunk<HP, HT, HI>(c0, c1, x, p, tag_in, P, nseg, seg_off, key, rank, off, xs, ps, ids_in, ids_out)
+    if (p) {
         if (tag_in) {
-            t = tag_in[i];
-        } else {   // canonical order: segment from the offsets
-            t = 0;
-            for (int g = 1; g < nseg; g++) t += (i >= seg_off[g]) ? 1 : 0;
+            if (ids_in) SCATTER(true, true, true);
+            else SCATTER(true, true, false);
+        } else {
+            if (ids_in) SCATTER(true, false, true);
+            else SCATTER(true, false, false);
         }
-        xs[d] = make_float4(x[i], x[P + i], x[2 * P + i], __int_as_float(t));
-        if (p) ps[d] = make_float4(p[i], p[P + i], p[2 * P + i], 0.f);
-        if (ids_in) ids_out[d] = ids_in[i];
+    } else {
+        if (tag_in) {
+            if (ids_in) SCATTER(false, true, true);
+            else SCATTER(false, true, false);
+        } else {
+            if (ids_in) SCATTER(false, false, true);
+            else SCATTER(false, false, false);
+        }
     }
+#undef SCATTER
 }
 
 }  // namespace
