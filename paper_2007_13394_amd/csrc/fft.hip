@@ -299,7 +299,9 @@ __global__ __launch_bounds__(256) void k_c2r_rows(const float2 *src, int64_t src
 }
 
 // ---------------------------------------------------------------- columns
-template <int LOGN, bool INV, int WW>
+// V2: a thread moves two adjacent columns of a row per access (16 bytes;
+// base 16-byte aligned, strides even), else one (8 bytes).
+template <int LOGN, bool INV, int WW, bool V2>
 __global__ __launch_bounds__((ColCfg<LOGN, WW>::T)) void k_cols(float2 *base, int64_t stride_l, int64_t stride_o,
                                                               int n_cb, const float2 *__restrict__ tw)
 {
@@ -312,17 +314,41 @@ __global__ __launch_bounds__((ColCfg<LOGN, WW>::T)) void k_cols(float2 *base, in
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int o = tile / n_cb, cb = tile % n_cb;
     const int tid = threadIdx.x;
-    // thread owns column tid % W and rows tid / W + i T / W (T is a multiple of W)
-    float2 *p = base + (int64_t)o * stride_o + cb * W + (tid % W) + (int64_t)(tid / W) * stride_l;
-    const int64_t step = (int64_t)(T / W) * stride_l;
     constexpr int SW = W == 8 ? -(3 + ColCfg<LOGN, WW>::R1) : 0;
     for (int i = tid; i < N; i += T) twl[i] = tw[N + i];
+    if constexpr (V2) {
+        // thread owns columns 2 (tid % (W/2)) + {0, 1} and rows tid / (W/2) + i 2T / W;
+        // element (row, col) sits at row W + col, and the swizzle keeps a pair adjacent
+        static_assert(C::PER % 2 == 0 && T % (W / 2) == 0, "pairs per thread");
+        constexpr int HW = W / 2;
+        float2 *p = base + (int64_t)o * stride_o + cb * W + 2 * (tid % HW) + (int64_t)(tid / HW) * stride_l;
+        const int64_t step = (int64_t)(T / HW) * stride_l;
 #pragma unroll
-    for (int i = 0; i < C::PER; i++) buf[pad<SW>(tid + i * T)] = p[i * step];
-    __syncthreads();
-    fft_from<N, 1, W, T, true, W, 1, INV, 4, SW>(buf, twl);
+        for (int i = 0; i < C::PER / 2; i++) {
+            const float4 v = *reinterpret_cast<const float4 *>(p + i * step);
+            const int e = 2 * (tid + i * T);
+            buf[pad<SW>(e)] = make_float2(v.x, v.y);
+            buf[pad<SW>(e + 1)] = make_float2(v.z, v.w);
+        }
+        __syncthreads();
+        fft_from<N, 1, W, T, true, W, 1, INV, 4, SW>(buf, twl);
 #pragma unroll
-    for (int i = 0; i < C::PER; i++) p[i * step] = buf[pad<SW>(tid + i * T)];
+        for (int i = 0; i < C::PER / 2; i++) {
+            const int e = 2 * (tid + i * T);
+            const float2 a = buf[pad<SW>(e)], b = buf[pad<SW>(e + 1)];
+            *reinterpret_cast<float4 *>(p + i * step) = make_float4(a.x, a.y, b.x, b.y);
+        }
+    } else {
+        // thread owns column tid % W and rows tid / W + i T / W (T is a multiple of W)
+        float2 *p = base + (int64_t)o * stride_o + cb * W + (tid % W) + (int64_t)(tid / W) * stride_l;
+        const int64_t step = (int64_t)(T / W) * stride_l;
+#pragma unroll
+        for (int i = 0; i < C::PER; i++) buf[pad<SW>(tid + i * T)] = p[i * step];
+        __syncthreads();
+        fft_from<N, 1, W, T, true, W, 1, INV, 4, SW>(buf, twl);
+#pragma unroll
+        for (int i = 0; i < C::PER; i++) p[i * step] = buf[pad<SW>(tid + i * T)];
+    }
 }
 
 // ---------------------------------------------------------------- axis 0 + multiplier
@@ -755,11 +781,13 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, f
     }
     __syncthreads();
     fft_from<L, 1, RB, T, false, 1, LS, true, 4, PS>(buf, twl);
+    // 16-byte stores: two complex (four reals) per thread per round
 #pragma unroll 4
-    for (int e = tid; e < RB * L; e += T) {
-        const int r = e / L, m = e % L;
-        *reinterpret_cast<float2 *>(dst + ((int64_t)(j1 + N2 * r) * N + x1) * dst_stride + 2 * m) =
-            buf[pad<PS>(r * LS + m)];
+    for (int e = tid; e < RB * L / 2; e += T) {
+        const int r = e / (L / 2), m = 2 * (e % (L / 2));
+        const float2 a = buf[pad<PS>(r * LS + m)], b = buf[pad<PS>(r * LS + m + 1)];
+        *reinterpret_cast<float4 *>(dst + ((int64_t)(j1 + N2 * r) * N + x1) * dst_stride + 2 * m) =
+            make_float4(a.x, a.y, b.x, b.y);
     }
 }
 
@@ -823,14 +851,25 @@ hipError_t launch_cols(int logn, bool inverse, float2 *base, int64_t stride_l, i
                        int n_cb, const float2 *tw, hipStream_t s)
 {
     const unsigned nb = (unsigned)n_o * (unsigned)n_cb;
-#define COLS(LG)                                                                                     \
+    // 16-byte accesses where the layout allows them
+    const bool v2 = logn >= 4 && (reinterpret_cast<uintptr_t>(base) & 15) == 0 && stride_l % 2 == 0 &&
+                    stride_o % 2 == 0;
+#define COLS_V(LG, V)                                                                                \
     {                                                                                                \
         if (inverse)                                                                                 \
-            hipLaunchKernelGGL((k_cols<LG, true, TILE_W>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base,  \
+            hipLaunchKernelGGL((k_cols<LG, true, TILE_W, V>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base, \
                                stride_l, stride_o, n_cb, tw);                                       \
         else                                                                                         \
-            hipLaunchKernelGGL((k_cols<LG, false, TILE_W>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base, \
+            hipLaunchKernelGGL((k_cols<LG, false, TILE_W, V>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base, \
                                stride_l, stride_o, n_cb, tw);                                       \
+    }
+#define COLS(LG)                                                                                     \
+    {                                                                                                \
+        if constexpr (LG >= 4) {                                                                     \
+            if (v2) COLS_V(LG, true) else COLS_V(LG, false)                                          \
+        } else {                                                                                     \
+            COLS_V(LG, false)                                                                        \
+        }                                                                                            \
     }
     PM_DISPATCH_LOGN(logn, COLS)
     return hipGetLastError();
@@ -904,6 +943,8 @@ hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_st
                          const float2 *tw, hipStream_t s)
 {
     if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    // the rows are stored 16 bytes at a time
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) != 0 || dst_stride % 4 != 0) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
 #define C2RX(LG)                                                                                     \
     hipLaunchKernelGGL((k_c2r_x0<LG>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, dst_stride, nhp, plane, tw)
