@@ -80,7 +80,7 @@ def model_bytes(P, n):
         "cols_fwd": 16 * Mc,
         "axis0": 8 * Mc + 24 * Mc,        # spectrum in, three force spectra out
         "r2c_x0": 8 * M + 8 * Mc,         # int64 density in, half spectrum out (16-point axis-0 pass fused)
-        "x0_green": 8 * Mc + 24 * Mc,     # spectrum in, three force spectra out
+        "x0_green": 8 * Mc + 16 * Mc,     # spectrum in, k0 T and T out (k1, k2 applied by the column passes)
         "c2r_x0": 8 * Mc + 4 * M,         # half spectrum in, real force mesh out (16-point pass fused)
         "cols_inv": 16 * Mc,
         "c2r_rows": 8 * Mc + 4 * M,
@@ -89,7 +89,7 @@ def model_bytes(P, n):
         "sort_scatter": 58 * P,           # x, p, key, rank, tag in; sorted x, p, tag out
     }
     paint_step = 12 * P + 8 * M           # positions in, int64 mesh written once
-    step = 60 * P + 40 * M + 128 * Mc
+    step = 60 * P + 40 * M + 120 * Mc
     return per_launch, paint_step, step
 
 

@@ -299,11 +299,30 @@ __global__ __launch_bounds__(256) void k_c2r_rows(const float2 *src, int64_t src
 }
 
 // ---------------------------------------------------------------- columns
+// Column factor of the force components (the k1 and k2 parts of the
+// gradient of the inverse Laplacian), applied on load: 1 -> 2 pi n1 / N with
+// n1 the signed row frequency, 2 -> 2 pi k2 / N with k2 the column; zero on
+// the component's own Nyquist frequency.  The row and column are the axis-1
+// and axis-2 frequencies when the pass runs along axis 1.
+template <int N>
+__device__ __forceinline__ float col_factor(int mul, int row, int col)
+{
+    const float sc = 6.28318530717958648f / (float)N;
+    if (mul == 1) {
+        const int r1 = row <= N / 2 ? row : row - N;
+        return (r1 == N / 2 || r1 == -N / 2) ? 0.f : sc * r1;
+    }
+    return col >= N / 2 ? 0.f : sc * col;
+}
+
 // V2: a thread moves two adjacent columns of a row per access (16 bytes;
-// base 16-byte aligned, strides even), else one (8 bytes).
+// base and dst 16-byte aligned, strides even), else one (8 bytes).
+// mul != 0 scales every element by col_factor before the transform; the
+// result goes to dst (the same offsets; dst == base: in place).
 template <int LOGN, bool INV, int WW, bool V2>
 __global__ __launch_bounds__((ColCfg<LOGN, WW>::T)) void k_cols(float2 *base, int64_t stride_l, int64_t stride_o,
-                                                              int n_cb, const float2 *__restrict__ tw)
+                                                              int n_cb, const float2 *__restrict__ tw, int mul,
+                                                              float2 *dst)
 {
     using C = ColCfg<LOGN, WW>;
     constexpr int N = C::N, W = C::W, E = C::E, T = C::T;
@@ -321,14 +340,21 @@ __global__ __launch_bounds__((ColCfg<LOGN, WW>::T)) void k_cols(float2 *base, in
         // element (row, col) sits at row W + col, and the swizzle keeps a pair adjacent
         static_assert(C::PER % 2 == 0 && T % (W / 2) == 0, "pairs per thread");
         constexpr int HW = W / 2;
-        float2 *p = base + (int64_t)o * stride_o + cb * W + 2 * (tid % HW) + (int64_t)(tid / HW) * stride_l;
+        const int64_t off = (int64_t)o * stride_o + cb * W + 2 * (tid % HW) + (int64_t)(tid / HW) * stride_l;
+        const float2 *p = base + off;
+        float2 *q = dst + off;
         const int64_t step = (int64_t)(T / HW) * stride_l;
 #pragma unroll
         for (int i = 0; i < C::PER / 2; i++) {
             const float4 v = *reinterpret_cast<const float4 *>(p + i * step);
             const int e = 2 * (tid + i * T);
-            buf[pad<SW>(e)] = make_float2(v.x, v.y);
-            buf[pad<SW>(e + 1)] = make_float2(v.z, v.w);
+            float fa = 1.f, fb = 1.f;
+            if (mul) {
+                fa = col_factor<N>(mul, e / W, cb * W + e % W);
+                fb = col_factor<N>(mul, e / W, cb * W + e % W + 1);
+            }
+            buf[pad<SW>(e)] = make_float2(fa * v.x, fa * v.y);
+            buf[pad<SW>(e + 1)] = make_float2(fb * v.z, fb * v.w);
         }
         __syncthreads();
         fft_from<N, 1, W, T, true, W, 1, INV, 4, SW>(buf, twl);
@@ -336,18 +362,25 @@ __global__ __launch_bounds__((ColCfg<LOGN, WW>::T)) void k_cols(float2 *base, in
         for (int i = 0; i < C::PER / 2; i++) {
             const int e = 2 * (tid + i * T);
             const float2 a = buf[pad<SW>(e)], b = buf[pad<SW>(e + 1)];
-            *reinterpret_cast<float4 *>(p + i * step) = make_float4(a.x, a.y, b.x, b.y);
+            *reinterpret_cast<float4 *>(q + i * step) = make_float4(a.x, a.y, b.x, b.y);
         }
     } else {
         // thread owns column tid % W and rows tid / W + i T / W (T is a multiple of W)
-        float2 *p = base + (int64_t)o * stride_o + cb * W + (tid % W) + (int64_t)(tid / W) * stride_l;
+        const int64_t off = (int64_t)o * stride_o + cb * W + (tid % W) + (int64_t)(tid / W) * stride_l;
+        const float2 *p = base + off;
+        float2 *q = dst + off;
         const int64_t step = (int64_t)(T / W) * stride_l;
 #pragma unroll
-        for (int i = 0; i < C::PER; i++) buf[pad<SW>(tid + i * T)] = p[i * step];
+        for (int i = 0; i < C::PER; i++) {
+            const int e = tid + i * T;
+            const float f = mul ? col_factor<N>(mul, e / W, cb * W + e % W) : 1.f;
+            const float2 v = p[i * step];
+            buf[pad<SW>(e)] = make_float2(f * v.x, f * v.y);
+        }
         __syncthreads();
         fft_from<N, 1, W, T, true, W, 1, INV, 4, SW>(buf, twl);
 #pragma unroll
-        for (int i = 0; i < C::PER; i++) p[i * step] = buf[pad<SW>(tid + i * T)];
+        for (int i = 0; i < C::PER; i++) q[i * step] = buf[pad<SW>(tid + i * T)];
     }
 }
 
@@ -523,8 +556,9 @@ __global__ __launch_bounds__(Ax0Cfg<LOGN>::T) void k_axis0(const float2 *src, in
 // Pass A rides on the row transforms (k_r2c_x0, k_c2r_x0 below, which hold
 // the 16 rows j2 < 16 of one x1 in LDS).  The force kernel fuses pass B with
 // the gradient of the inverse Laplacian and the inverse of pass B for two
-// fields; the inverse of pass A, inside the complex-to-real rows, restores
-// natural order on all three outputs.  Plane offsets e (0 <= e < N nhp) index
+// fields; the inverse column passes apply the k1 and k2 factors (they do not
+// depend on k0, so they commute with the axis-0 inverse), and the inverse of
+// pass A, inside the complex-to-real rows, restores natural order.  Plane offsets e (0 <= e < N nhp) index
 // (k1, k2) = (e / nhp, e % nhp).
 
 // Pass B of the force solve: grid (N nhp / 64, 16), 64 R2 threads with
@@ -533,8 +567,9 @@ __global__ __launch_bounds__(Ax0Cfg<LOGN>::T) void k_axis0(const float2 *src, in
 // 16-point DFT over j1 = g + R2 i and the twiddle w_N2^(g a), step 2 (thread
 // (c, q), after an LDS exchange) the R2-point DFTs over g for a = q + R2 s,
 // giving k = a + 16 l.  T = coef i S / k^2 is kept in registers; k0 T and T
-// go through the inverse steps; outputs k0 T -> out0 (which may alias src),
-// k1 T -> out1, k2 T -> out2, each zero at k = 0 and on its own Nyquist plane.
+// go through the inverse steps; outputs k0 T -> out0 (which may alias src,
+// zero on the k0 Nyquist plane) and T -> out1, both zero at k = 0.  Writing T
+// once instead of k1 T and k2 T saves a third of the pass's writes.
 template <int N>
 struct X0Cfg {
     static constexpr int N2 = N / 16, R2 = N2 / 16, C = 64, T = C * R2, SPT = 16 / R2;
@@ -569,7 +604,7 @@ __device__ __forceinline__ void x0_inverse_b(float2 (&w)[16], float2 *lds, int c
 
 template <int N>
 __global__ __launch_bounds__(X0Cfg<N>::T, 4) void k_x0_green(const float2 *src, float2 *out0, float2 *out1,
-                                                          float2 *out2, int64_t plane, int nhp, float coef,
+                                                          int64_t plane, int nhp, float coef,
                                                           const float2 *__restrict__ tw)
 {
     using X = X0Cfg<N>;
@@ -638,19 +673,12 @@ __global__ __launch_bounds__(X0Cfg<N>::T, 4) void k_x0_green(const float2 *src, 
     }
     x0_inverse_b<N>(keep, lds, c, g, twN2);
     {
-        // k1, k2 multipliers recomputed here rather than kept live
-        const int64_t e2 = (int64_t)blockIdx.x * C + threadIdx.x % C;
-        const int r1 = signed_mode((int)(e2 / nhp), N), r2 = (int)(e2 % nhp);
-        const float f1 = (r1 == N / 2 || r1 == -N / 2) ? 0.f : sc * r1;
-        const float f2 = (r2 >= N / 2) ? 0.f : sc * r2;
-        float2 *q1 = out1 + pbase, *q2 = out2 + pbase;
+        float2 *q1 = out1 + pbase;
 #pragma unroll
         for (int i = 0; i < 16; i++) {
-            asm volatile("" : "+v"(q1), "+v"(q2));
-            *q1 = make_float2(f1 * keep[i].x, f1 * keep[i].y);
-            *q2 = make_float2(f2 * keep[i].x, f2 * keep[i].y);
+            asm volatile("" : "+v"(q1));
+            *q1 = keep[i];
             q1 += pstep;
-            q2 += pstep;
         }
     }
 }
@@ -848,20 +876,22 @@ hipError_t launch_c2r_rows(int logn, const float2 *src, int64_t src_stride, floa
 }
 
 hipError_t launch_cols(int logn, bool inverse, float2 *base, int64_t stride_l, int64_t stride_o, int n_o,
-                       int n_cb, const float2 *tw, hipStream_t s)
+                       int n_cb, const float2 *tw, hipStream_t s, int mul, float2 *dst)
 {
     const unsigned nb = (unsigned)n_o * (unsigned)n_cb;
+    if (mul < 0 || mul > 2) return hipErrorInvalidValue;
+    if (!dst) dst = base;
     // 16-byte accesses where the layout allows them
-    const bool v2 = logn >= 4 && (reinterpret_cast<uintptr_t>(base) & 15) == 0 && stride_l % 2 == 0 &&
-                    stride_o % 2 == 0;
+    const bool v2 = logn >= 4 && ((reinterpret_cast<uintptr_t>(base) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0 &&
+                    stride_l % 2 == 0 && stride_o % 2 == 0;
 #define COLS_V(LG, V)                                                                                \
     {                                                                                                \
         if (inverse)                                                                                 \
             hipLaunchKernelGGL((k_cols<LG, true, TILE_W, V>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base, \
-                               stride_l, stride_o, n_cb, tw);                                       \
+                               stride_l, stride_o, n_cb, tw, mul, dst);                             \
         else                                                                                         \
             hipLaunchKernelGGL((k_cols<LG, false, TILE_W, V>), dim3(nb), dim3(ColCfg<LG>::T), 0, s, base, \
-                               stride_l, stride_o, n_cb, tw);                                       \
+                               stride_l, stride_o, n_cb, tw, mul, dst);                             \
     }
 #define COLS(LG)                                                                                     \
     {                                                                                                \
@@ -903,14 +933,14 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
     return hipGetLastError();
 }
 
-hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, float2 *out2, int64_t plane,
-                           int nhp, double coef, const float2 *tw, hipStream_t s)
+hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, int64_t plane, int nhp,
+                           double coef, const float2 *tw, hipStream_t s)
 {
     if (logn < 8 || logn > 11 || plane % 64 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(plane / 64), 16);
     const float fc = (float)coef;
 #define X0B(NN)                                                                                      \
-    hipLaunchKernelGGL((k_x0_green<NN>), grid, dim3(X0Cfg<NN>::T), 0, s, src, out0, out1, out2, plane, nhp, fc, tw)
+    hipLaunchKernelGGL((k_x0_green<NN>), grid, dim3(X0Cfg<NN>::T), 0, s, src, out0, out1, plane, nhp, fc, tw)
     switch (logn) {
     case 8: X0B(256); break;
     case 9: X0B(512); break;

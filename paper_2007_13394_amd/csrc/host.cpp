@@ -266,9 +266,12 @@ pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s)
         const int64_t plane = (int64_t)n * nhp;
         LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0(lg, src, F, (int)nhp, plane, scale, -1.0, c->ws.tw, c->ws.flag, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
-        LAUNCH(pm::K_X0_GREEN, pm::launch_x0_green(lg, F, F, F + cs, F + 2 * cs, plane, (int)nhp, coef, c->ws.tw, s));
-        for (int d = 0; d < 3; d++) {
-            LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + d * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        // F0 <- k0 T, F1 <- T; the inverse column passes apply the k2 and
+        // k1 factors: component 2 from F1 into F2 first, then 1 in place
+        LAUNCH(pm::K_X0_GREEN, pm::launch_x0_green(lg, F, F, F + cs, plane, (int)nhp, coef, c->ws.tw, s));
+        for (int d = 2; d >= 0; d--) {
+            LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, d == 0 ? F : F + cs, nhp, n * nhp, n, ncb, c->ws.tw, s,
+                                                   d, F + d * cs));
             LAUNCH(pm::K_C2R_X0, pm::launch_c2r_x0(lg, F + d * cs, reinterpret_cast<float *>(F + d * cs), 2 * nhp,
                                                    (int)nhp, plane, c->ws.tw, s));
         }

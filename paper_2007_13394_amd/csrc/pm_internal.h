@@ -168,8 +168,10 @@ hipError_t launch_r2c_rows_f32(int logn, const float *src, int64_t src_stride, f
                                int64_t dst_stride, int64_t nrows, const float2 *tw, hipStream_t s);
 hipError_t launch_c2r_rows(int logn, const float2 *src, int64_t src_stride, float *dst,
                            int64_t dst_stride, int64_t nrows, const float2 *tw, hipStream_t s);
+// mul: 0, or the k1 (1) / k2 (2) factor of a force component applied before
+// the transform; dst: output at the same offsets (nullptr: in place).
 hipError_t launch_cols(int logn, bool inverse, float2 *base, int64_t stride_l, int64_t stride_o,
-                       int n_o, int n_cb, const float2 *tw, hipStream_t s);
+                       int n_o, int n_cb, const float2 *tw, hipStream_t s, int mul = 0, float2 *dst = nullptr);
 // axis-0 pass: forward FFT, then per output a multiplier and an inverse FFT.
 enum { MULT_FORCE = 0, MULT_IC = 1, MULT_NONE = 2 };
 hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int64_t s_o, float2 *out0,
@@ -181,8 +183,8 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
 // nf fields field_stride apart, and pass B fused with the gradient of the
 // inverse Laplacian (src may alias out0; outputs digit-reversed until the
 // inverse of pass A).
-hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, float2 *out2, int64_t plane,
-                           int nhp, double coef, const float2 *tw, hipStream_t s);
+hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, int64_t plane, int nhp,
+                           double coef, const float2 *tw, hipStream_t s);
 // Row transforms fused with pass A (forward: int64 density rows -> twiddled
 // pass-A output; inverse: pass-A inverse -> real rows, in place allowed).
 hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int64_t plane, double scale,
