@@ -117,11 +117,12 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
     __shared__ long long qtab[MAX_SEG];
     __shared__ int rbeg[NRANGE], rpre[NRANGE + 1];
     const int nt = n / TILE, mask = n - 1;
-    // workgroups walk the tiles in row-major order (consecutive tiles share
-    // rows of the mesh); particle ranges are looked up by Morton index
-    const int b = xcd_tile(blockIdx.x, gridDim.x);
-    const int t0 = b / (nt * nt), t1 = (b / nt) % nt, t2 = b % nt;
-    const int t = tile_index(t0, t1, t2);
+    // workgroups walk the tiles in Morton order (the sort keys' order, nt a
+    // power of two): the neighbour ranges a tile reads were mostly just read
+    // by the tiles around it
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int t2 = (int)morton_compact((unsigned)t), t1 = (int)morton_compact((unsigned)t >> 1),
+              t0 = (int)morton_compact((unsigned)t >> 2);
     for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PAINT_T) acc[i] = 0;
     for (int i = threadIdx.x; i < nseg; i += PAINT_T) qtab[i] = quanta[i];
     // range 0: the own tile (all flags); ranges 1..19: lower neighbour e != 0,

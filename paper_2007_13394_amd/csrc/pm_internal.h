@@ -51,6 +51,16 @@ __device__ __forceinline__ int tile_index(int t0, int t1, int t2)
     return (int)(morton_spread((unsigned)t2) | (morton_spread((unsigned)t1) << 1) |
                  (morton_spread((unsigned)t0) << 2));
 }
+// Inverse of morton_spread: every third bit of v, packed.
+__device__ __forceinline__ unsigned morton_compact(unsigned v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030C30C3u;
+    v = (v | (v >> 4)) & 0x0300F00Fu;
+    v = (v | (v >> 8)) & 0x030000FFu;
+    v = (v | (v >> 16)) & 0x000003FFu;
+    return v;
+}
 
 // Device-side guard bits (workspace flag word).
 enum { FLAG_OVERFLOW = 1, FLAG_NAN = 2 };
