@@ -450,10 +450,28 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const int64_t *__restrict__ q
 #pragma unroll
     for (int pr = 0; pr < NPAIR; pr++)
         wa[pr] = *reinterpret_cast<const v8bf *>(wpk + WPK_W2 / 2 + ((pr * NET_C + col) * 4 + kg) * 8);
-    for (int e = tid; e < U1N; e += 256) {
-        const int ux = e % U1X, uy = (e / U1X) % U1Y, uz = e / (U1X * U1Y);
-        const int64_t row = (int64_t)((z0 + uz - 2) & m) * n + ((y0 + uy - 2) & m);
-        U[e] = delta_bf16(q[row * n + ((x0 + ux - 2) & m)], qs);
+    {
+        // every load of the halo fill issued before the first LDS store (one
+        // memory round trip per tile rather than one per round); indices past
+        // the end are clamped, and the empty asm keeps the loads from being
+        // sunk into the guarded stores
+        constexpr int NU = (U1N + 255) / 256;
+        static_assert(NU == 8, "eight int64 loads per thread");
+        int64_t qv[NU];
+#pragma unroll
+        for (int k = 0; k < NU; k++) {
+            const int e = min(tid + 256 * k, U1N - 1);
+            const int ux = e % U1X, uy = (e / U1X) % U1Y, uz = e / (U1X * U1Y);
+            const int64_t row = (int64_t)((z0 + uz - 2) & m) * n + ((y0 + uy - 2) & m);
+            qv[k] = q[row * n + ((x0 + ux - 2) & m)];
+        }
+        asm volatile("" : "+v"(qv[0]), "+v"(qv[1]), "+v"(qv[2]), "+v"(qv[3]), "+v"(qv[4]), "+v"(qv[5]), "+v"(qv[6]),
+                     "+v"(qv[7]));
+#pragma unroll
+        for (int k = 0; k < NU; k++) {
+            const int e = tid + 256 * k;
+            if (e < U1N) U[e] = delta_bf16(qv[k], qs);
+        }
     }
     __syncthreads();
     {
@@ -528,23 +546,48 @@ __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ 
     static_assert(16 * TY * (TZ / ZPT) == 256 && TZ % ZPT == 0, "conv3 tile shape");
     constexpr int HX = 18, HY = TY + 2, HZ = TZ + 2, HALO = HX * HY * HZ;
     // channel halves of each halo voxel in two planes: 16-byte rows, no bank conflicts
-    __shared__ __align__(16) uint4 X[2 * HALO];
+    // + one slot per lane after the two planes (stores of idle fill tasks)
+    __shared__ __align__(16) uint4 X[2 * HALO + 64];
     __shared__ __align__(16) uint32_t W[27 * NET_C / 2];   // BF16 pairs [t][ci / 2]
     const int tid = threadIdx.x;
     const int ntx = n / 16, nty = n / TY;
     const int tile = blockIdx.x;
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
     const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ, m = n - 1;
-    for (int e = tid; e < 27 * NET_C / 8; e += 256)
-        reinterpret_cast<uint4 *>(W)[e] = reinterpret_cast<const uint4 *>(wpk + WPK_W3 / 2)[e];
-    for (int e = tid; e < HALO * 2; e += 256) {
-        const int hv = e >> 1, half = e & 1;
-        const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-        const int64_t g = ((int64_t)((z0 + hz - 1) & m) * n + ((y0 + hy - 1) & m)) * n + ((x0 + hx - 1) & m);
-        X[half * HALO + hv] = reinterpret_cast<const uint4 *>(a2 + g * NET_C)[half];
+    const int lx = tid % 16, ly = (tid / 16) % TY, zg = tid / (16 * TY);
+    // phi_f of the thread's voxels, loaded now rather than after the sums
+    float pf[ZPT];
+#pragma unroll
+    for (int z = 0; z < ZPT; z++) pf[z] = phif[((int64_t)(z0 + zg * ZPT + z) * n + (y0 + ly)) * rs + (x0 + lx)];
+    {
+        // Every load of the halo fill is issued before the first LDS store
+        // (one memory round trip per tile, not one per round).  Indices past
+        // the end are clamped, and those lanes store to their own slot after
+        // the tile, so no store is guarded (a guarded store would let the
+        // compiler sink its load into the guard).
+        constexpr int NX = (HALO * 2 + 255) / 256;
+        uint4 xv[NX];
+#pragma unroll
+        for (int k = 0; k < NX; k++) {
+            const int e = min(tid + 256 * k, HALO * 2 - 1);
+            const int hv = e >> 1, half = e & 1;
+            const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+            const int64_t g = ((int64_t)((z0 + hz - 1) & m) * n + ((y0 + hy - 1) & m)) * n + ((x0 + hx - 1) & m);
+            xv[k] = reinterpret_cast<const uint4 *>(a2 + g * NET_C)[half];
+        }
+        // the conv3 weights, one 16-byte row per thread, unconditional like
+        // the halo (lanes past the last row store to their slot after the tile)
+        constexpr int NW = 27 * NET_C / 8;
+        static_assert(NW <= 256, "one weight row per thread");
+        const uint4 wv = reinterpret_cast<const uint4 *>(wpk + WPK_W3 / 2)[min(tid, NW - 1)];
+        *(tid < NW ? reinterpret_cast<uint4 *>(W) + tid : X + 2 * HALO + (tid & 63)) = wv;
+#pragma unroll
+        for (int k = 0; k < NX; k++) {
+            const int e = tid + 256 * k;
+            X[e < HALO * 2 ? (e & 1) * HALO + (e >> 1) : 2 * HALO + (tid & 63)] = xv[k];
+        }
     }
     __syncthreads();
-    const int lx = tid % 16, ly = (tid / 16) % TY, zg = tid / (16 * TY);
     const float b = th[NC3B];
     float acc[ZPT];
 #pragma unroll
@@ -577,7 +620,7 @@ __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ 
 #pragma unroll
     for (int z = 0; z < ZPT; z++) {
         const int64_t o = ((int64_t)(z0 + zg * ZPT + z) * n + (y0 + ly)) * rs + (x0 + lx);
-        out[o] = phif[o] + acc[z];
+        out[o] = pf[z] + acc[z];
     }
 }
 
