@@ -191,8 +191,9 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
 // fields of nhp-padded half spectra whose planes hold `plane` = N nhp complex:
 // pass A (16-point DFTs over planes N/16 apart, twiddled; or its inverse) on
 // nf fields field_stride apart, and pass B fused with the gradient of the
-// inverse Laplacian (src may alias out0; outputs digit-reversed until the
-// inverse of pass A).
+// inverse Laplacian: out0 <- k0 T, out1 <- T, T = coef i S / k^2 (src may
+// alias out0; the k1 and k2 factors are applied by the inverse column passes,
+// launch_cols mul 1 and 2; outputs digit-reversed until the inverse of pass A).
 hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, int64_t plane, int nhp,
                            double coef, const float2 *tw, hipStream_t s);
 // Row transforms fused with pass A (forward: int64 density rows -> twiddled
