@@ -114,14 +114,22 @@ struct Dft<1, INV> {
 // R apart (-PS = 3 + log2 R), then spread over four groups of eight bank
 // pairs, and aligned groups of four rows only permute, so consecutive
 // accesses stay conflict-free; no extra LDS.
+//
+// PS == SWZ_ROWS (rows of N/2 complex, one per Stockham transform, radix
+// 16/8/8): bits 0-4 of i are XORed with bits 4-8 and bit 4 also with bit 7.
+// Within aligned groups of 32 elements this only permutes, so consecutive
+// accesses stay conflict-free, and the strided writes of every stage spread
+// over all bank pairs, with no extra LDS.
+constexpr int SWZ_ROWS = 32;
 template <int PS>
 __device__ __forceinline__ int pad(int i)
 {
-    if constexpr (PS > 0) return i + (i >> PS);
+    if constexpr (PS == SWZ_ROWS) return i ^ ((i >> 4) & 31) ^ (((i >> 7) & 1) << 4);
+    else if constexpr (PS > 0) return i + (i >> PS);
     else if constexpr (PS < 0) return i ^ (((i >> (-PS)) & 3) << 3);
     else return i;
 }
-constexpr int padded(int n, int ps) { return ps > 0 ? n + (n >> ps) + 1 : n; }
+constexpr int padded(int n, int ps) { return ps > 0 && ps != SWZ_ROWS ? n + (n >> ps) + 1 : n; }
 
 // One Stockham stage of radix R over NC independent transforms of length L
 // held in LDS: element (c, l) at buf[c * SC + l * SL].  NS = product of the
@@ -696,7 +704,7 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const int64_t *src, 
                                                             double scale, double offset,
                                                             const float2 *__restrict__ tw, int *flag)
 {
-    constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, PS = 4;
+    constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, PS = SWZ_ROWS;
     __shared__ float2 buf[padded(RB * L, PS)];
     __shared__ float2 twl[L];   // the row stages' twiddles (one per thread)
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -751,9 +759,10 @@ template <int LOGN>
 __global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, float *dst, int64_t dst_stride,
                                                             int nhp, int64_t plane, const float2 *__restrict__ tw)
 {
-    constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, LS = L + 1, PS = 4;
+    constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, LS = L, PS = SWZ_ROWS;
     __shared__ float2 buf[padded(RB * LS, PS)];
     __shared__ float2 twl[L];   // the row stages' twiddles (one per thread)
+    __shared__ float2 xnq[RB];  // the Nyquist column X_L of the 16 rows
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int j1 = tile / N, x1 = tile % N;
     const int tid = threadIdx.x;
@@ -787,7 +796,7 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, f
             for (int m = 1; m < 16; m++) vn[m] = cmul(vn[m], cconj(twN[j1 * m]));
             Dft<16, true>::run(vn);
 #pragma unroll
-            for (int r = 0; r < 16; r++) buf[pad<PS>(r * LS + L)] = vn[r];
+            for (int r = 0; r < 16; r++) xnq[r] = vn[r];
         }
     }
     __syncthreads();
@@ -803,7 +812,7 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, f
         if (hk != L / 2) buf[pad<PS>(r * LS + L - hk)] = make_float2(A.x + B.y, B.x - A.y);
     }
     if (tid < RB) {
-        const float2 X = buf[pad<PS>(tid * LS)], Y = cconj(buf[pad<PS>(tid * LS + L)]);
+        const float2 X = buf[pad<PS>(tid * LS)], Y = cconj(xnq[tid]);
         const float2 A = cadd(X, Y), B = csub(X, Y);
         buf[pad<PS>(tid * LS)] = make_float2(A.x - B.y, A.y + B.x);
     }
