@@ -85,8 +85,8 @@ def model_bytes(P, n):
         "cols_inv": 16 * Mc,
         "c2r_rows": 8 * Mc + 4 * M,
         "readout_kick_drift": 12 * M + 48 * P,
-        "sort_count": 20 * P,             # positions in, key and rank out
-        "sort_scatter": 58 * P,           # x, p, key, rank, tag in; sorted x, p, tag out
+        "sort_count": 12 * P,             # positions in (counts per key only)
+        "sort_scatter": 50 * P,           # x, p, tag in (key recomputed); sorted x, p, tag out
     }
     paint_step = 12 * P + 8 * M           # positions in, int64 mesh written once
     step = 60 * P + 40 * M + 120 * Mc

@@ -62,7 +62,7 @@ int ilog2i(int v)
 }
 
 struct Layout {
-    size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags, ids, koff, key, rank, cnt, bsum, total;
+    size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags, ids, koff, cnt, bsum, total;
     size_t net_phif, net_z1, net_a1, net_z2, net_a2, net_g1, net_g2, net_dpsi, net_dk, net_acc, net_table, net_tbar,
         net_red, net_wpk;
     int64_t nkeys;
@@ -97,7 +97,7 @@ Layout layout(const pm_config &c)
     off = align256(off + (size_t)(3 * (2 * c.n_fib + 1) + 2 * c.n_shell + ((c.flags & PM_FLAG_NU_PSEUDO) ? 4097 : 0)) * 4);
     L.segtab = off;
     off = align256(off + (size_t)(2 * pm::MAX_SEG + 1) * 8);
-    L.xs = L.ps = L.tags = L.ids = L.koff = L.key = L.rank = L.cnt = L.bsum = 0;
+    L.xs = L.ps = L.tags = L.ids = L.koff = L.cnt = L.bsum = 0;
     if (L.nkeys > 0) {
         // tile-sorted particle records and the tags survive the whole step
         L.xs = off;
@@ -112,15 +112,13 @@ Layout layout(const pm_config &c)
         off = align256(off + (size_t)(4 * (L.nkeys + 1)));
         // sort scratch is dead before the FFT writes the force region: alias it there when it fits
         const size_t nb = (size_t)((L.nkeys + 1 + 2047) / 2048 + 1);
-        const size_t scratch = align256(4 * (size_t)P) * 2 + align256(4 * (size_t)(L.nkeys + 1)) + align256(4 * nb);
+        const size_t scratch = align256(4 * (size_t)(L.nkeys + 1)) + align256(4 * nb);
         size_t s0 = L.f;
         if (scratch > fbytes) {
             s0 = off;
             off = align256(off + scratch);
         }
-        L.key = s0;
-        L.rank = L.key + align256(4 * (size_t)P);
-        L.cnt = L.rank + align256(4 * (size_t)P);
+        L.cnt = s0;
         L.bsum = L.cnt + align256(4 * (size_t)(L.nkeys + 1));
     }
     L.net_phif = L.net_z1 = L.net_a1 = L.net_z2 = L.net_a2 = L.net_g1 = L.net_g2 = L.net_dpsi = L.net_dk = 0;
@@ -228,12 +226,13 @@ pm_status tile_sort(pm_ctx *c, const float *x, const float *p, hipStream_t s)
 {
     const int64_t K = c->nkeys;
     LAUNCH(pm::K_FILL, pm::launch_fill_i32(c->ws.cnt, K + 1, s));
-    LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, c->ws.cnt, c->ws.key, c->ws.rank, s));
-    LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt, c->ws.koff, K + 1, c->ws.bsum, s));
+    LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, c->ws.cnt, s));
+    // koff <- exclusive scan of the counts; cnt <- the same, as cursors
+    LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt, c->ws.koff, K + 1, c->ws.bsum, s, c->ws.cnt));
     const uint8_t *tin = c->permuted ? c->ws.tags : nullptr;
     LAUNCH(pm::K_SORT_SCATTER,
-           pm::launch_sort_scatter(x, p, tin, c->P, c->nseg, c->ws.seg_off, c->ws.key, c->ws.rank, c->ws.koff,
-                                   c->ws.xs, p ? c->ws.ps : nullptr, c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
+           pm::launch_sort_scatter(x, p, tin, c->P, c->nseg, c->ws.seg_off, c->n, c->ws.cnt, c->ws.xs,
+                                   p ? c->ws.ps : nullptr, c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
     return PM_OK;
 }
 
@@ -449,8 +448,6 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
         c->ws.tags = reinterpret_cast<uint8_t *>(b + L.tags);
         c->ws.ids_tmp = reinterpret_cast<uint32_t *>(b + L.ids);
         c->ws.koff = reinterpret_cast<int *>(b + L.koff);
-        c->ws.key = reinterpret_cast<int *>(b + L.key);
-        c->ws.rank = reinterpret_cast<int *>(b + L.rank);
         c->ws.cnt = reinterpret_cast<int *>(b + L.cnt);
         c->ws.bsum = reinterpret_cast<int *>(b + L.bsum);
     }

@@ -80,9 +80,7 @@ struct Workspace {
     float4 *ps = nullptr;        // tile-sorted momenta (p0, p1, p2, 0) [P]
     uint8_t *tags = nullptr;     // segment tag per particle in the caller's current order [P]
     uint32_t *ids_tmp = nullptr; // tile-sorted ids [P]
-    int *key = nullptr;          // sort key per particle (aliases the F region)
-    int *rank = nullptr;         // rank within key
-    int *cnt = nullptr;          // counts per key (K + 1)
+    int *cnt = nullptr;          // counts per key (K + 1), then the scatter's cursors (aliases the F region)
     int *koff = nullptr;         // exclusive offsets per key (K + 1)
     int *bsum = nullptr;         // scan block sums
     // learned force correction (PM_FLAG_LEARNED)
@@ -255,11 +253,14 @@ hipError_t launch_paint_tiles(const float4 *xs, const int *koff, const int64_t *
                               int seg_hi, int n, int64_t *mesh, hipStream_t s);
 
 // ---- launchers (sort.hip)
-hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, int *key, int *rank, hipStream_t s);
-hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipStream_t s);
+// Counting sort by tile key: counts per key (cnt zeroed by the caller), an
+// exclusive scan (out2: a second copy, the scatter's cursors), and the
+// scatter of particles to their cursor slots (cursor advanced by the counts).
+hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, hipStream_t s);
+hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipStream_t s, int *out2 = nullptr);
 hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
-                               const int64_t *seg_off, const int *key, const int *rank, const int *off, float4 *xs,
-                               float4 *ps, const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s);
+                               const int64_t *seg_off, int n, int *cursor, float4 *xs, float4 *ps,
+                               const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s);
 
 // ---- launchers (particles.hip)
 hipError_t launch_fill_i64(int64_t *p, int64_t count, hipStream_t s);

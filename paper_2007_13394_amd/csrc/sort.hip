@@ -5,11 +5,14 @@
 // TILE^3-cell block holding floor(u); bit d of the flags is set when floor(u_d) is the last
 // cell of the tile along axis d (its +1 cloud-in-cell corner then lies in the
 // next tile).  Counting: one atomic per distinct key per wavefront (lanes
-// sharing a key are ranked by ballot), so lattice-ordered CDM, where most of
+// sharing a key are grouped by ballot), so lattice-ordered CDM, where most of
 // a wavefront falls in one tile, costs few atomics.  Offsets come from an
-// exclusive scan of the counts; the scatter writes the position record (with
-// the segment tag), the momentum and the optional id of particle i to
-// offset[key_i] + rank_i.
+// exclusive scan of the counts, which also leaves a copy of them as per-key
+// cursors; the scatter recomputes each particle's key from its position,
+// takes its slot from the cursor (one returning atomic per key and
+// wavefront, lanes ranked by ballot), and writes the position record (with
+// the segment tag), the momentum and the optional id there.  The order of
+// particles within a key depends on the order of the atomics.
 #include "pm_internal.h"
 
 namespace pm {
@@ -38,59 +41,51 @@ __device__ __forceinline__ int tile_key(float u0, float u1, float u2, int n)
 // sorted state then writes whole cache lines from one L2).
 constexpr int SORT_T = 256, SORT_CH = SORT_T * 8;
 
-__global__ __launch_bounds__(SORT_T) void k_sort_count(const float *__restrict__ x, int64_t P, int n, int *cnt,
-                                                       int *key, int *rank)
+// Lanes of the wavefront that share this lane's key: the mask and its
+// lowest lane (ballot loop, no memory traffic).
+__device__ __forceinline__ void key_group(bool live, int k, uint64_t &group, int &leader)
+{
+    uint64_t todo = __ballot(live);
+    group = 0;
+    leader = 0;
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        const int lk = __shfl(k, l);
+        const uint64_t same = __ballot(live && k == lk);
+        if (live && k == lk) {
+            group = same;
+            leader = l;
+        }
+        todo &= ~same;
+    }
+}
+
+__global__ __launch_bounds__(SORT_T) void k_sort_count(const float *__restrict__ x, int64_t P, int n, int *cnt)
 {
     const int lane = threadIdx.x & 63;
     const int64_t c0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * SORT_CH;
     const int64_t c1 = c0 + SORT_CH < P ? c0 + SORT_CH : P;
     if (c0 >= c1) return;
-    // The next round's position is loaded before this round's atomic, so the
-    // two memory round trips of a round overlap.  Indices past the chunk are
-    // clamped to c0, a valid particle.
-    int64_t i = c0 + threadIdx.x;
-    float a0, a1, a2;
-    {
-        const int64_t ic = i < c1 ? i : c0;
-        a0 = x[ic];
-        a1 = x[P + ic];
-        a2 = x[2 * P + ic];
-        // taken here, the first loads leave nothing for the loop head to wait
-        // on (a wait there would also hold for the previous round's stores)
-        asm volatile("" : "+v"(a0), "+v"(a1), "+v"(a2));
+    // All rounds' positions are loaded up front (8 per thread; indices past
+    // the chunk are clamped to c0, a valid particle); the atomics return
+    // nothing, so no round waits on memory after the first.
+    constexpr int NR = SORT_CH / SORT_T;
+    float a0[NR], a1[NR], a2[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const int64_t i = c0 + threadIdx.x + r * SORT_T, ic = i < c1 ? i : c0;
+        a0[r] = x[ic];
+        a1[r] = x[P + ic];
+        a2[r] = x[2 * P + ic];
     }
-    for (int64_t base = c0; base < c1; base += SORT_T, i += SORT_T) {
-        const bool live = i < c1;
-        const int k = live ? tile_key(a0, a1, a2, n) : -1;
-        {
-            const int64_t in = i + SORT_T, ic = in < c1 ? in : c0;
-            a0 = x[ic];
-            a1 = x[P + ic];
-            a2 = x[2 * P + ic];
-        }
-        // group lanes with equal keys (ballot loop: no memory traffic), then
-        // the leader of every group issues its atomic in one instruction
-        uint64_t todo = __ballot(live);
-        uint64_t group = 0;
-        int leader = 0;
-        while (todo) {
-            const int l = __ffsll((unsigned long long)todo) - 1;
-            const int lk = __shfl(k, l);
-            const uint64_t same = __ballot(live && k == lk);
-            if (live && k == lk) {
-                group = same;
-                leader = l;
-            }
-            todo &= ~same;
-        }
-        int b = 0;
-        if (live && lane == leader) b = atomicAdd(cnt + k, __popcll(group));
-        b = __shfl(b, leader);
-        const int r = b + __popcll(group & ((1ull << lane) - 1));
-        if (live) {
-            key[i] = k;
-            rank[i] = r;
-        }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const bool live = c0 + threadIdx.x + r * SORT_T < c1;
+        const int k = live ? tile_key(a0[r], a1[r], a2[r], n) : -1;
+        uint64_t group;
+        int leader;
+        key_group(live, k, group, leader);
+        if (live && lane == leader) atomicAdd(cnt + k, __popcll(group));
     }
 }
 
@@ -162,63 +157,92 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_sums(int *sums, int nb)
     }
 }
 
-__global__ void k_scan_add(int *out, int64_t n, const int *sums)
+// out2 (optional): a second copy of the result.
+__global__ void k_scan_add(int *out, int64_t n, const int *sums, int *out2)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] += sums[i / SCAN_B];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int v = out[i] + sums[i / SCAN_B];
+        out[i] = v;
+        if (out2) out2[i] = v;
+    }
 }
 
 // Scatter into float4 records: one 16-byte store for the position and the
 // segment tag, one for the momentum, so a particle that moves far in the
 // order costs two stores instead of seven partial ones.  The optional arrays
-// are template flags, so every load of a particle is issued at once (one
-// round trip, then the dependent offset lookup); the pointers do not alias
-// (caller arrays in, workspace records out), which lets unrolled iterations
-// overlap.
+// are template flags, so a particle's loads are issued at once; the next
+// round's position is loaded before this round's atomic, so the two memory
+// round trips of a round overlap.  The pointers do not alias (caller arrays
+// in, workspace records out).
 template <bool HP, bool HT, bool HI>
 __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const float *__restrict__ x,
                                               const float *__restrict__ p, const uint8_t *__restrict__ tag_in,
-                                              int64_t P, int nseg, const int64_t *__restrict__ seg_off,
-                                              const int *__restrict__ key, const int *__restrict__ rank,
-                                              const int *__restrict__ off, float4 *__restrict__ xs,
-                                              float4 *__restrict__ ps, const uint32_t *__restrict__ ids_in,
-                                              uint32_t *__restrict__ ids_out)
+                                              int64_t P, int nseg, const int64_t *__restrict__ seg_off, int n,
+                                              int *cursor, float4 *__restrict__ xs, float4 *__restrict__ ps,
+                                              const uint32_t *__restrict__ ids_in, uint32_t *__restrict__ ids_out)
 {
-#pragma unroll 2
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += SORT_T) {
-        const int k = key[i], r = rank[i];
-        const float a0 = x[i], a1 = x[P + i], a2 = x[2 * P + i];
+    const int lane = threadIdx.x & 63;
+    int64_t i = c0 + threadIdx.x;
+    float a0, a1, a2;
+    {
+        const int64_t ic = i < c1 ? i : c0;
+        a0 = x[ic];
+        a1 = x[P + ic];
+        a2 = x[2 * P + ic];
+        // taken here, the first loads leave nothing for the loop head to wait on
+        asm volatile("" : "+v"(a0), "+v"(a1), "+v"(a2));
+    }
+    for (int64_t base = c0; base < c1; base += SORT_T, i += SORT_T) {
+        const bool live = i < c1;
+        const int64_t ic = live ? i : c0;
+        const float u0 = a0, u1 = a1, u2 = a2;
+        const int k = live ? tile_key(u0, u1, u2, n) : -1;
         float b0 = 0.f, b1 = 0.f, b2 = 0.f;
         if constexpr (HP) {
-            b0 = p[i];
-            b1 = p[P + i];
-            b2 = p[2 * P + i];
+            b0 = p[ic];
+            b1 = p[P + ic];
+            b2 = p[2 * P + ic];
         }
         int t = 0;
         if constexpr (HT) {
-            t = tag_in[i];
+            t = tag_in[ic];
         } else {   // canonical order: segment from the offsets
-            for (int g = 1; g < nseg; g++) t += (i >= seg_off[g]) ? 1 : 0;
+            for (int g = 1; g < nseg; g++) t += (ic >= seg_off[g]) ? 1 : 0;
         }
         uint32_t id = 0;
-        if constexpr (HI) id = ids_in[i];
-        const int64_t d = (int64_t)off[k] + r;
-        xs[d] = make_float4(a0, a1, a2, __int_as_float(t));
-        if constexpr (HP) ps[d] = make_float4(b0, b1, b2, 0.f);
-        if constexpr (HI) ids_out[d] = id;
+        if constexpr (HI) id = ids_in[ic];
+        {
+            const int64_t in = i + SORT_T, icn = in < c1 ? in : c0;
+            a0 = x[icn];
+            a1 = x[P + icn];
+            a2 = x[2 * P + icn];
+        }
+        uint64_t group;
+        int leader;
+        key_group(live, k, group, leader);
+        int b = 0;
+        if (live && lane == leader) b = atomicAdd(cursor + k, __popcll(group));
+        b = __shfl(b, leader);
+        if (live) {
+            const int64_t d = (int64_t)b + __popcll(group & ((1ull << lane) - 1));
+            xs[d] = make_float4(u0, u1, u2, __int_as_float(t));
+            if constexpr (HP) ps[d] = make_float4(b0, b1, b2, 0.f);
+            if constexpr (HI) ids_out[d] = id;
+        }
     }
 }
 
 __global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict__ x, const float *__restrict__ p,
                                                          const uint8_t *__restrict__ tag_in, int64_t P, int nseg,
-                                                         const int64_t *__restrict__ seg_off, const int *key,
-                                                         const int *rank, const int *off, float4 *xs, float4 *ps,
-                                                         const uint32_t *ids_in, uint32_t *ids_out)
+                                                         const int64_t *__restrict__ seg_off, int n, int *cursor,
+                                                         float4 *xs, float4 *ps, const uint32_t *ids_in,
+                                                         uint32_t *ids_out)
 {
     const int64_t c0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * SORT_CH;
     const int64_t c1 = c0 + SORT_CH < P ? c0 + SORT_CH : P;
+    if (c0 >= c1) return;
 #define SCATTER(HP, HT, HI) \
-    scatter_chunk<HP, HT, HI>(c0, c1, x, p, tag_in, P, nseg, seg_off, key, rank, off, xs, ps, ids_in, ids_out)
+    scatter_chunk<HP, HT, HI>(c0, c1, x, p, tag_in, P, nseg, seg_off, n, cursor, xs, ps, ids_in, ids_out)
     if (p) {
         if (tag_in) {
             if (ids_in) SCATTER(true, true, true);
@@ -241,32 +265,32 @@ __global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict
 
 }  // namespace
 
-hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, int *key, int *rank, hipStream_t s)
+hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, hipStream_t s)
 {
     const int64_t nb = (P + SORT_CH - 1) / SORT_CH;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sort_count, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SORT_T), 0, s, x, P, n, cnt, key, rank);
+    hipLaunchKernelGGL(k_sort_count, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SORT_T), 0, s, x, P, n, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipStream_t s)
+hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipStream_t s, int *out2)
 {
     const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
     if (nb > (int64_t)SCAN_B * 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, block_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, s, block_sums, (int)nb);
-    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n, 256)), dim3(256), 0, s, out, n, block_sums);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n, 256)), dim3(256), 0, s, out, n, block_sums, out2);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
-                               const int64_t *seg_off, const int *key, const int *rank, const int *off, float4 *xs,
-                               float4 *ps, const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s)
+                               const int64_t *seg_off, int n, int *cursor, float4 *xs, float4 *ps,
+                               const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s)
 {
     const int64_t nb = (P + SORT_CH - 1) / SORT_CH;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SORT_T), 0, s, x, p, tag_in, P, nseg, seg_off, key,
-                       rank, off, xs, ps, ids_in, ids_out);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SORT_T), 0, s, x, p, tag_in, P, nseg,
+                       seg_off, n, cursor, xs, ps, ids_in, ids_out);
     return hipGetLastError();
 }
 
