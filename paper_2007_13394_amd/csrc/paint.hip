@@ -104,9 +104,9 @@ __global__ __launch_bounds__(256) void k_paint_tagged(const float *__restrict__ 
 // sums are formed with LDS atomics and the tile is written once with plain
 // stores, so the mesh needs no zero fill and no global atomics.  The own
 // tile's particles (one contiguous range) and the 19 neighbour ranges are
-// walked as one flat index space, two particles per thread per round, so
+// walked as one flat index space, four particles per thread per round, so
 // that the global loads of a thread are independent of each other.
-constexpr int PAINT_T = 256, NRANGE = 20;
+constexpr int PAINT_T = 256, NRANGE = 20, NPT = 4;   // NPT particles per thread per round
 
 __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restrict__ xs,
                                                          const int *__restrict__ koff,
@@ -157,11 +157,11 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
     __syncthreads();
     const int total = rpre[NRANGE];
     const int ox = t0 * TILE, oy = t1 * TILE, oz = t2 * TILE;
-    for (int k0 = threadIdx.x; k0 < total; k0 += 2 * PAINT_T) {
-        int idx[2];
-        bool ok[2];
+    for (int k0 = threadIdx.x; k0 < total; k0 += NPT * PAINT_T) {
+        int idx[NPT];
+        bool ok[NPT];
 #pragma unroll
-        for (int u = 0; u < 2; u++) {
+        for (int u = 0; u < NPT; u++) {
             const int k = k0 + u * PAINT_T;
             ok[u] = k < total;
             int r = 0;   // last range whose prefix is <= k
@@ -170,18 +170,21 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
                 if (r + step < NRANGE && rpre[r + step] <= k) r += step;
             idx[u] = ok[u] ? rbeg[r] + (k - rpre[r]) : 0;
         }
-        // Both loads unconditional (idx 0, a valid particle whenever the loop
+        // All loads unconditional (idx 0, a valid particle whenever the loop
         // runs, stands in past the end) and issued back to back: a load under
         // a branch is joined with the other path's value, and the join waits
-        // for it.  The empty asm takes all eight values, so neither load can
-        // be sunk into the branch that uses it (one memory round trip).
-        float4 r0 = xs[idx[0]], r1 = xs[idx[1]];   // position and segment tag
+        // for it.  The empty asm takes every loaded value, so no load can be
+        // sunk into the branch that uses it (one memory round trip per round).
+        float4 r0 = xs[idx[0]], r1 = xs[idx[1]], r2 = xs[idx[2]], r3 = xs[idx[3]];   // position and tag
         asm volatile("" : "+v"(r0.x), "+v"(r0.y), "+v"(r0.z), "+v"(r0.w), "+v"(r1.x), "+v"(r1.y), "+v"(r1.z),
-                     "+v"(r1.w));
-        const float u0[2] = {r0.x, r1.x}, u1[2] = {r0.y, r1.y}, u2[2] = {r0.z, r1.z};
-        const int g[2] = {ok[0] ? __float_as_int(r0.w) : -1, ok[1] ? __float_as_int(r1.w) : -1};
+                     "+v"(r1.w), "+v"(r2.x), "+v"(r2.y), "+v"(r2.z), "+v"(r2.w), "+v"(r3.x), "+v"(r3.y), "+v"(r3.z),
+                     "+v"(r3.w));
+        const float u0[NPT] = {r0.x, r1.x, r2.x, r3.x}, u1[NPT] = {r0.y, r1.y, r2.y, r3.y},
+                    u2[NPT] = {r0.z, r1.z, r2.z, r3.z};
+        const int g[NPT] = {ok[0] ? __float_as_int(r0.w) : -1, ok[1] ? __float_as_int(r1.w) : -1,
+                            ok[2] ? __float_as_int(r2.w) : -1, ok[3] ? __float_as_int(r3.w) : -1};
 #pragma unroll
-        for (int u = 0; u < 2; u++) {
+        for (int u = 0; u < NPT; u++) {
             if (!ok[u] || g[u] < lo || g[u] >= hi) continue;
             int c[3][2];
             long long q[8];
