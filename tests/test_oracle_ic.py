@@ -104,3 +104,37 @@ def test_neutrino_site_displacement_is_the_field_half_a_cell_off():
     tot = tot / n ** 3 * (16 / 64.0)
     j = (1 * 2 + 0) * 2 + 1
     assert np.allclose(dn[:, j], tot, rtol=1e-10, atol=1e-14)
+
+
+def test_free_streaming_transfer_against_a_hand_computed_k_fs():
+    """The neutrino displacement is the CDM one times 1 / (1 + (k / k_fs)^2)
+    (the configurations' neutrino spectrum is the CDM spectrum times
+    [1 + (k / k_fs)^2]^-2), with k_fs the free-streaming wavenumber of
+    Lesgourgues & Pastor (2006), 0.82 sqrt(Omega_L + Omega_m (1+z)^3) /
+    (1+z)^2 (m / 1 eV) h/Mpc.  Worked by hand for Omega_m = 0.3, z = 99,
+    m = 0.1 / 3 eV: Omega_L = 0.69995 after radiation and neutrinos, so
+    sqrt(0.69995 + 0.3e6) = 547.72320, times 0.82 = 449.13302, over
+    (1+z)^2 = 1e4 and times 1 / 30 eV: k_fs = 1.4971101e-3 h/Mpc.  A box of
+    4096 Mpc/h puts its fundamental mode (1.5339808e-3 h/Mpc) near k_fs,
+    where the suppression is 0.4878376 and moves with k_fs one to one."""
+    s = _sim(n_cdm=8, n_sites=2, n_mesh=16, box=4096.0)
+    n = 8
+    i0 = np.arange(n)
+    w = np.broadcast_to(np.cos(2 * np.pi * i0 / n)[:, None, None], (n, n, n)).astype(np.float32)
+    x, p, dc, dn = O.ic(s, w, want_disp=True)
+    # CDM displacement along axis 0 on the lattice: alpha cos + beta sin of the mode
+    th = 2 * np.pi / n
+    f0 = dc[0].reshape(n, n, n)[:, 0, 0]
+    alpha, beta = 2 * np.mean(f0 * np.cos(th * i0)), 2 * np.mean(f0 * np.sin(th * i0))
+    assert np.allclose(dc[0].reshape(n, n, n), f0[:, None, None], rtol=0, atol=1e-15 * np.abs(f0).max())
+    assert np.abs(dc[1:]).max() < 1e-15 * np.abs(f0).max()
+    # sites sit half a lattice cell off the lattice points: g = j R + R / 2 + 1/2 (R = 4)
+    g = (np.arange(2) * 4 + 2 + 0.5)
+    pred = alpha * np.cos(th * g) + beta * np.sin(th * g)
+    got = dn[0].reshape(2, 2, 2)
+    T = np.sum(got * pred[:, None, None]) / np.sum(4 * pred ** 2)
+    assert np.allclose(got, T * pred[:, None, None], rtol=1e-12, atol=1e-16)
+    k = 2 * np.pi / 4096.0
+    assert abs(k - 1.5339808e-3) < 1e-10
+    assert abs(T / (1.0 / (1.0 + (k / 1.4971101e-3) ** 2)) - 1) < 1e-6
+    assert abs(T - 0.4878376) < 1e-6

@@ -139,3 +139,41 @@ def test_learned_loss_gradient_finite_differences(name):
             v[o:o + n] = rng.standard_normal(n)
         fd = (4.0 * cd(v, h / 2) - cd(v, h)) / 3.0
         assert _rel(fd, np.sum(d * v)) < 1e-7, part
+
+
+def test_mlp_hidden_layers_closed_form_through_silu_pairs():
+    """silu(z) - silu(-z) = z for every z, so two hidden units fed +z and -z,
+    read with weights +1 and -1 by the next layer, pass z through exactly.
+    Chaining such pairs through all three hidden layers at unrelated unit
+    indices makes the MLP the affine map h = c0 + c1 kt + c2 a.  A transposed
+    weight matrix, swapped inputs (kt, a), a misplaced bias or a dropped
+    layer breaks the identity."""
+    H = O.NET_H
+    th = np.zeros(O.NET_NPARAM)
+    W0, B0 = O.NET_OFF["W0"][0], O.NET_OFF["B0"][0]
+    W1, B1 = O.NET_OFF["W1"][0], O.NET_OFF["B1"][0]
+    W2, B2 = O.NET_OFF["W2"][0], O.NET_OFF["B2"][0]
+    W3, B3 = O.NET_OFF["W3"][0], O.NET_OFF["B3"][0]
+    c1, c2, c0 = 0.37, -1.9, 0.125
+    u0, v0 = 3, 70        # layer-0 pair: z0 = c1 kt + c2 a + c0
+    u1, v1 = 11, 40       # layer-1 pair: z1 = 2 z0 - 0.5
+    u2, v2 = 90, 5        # layer-2 pair: z2 = -z1 + 0.25
+    for j, sg in ((u0, 1.0), (v0, -1.0)):
+        th[W0 + j * 2 + 0] = sg * c1
+        th[W0 + j * 2 + 1] = sg * c2
+        th[B0 + j] = sg * c0
+    for j, sg in ((u1, 1.0), (v1, -1.0)):
+        th[W1 + j * H + u0] = sg * 2.0
+        th[W1 + j * H + v0] = -sg * 2.0
+        th[B1 + j] = -sg * 0.5
+    for j, sg in ((u2, 1.0), (v2, -1.0)):
+        th[W2 + j * H + u1] = -sg
+        th[W2 + j * H + v1] = sg
+        th[B2 + j] = sg * 0.25
+    th[W3 + u2], th[W3 + v2], th[B3] = 3.0, -3.0, -0.75
+    for a in (0.05, 0.4, 1.0):
+        kt = np.array([O.net_kt(b) for b in range(O.NET_NB)])
+        z0 = c1 * kt + c2 * a + c0
+        z2 = -(2 * z0 - 0.5) + 0.25
+        expect = 1.0 + 3.0 * z2 - 0.75
+        assert np.allclose(O.net_table(th, a), expect, rtol=0, atol=1e-13)
