@@ -174,3 +174,34 @@ def synthetic_density_q(n, seed, shift=40):
     idx = rng.integers(0, n, size=(3, 8))
     rho[idx[0], idx[1], idx[2]] += 500.0
     return np.rint(np.ldexp(rho, shift)).astype(np.int64)
+
+
+def tile_face_positions(n, count, seed, tile=16):
+    """Paint edge cases at the faces of the tile^3-cell blocks that a tiled
+    paint works on: on each axis independently (so every combination of
+    axes occurs) the cell is the last of its block, the last of the mesh
+    (its upper corner wraps to cell 0) or a random one, and the offset in the
+    cell is 0 (a cell face), 1/2, random, or the largest float32 below the
+    next face (N - eps on the last cell).  A tenth of the particles form
+    clumps on single points of such cells."""
+    rng = np.random.default_rng(seed)
+    nt = n // tile
+    cell = rng.integers(0, n, size=(3, count))
+    kind = rng.integers(0, 4, size=(3, count))
+    last_of_tile = rng.integers(0, nt, size=(3, count)) * tile + (tile - 1)
+    cell = np.where(kind == 0, last_of_tile, cell)
+    cell = np.where(kind == 1, n - 1, cell)
+    frac_kind = rng.integers(0, 4, size=(3, count))
+    x = cell.astype(np.float32)
+    below = np.nextafter((cell + 1).astype(np.float32), np.float32(0))
+    x = np.where(frac_kind == 1, x + np.float32(0.5), x)
+    x = np.where(frac_kind == 2, (cell + rng.uniform(0, 1, size=(3, count))).astype(np.float32), x)
+    x = np.where(frac_kind == 3, below, x)
+    x = x.astype(np.float32)
+    nclump = count // 10
+    if nclump:
+        pts = x[:, rng.integers(0, count, size=8)]
+        x[:, count - nclump:] = pts[:, rng.integers(0, 8, size=nclump)]
+    x[x >= n] = 0
+    x[x < 0] = 0
+    return np.ascontiguousarray(x)
