@@ -94,42 +94,46 @@ def model_bytes(P, n):
 
 
 def cpu_baseline(P_target, n_target):
-    """The oracle as it stands, one step on the C2 shape (512^3 mesh, 19.07M
-    particles, synthetic evolved state), particle and mesh parts timed apart
-    and scaled to the target workload (particle part x P, mesh part x M log M)."""
+    """The oracle as it stands: one FP64 orc_step (paint, FFT, Green's
+    function, three inverse FFTs, readout, kick and drift) on synthetic
+    evolved states of the C1, C5, C4-coarse and C2 shapes, timed on the host
+    cores, and a least-squares fit t = c + a P + b M ln M over the four (relative
+    residuals), extrapolated to the target workload, whose 2048^3 FP64 mesh
+    does not fit in host memory."""
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     import numpy as np
     import oracle as O
     from paper_2007_13394_amd import inputs as I
-    cfg = I.config("C2")
-    s = O.make_sim(cfg)
-    x32, p32 = I.synthetic_state(cfg, seed=99)
-    x, p = x32.astype(np.float64), p32.astype(np.float64)
-    P = x.shape[1]
-    n = cfg["n_mesh"]
-    t0 = time.perf_counter()
-    mesh = O.paint_sim(s, x)
-    t1 = time.perf_counter()
-    F = O.force_mesh(mesh, cfg["shift"], cfg["omega_m"])
-    t2 = time.perf_counter()
-    acc = O.readout(F, x)
-    p += 0.5 * acc
-    x = np.mod(x + 0.1 * p, n)
-    t3 = time.perf_counter()
-    t_part = (t1 - t0) + (t3 - t2)
-    t_mesh = t2 - t1
-    M, Mt = n ** 3, n_target ** 3
-    t_target = t_part * P_target / P + t_mesh * (Mt * math.log(Mt)) / (M * math.log(M))
+    rows = []
+    for name in ("C1", "C5", "C4_coarse", "C2"):
+        cfg = I.config(name)
+        s = O.make_sim(cfg)
+        x32, p32 = I.synthetic_state(cfg, seed=99)
+        x, p = x32.astype(np.float64), p32.astype(np.float64)
+        kick, drift = O.kdk_factors(s.cosmo, [0.5], [0.48], [0.52], [0.54])
+        t0 = time.perf_counter()
+        O.step(s, x, p, float(kick[0]), float(drift[0]))
+        dt = time.perf_counter() - t0
+        M = cfg["n_mesh"] ** 3
+        rows.append((name, x.shape[1], M, dt))
+        del x, p
+    A = np.array([[1.0 / t, P / t, M * math.log(M) / t] for _, P, M, t in rows])
+    coef, *_ = np.linalg.lstsq(A, np.ones(len(rows)), rcond=None)
+    c0, a, b = (float(v) for v in coef)
+    resid = [(c0 + a * P + b * M * math.log(M)) / t - 1.0 for _, P, M, t in rows]
+    Mt = n_target ** 3
+    t_target = c0 + a * P_target + b * Mt * math.log(Mt)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    meas = ", ".join(f"{nm} {P} particles {round(M ** (1 / 3))}^3 mesh {t:.2f} s ({P / t:.3g}/s, fit {r:+.1%})"
+                     for (nm, P, M, t), r in zip(rows, resid))
     return {
         "value": P_target / t_target,
         "unit": "particle-steps/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"one FP64 oracle step on the C2 shape ({n}^3 mesh, {P} particles, synthetic evolved state): "
-                   f"paint+readout+kick/drift {t_part:.2f} s, FFT+Green {t_mesh:.2f} s, scaled to "
-                   f"{P_target} particles (x P) and a {n_target}^3 mesh (x M log M); measured C2 rate "
-                   f"{P / (t_part + t_mesh):.3g} particle-steps/s"),
+        "sample": (f"one FP64 oracle step (orc_step, synthetic evolved state) each: {meas}; fit t = c + a P + b M ln M, "
+                   f"c = {c0:.3g} s, a = {a:.3g} s, b = {b:.3g} s, extrapolated to {P_target} particles on a {n_target}^3 mesh "
+                   f"(t = {t_target:.1f} s/step)"),
     }
 
 

@@ -31,7 +31,13 @@
  *     dx/da = p / (a^3 E) and dp/da = F / (a^2 E).
  *   - The force is F = -grad phi with lap phi = 1.5 Omega_m delta in mesh
  *     units; masses are normalised to a mean of one unit per cell.
- *   - Mass is accumulated in fixed point: one unit of mass is 2^shift.
+ *   - Mass is accumulated in fixed point: one unit of mass is 2^shift, and a
+ *     cell holds at most 2^(63 - shift) units (mean-cell masses) before its
+ *     int64 sum wraps.  The device guard flags a cell that reads below
+ *     -2^36 quanta: a sum that wrapped into [2^63, 2^64 - 2^36) is reported
+ *     as PM_ERR_OVERFLOW; a sum that passed 2^64 is not detected.  (A cell
+ *     with no other mass may legitimately hold a few negative quanta: each
+ *     particle's last corner takes its quantum minus seven rounded corners.)
  *   - "device" pointers are HIP device memory owned by the caller; "host"
  *     pointers are ordinary host memory owned by the caller.  The library
  *     never allocates device memory: all scratch lives in the caller's
@@ -165,7 +171,10 @@ pm_status pm_ic(pm_ctx *ctx, const float *white, float *x, float *p, void *strea
 pm_status pm_ic_pseudo(pm_ctx *ctx, const float *white, const float *u, float *x, float *p, void *stream);
 
 /* Cloud-in-cell assignment of particles [first, first + count) with one mass
- * quantum, ADDED to the int64 mesh (caller zeroes it).
+ * quantum, ADDED to the int64 mesh (caller zeroes it).  This is the mass
+ * assignment of the particle-mesh method FastPM is built on (Sec. 1 and
+ * 2.3); the density it builds is the source of Poisson's equation, to which
+ * CDM and neutrino particles both contribute (Sec. 2.2, "Om_pois" eq.).
  *   x      : device float32, coordinate d of particle i at x[d * stride + i],
  *            every value in [0, N)
  *   mesh_q : device int64 [N]^3
@@ -177,7 +186,13 @@ pm_status pm_paint_q(pm_ctx *ctx, const float *x, int64_t stride, int64_t first,
                      int64_t quantum, int64_t *mesh_q, void *stream);
 
 /* pm_paint_q over segments [seg_lo, seg_hi) of a [3][P] particle array, each
- * with its own quantum; added to mesh_q (device int64 [N]^3). */
+ * with its own quantum; added to mesh_q (device int64 [N]^3).  Segment 0 is
+ * the CDM, segment 1 + s neutrino shell s with the shell's mass fraction
+ * (Sec. 2.1, "m_shell" eq.); painting all of them gives the total-matter
+ * density of the Poisson source (Sec. 2.2, "Om_pois" eq.).  On a sorting
+ * context the particles are tile-sorted into the workspace and painted tile
+ * by tile (the same integers as pm_paint_q); otherwise with global atomics.
+ * Errors: PM_ERR_ARG for a bad segment range or NULL pointer. */
 pm_status pm_paint(pm_ctx *ctx, const float *x, int32_t seg_lo, int32_t seg_hi, int64_t *mesh_q,
                    void *stream);
 
@@ -194,13 +209,18 @@ pm_status pm_fft_c2r(pm_ctx *ctx, const float *spec, float *real, void *stream);
 
 /* Force meshes from a fixed-point density: delta = Q 2^-shift - 1, F_d(k) =
  * 1.5 Omega_m i k_d / k^2 delta(k) (zero at k = 0 and on the Nyquist plane of
- * component d).  mesh_q: device int64 [N]^3; out: device float32 [3][N]^3.
+ * component d): Poisson's equation with the matter source of Sec. 2.2
+ * ("Om_pois" eq., Omega_m = Omega_c0 + Omega_nu0) solved by FFT, and minus
+ * its gradient.  mesh_q: device int64 [N]^3; out: device float32 [3][N]^3.
  * mesh_q is consumed completely before out is written, so it may lie inside
  * out's memory (a caller short of memory can build the density there). */
 pm_status pm_force_mesh(pm_ctx *ctx, const int64_t *mesh_q, float *out, void *stream);
 
 /* Force on every particle at positions x: paint all segments, solve, read
- * back with cloud-in-cell weights.  x: device [3][P]; acc: device [3][P]. */
+ * back with cloud-in-cell weights (the force of the particle-mesh step,
+ * Sec. 2.2 "Om_pois" eq. and Sec. 2.3).  x: device [3][P] in the context's
+ * current order; acc: device [3][P], same order.  Errors: PM_ERR_OVERFLOW as
+ * for pm_step (unless PM_FLAG_NO_GUARDS). */
 pm_status pm_force(pm_ctx *ctx, const float *x, float *acc, void *stream);
 
 /* One call of the kick-drift-kick loop (Sec. 2.3): force at x (time

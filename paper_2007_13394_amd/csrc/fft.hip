@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_r2c_rows(const SRC *src, int64_t src_st
         float a, b;
         if constexpr (std::is_same<SRC, int64_t>::value) {
             const longlong2 q = *reinterpret_cast<const longlong2 *>(s);
-            bad |= (q.x < -(1LL << 40)) | (q.y < -(1LL << 40));
+            bad |= (q.x < GUARD_MIN_Q) | (q.y < GUARD_MIN_Q);
             a = (float)((double)q.x * scale + offset);
             b = (float)((double)q.y * scale + offset);
         } else {
@@ -723,7 +723,7 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const int64_t *src, 
         const int r = e / L, m = e % L;
         const longlong2 q =
             *reinterpret_cast<const longlong2 *>(src + ((int64_t)(j1 + N2 * r) * N + x1) * N + 2 * m);
-        bad |= (q.x < -(1LL << 40)) | (q.y < -(1LL << 40));
+        bad |= (q.x < GUARD_MIN_Q) | (q.y < GUARD_MIN_Q);
         buf[pad<PS>(e)] = make_float2((float)((double)q.x * scale + offset), (float)((double)q.y * scale + offset));
     }
     if (bad) atomicOr(flag, FLAG_OVERFLOW);

@@ -64,6 +64,13 @@ __device__ __forceinline__ unsigned morton_compact(unsigned v)
 
 // Device-side guard bits (workspace flag word).
 enum { FLAG_OVERFLOW = 1, FLAG_NAN = 2 };
+// A painted cell below this many quanta has wrapped past 2^63.  Cells are
+// sums of positive particle quanta, but a particle's remainder corner (its
+// quantum minus seven rounded corners) can be a few units negative when its
+// true weight is nearly zero, so an otherwise empty cell may read -1..-3 per
+// such particle; the threshold leaves room for far more of those than there
+// can be particles, independent of the fixed-point shift.
+constexpr long long GUARD_MIN_Q = -(1LL << 36);
 
 struct Workspace {
     char *base = nullptr;

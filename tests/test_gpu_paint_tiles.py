@@ -75,7 +75,8 @@ def test_tile_paint_bit_exact_vs_oracle(dev, name):
         got = mesh.cpu().numpy().reshape(n, n, n)
         ref = _oracle_mesh(x64, off, q, n, lo, hi)
         assert np.array_equal(got, ref), f"{name} segments [{lo}, {hi}): {int(np.sum(got != ref))} cells differ"
-        assert int(got.sum()) == int(sum((off[g + 1] - off[g]) * q[g] for g in range(lo, hi)))
+        total = sum(int(off[g + 1] - off[g]) * int(q[g]) for g in range(lo, hi))   # exact, Python ints
+        assert int(got.sum(dtype=np.uint64)) == total % 2 ** 64   # the mesh total wraps like the sum
         del got, ref
     # full paint again after shuffling every segment: identical mesh
     mesh.zero_()
