@@ -71,15 +71,18 @@ def copy_calibration():
 
 
 def model_bytes(P, n):
-    """Algorithmic HBM bytes per kernel kind per launch, and per step (fused
-    minimum: one read and one write of each mesh per pass)."""
+    """Algorithmic HBM bytes per launch of each kernel kind as implemented
+    (one read and one write of what the kernel must move), the paint's per
+    step, and the step's model-A bytes 60 P + 40 M + 128 Mc (fused minimum
+    passes with an int64 mesh written and read once), against which the step
+    is placed on the roofline."""
     M = n ** 3
     Mc = n * n * (n // 2 + 1)
     per_launch = {
         "r2c_rows": 8 * M + 8 * Mc,       # int64 density in, half spectrum out
         "cols_fwd": 16 * Mc,
         "axis0": 8 * Mc + 24 * Mc,        # spectrum in, three force spectra out
-        "r2c_x0": 8 * M + 8 * Mc,         # int64 density in, half spectrum out (16-point axis-0 pass fused)
+        "r2c_x0": 4 * M + 8 * Mc,         # float32 density contrast in, half spectrum out (16-point pass fused)
         "x0_green": 8 * Mc + 16 * Mc,     # spectrum in, k0 T and T out (k1, k2 applied by the column passes)
         "c2r_x0": 8 * Mc + 4 * M,         # half spectrum in, real force mesh out (16-point pass fused)
         "cols_inv": 16 * Mc,
@@ -88,8 +91,8 @@ def model_bytes(P, n):
         "sort_count": 12 * P,             # positions in (counts per key only)
         "sort_scatter": 50 * P,           # x, p, tag in (key recomputed); sorted x, p, tag out
     }
-    paint_step = 12 * P + 8 * M           # positions in, int64 mesh written once
-    step = 60 * P + 40 * M + 120 * Mc
+    paint_step = 12 * P + 4 * M           # positions in, float32 density contrast written once
+    step = 60 * P + 40 * M + 128 * Mc
     return per_launch, paint_step, step
 
 
@@ -199,24 +202,43 @@ def runtime_increase():
             "shapes": rows, "not_run": not_run}
 
 
-def learned_speed(steps=10):
-    """Live speed half of the learned-vs-plain comparison (C4, 19 070 976
-    particles): learned steps on the 256^3 mesh against plain steps on the
-    256^3 and 1024^3 meshes, tile-sorted contexts.  The accuracy half needs
-    training and is measured by `python -m paper_2007_13394_amd.learn`."""
+def learned_vs_plain(steps=10, seeds=(200, 201, 202, 203)):
+    """Both halves of the learned-vs-plain comparison on C4 (19 070 976
+    particles, 25 linear steps from z = 19).  Speed: learned steps on the
+    256^3 mesh against plain steps on the 256^3 and 1024^3 meshes, sorted
+    contexts, `steps` calls after two untimed ones.  Accuracy: the committed
+    parameters (trained and calibrated by `python -m paper_2007_13394_amd.learn`
+    on seeds 100-115, loaded with allow_pickle=False) run full learned coarse
+    runs from held-out seeds; each is compared with the plain fine-mesh run
+    and the plain coarse run from the same seed, painted on the coarse mesh,
+    by max |P / P_fine - 1| and min r(k) over k < k_Nyq / 2, per seed and for
+    the spectra averaged over the seeds."""
+    from paper_2007_13394_amd import inputs as I
     from paper_2007_13394_amd import learn
     co = learn.time_steps("C4_coarse", steps)
     fi = learn.time_steps("C4_fine", steps, which=("plain",))
-    return {"workload": "C4: 256^3 CDM + 32^3 sites x 70 neutrinos, L=256 Mpc/h; learned correction on a 256^3 "
-                        "mesh vs plain PM on a 1024^3 mesh",
+    theta = learn.load_params(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2007_13394_amd",
+                                           "c4_learned_theta.npy"))
+    held = learn.heldout(I.config("C4_coarse"), I.config("C4_fine"), list(seeds), theta)
+    per_seed = [{"seed": r["seed"], "learned_max_err": round(r["learned"], 5),
+                 "learned_r_min": round(r["learned_r_min"], 4),
+                 "plain_coarse_max_err": round(r["plain_coarse"], 5),
+                 "plain_coarse_r_min": round(r["plain_coarse_r_min"], 4)} for r in held["pk_max_rel_err_per_seed"]]
+    worst = max(r["learned_max_err"] for r in per_seed)
+    return {"workload": "C4: 256^3 CDM + 32^3 sites x 70 neutrinos, L=256 Mpc/h, 25 linear steps from z=19; learned "
+                        "correction on a 256^3 mesh vs plain PM on a 1024^3 mesh",
             "particles": co["particles"], "steps_timed": steps,
             "learned_coarse_ms_per_step": round(co["learned_ms_per_step"], 3),
             "plain_coarse_ms_per_step": round(co["plain_ms_per_step"], 3),
             "plain_fine_ms_per_step": round(fi["plain_ms_per_step"], 3),
             "learned_particle_steps_per_s": co["particles"] / (co["learned_ms_per_step"] * 1e-3),
             "speedup_vs_fine": round(fi["plain_ms_per_step"] / co["learned_ms_per_step"], 2),
-            "accuracy": "measured by python -m paper_2007_13394_amd.learn (trains, then judges P(k) on held-out "
-                        "seeds); not run here"}
+            "accuracy": {"k_range_hMpc": [round(v, 4) for v in held["k_range_hMpc"]], "held_out_seeds": per_seed,
+                         "mean_spectrum_learned_max_err": round(held["pk_max_rel_err"]["learned"], 5),
+                         "mean_spectrum_plain_coarse_max_err": round(held["pk_max_rel_err"]["plain_coarse"], 5),
+                         "mean_spectrum_learned_r_min": round(held["r_min"]["learned"], 4),
+                         "mean_spectrum_plain_coarse_r_min": round(held["r_min"]["plain_coarse"], 4),
+                         "every_seed_within_1pct": bool(worst <= 0.01)}}
 
 
 def main():
@@ -338,8 +360,8 @@ def main():
     del ctx, x, p
     torch.cuda.empty_cache()
     if not args.no_learned and args.config == "C3":
-        log("[bench] timing learned (256^3 mesh) and plain (256^3, 1024^3 meshes) steps on C4")
-        out["learned_vs_plain"] = learned_speed()
+        log("[bench] learned (256^3 mesh) vs plain (256^3, 1024^3 meshes) on C4: step timing, held-out runs")
+        out["learned_vs_plain"] = learned_vs_plain()
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")

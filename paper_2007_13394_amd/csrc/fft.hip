@@ -699,8 +699,11 @@ __global__ __launch_bounds__(X0Cfg<N>::T, 4) void k_x0_green(const float2 *src, 
 // and the inverse DFT over m, then the 16 complex-to-real rows.  The x1
 // transform commutes with both, so it may run before or after.  L = N/2
 // threads, 16 rows of L complex in LDS (128 KiB at N = 2048).
-template <int LOGN>
-__global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const int64_t *src, float2 *dst, int nhp, int64_t plane,
+// SRC int64_t: the fixed-point density, converted to delta = Q scale + offset
+// on load (overflow flag as in the row transform); SRC float: the density
+// contrast itself, written by the tile paint.
+template <int LOGN, typename SRC>
+__global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const SRC *src, float2 *dst, int nhp, int64_t plane,
                                                             double scale, double offset,
                                                             const float2 *__restrict__ tw, int *flag)
 {
@@ -721,10 +724,15 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const int64_t *src, 
 #pragma unroll 4
     for (int e = tid; e < RB * L; e += T) {
         const int r = e / L, m = e % L;
-        const longlong2 q =
-            *reinterpret_cast<const longlong2 *>(src + ((int64_t)(j1 + N2 * r) * N + x1) * N + 2 * m);
-        bad |= (q.x < GUARD_MIN_Q) | (q.y < GUARD_MIN_Q);
-        buf[pad<PS>(e)] = make_float2((float)((double)q.x * scale + offset), (float)((double)q.y * scale + offset));
+        const SRC *row = src + ((int64_t)(j1 + N2 * r) * N + x1) * N + 2 * m;
+        if constexpr (std::is_same<SRC, int64_t>::value) {
+            const longlong2 q = *reinterpret_cast<const longlong2 *>(row);
+            bad |= (q.x < GUARD_MIN_Q) | (q.y < GUARD_MIN_Q);
+            buf[pad<PS>(e)] =
+                make_float2((float)((double)q.x * scale + offset), (float)((double)q.y * scale + offset));
+        } else {
+            buf[pad<PS>(e)] = *reinterpret_cast<const float2 *>(row);
+        }
     }
     if (bad) atomicOr(flag, FLAG_OVERFLOW);
     __syncthreads();
@@ -966,8 +974,26 @@ hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int
     if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
 #define R2CX(LG)                                                                                     \
-    hipLaunchKernelGGL((k_r2c_x0<LG>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, nhp, plane, scale, offset, \
-                       tw, flag)
+    hipLaunchKernelGGL((k_r2c_x0<LG, int64_t>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, nhp, plane, scale, \
+                       offset, tw, flag)
+    switch (logn) {
+    case 8: R2CX(8); break;
+    case 9: R2CX(9); break;
+    case 10: R2CX(10); break;
+    default: R2CX(11); break;
+    }
+#undef R2CX
+    return hipGetLastError();
+}
+
+hipError_t launch_r2c_x0_f32(int logn, const float *src, float2 *dst, int nhp, int64_t plane, const float2 *tw,
+                             hipStream_t s)
+{
+    if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
+#define R2CX(LG)                                                                                     \
+    hipLaunchKernelGGL((k_r2c_x0<LG, float>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, nhp, plane, 1.0, 0.0, \
+                       tw, static_cast<int *>(nullptr))
     switch (logn) {
     case 8: R2CX(8); break;
     case 9: R2CX(9); break;

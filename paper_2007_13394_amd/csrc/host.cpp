@@ -62,7 +62,7 @@ int ilog2i(int v)
 }
 
 struct Layout {
-    size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags, ids, koff, cnt, bsum, total;
+    size_t q, f, tw, flag, partial, tables, segtab, xs, ps, tags, ids, koff, cnt, bsum, cnt_next, total;
     size_t net_phif, net_z1, net_a1, net_z2, net_a2, net_g1, net_g2, net_dpsi, net_dk, net_acc, net_table, net_tbar,
         net_red, net_wpk;
     int64_t nkeys;
@@ -97,7 +97,7 @@ Layout layout(const pm_config &c)
     off = align256(off + (size_t)(3 * (2 * c.n_fib + 1) + 2 * c.n_shell + ((c.flags & PM_FLAG_NU_PSEUDO) ? 4097 : 0)) * 4);
     L.segtab = off;
     off = align256(off + (size_t)(2 * pm::MAX_SEG + 1) * 8);
-    L.xs = L.ps = L.tags = L.ids = L.koff = L.cnt = L.bsum = 0;
+    L.xs = L.ps = L.tags = L.ids = L.koff = L.cnt = L.bsum = L.cnt_next = 0;
     if (L.nkeys > 0) {
         // tile-sorted particle records and the tags survive the whole step
         L.xs = off;
@@ -109,6 +109,10 @@ Layout layout(const pm_config &c)
         L.ids = off;
         off = align256(off + (size_t)(4 * P));
         L.koff = off;
+        off = align256(off + (size_t)(4 * (L.nkeys + 1)));
+        // counts of the next step's keys, written by the tile readout while it
+        // reads the force region: a region of its own
+        L.cnt_next = off;
         off = align256(off + (size_t)(4 * (L.nkeys + 1)));
         // sort scratch is dead before the FFT writes the force region: alias it there when it fits
         const size_t nb = (size_t)((L.nkeys + 1 + 2047) / 2048 + 1);
@@ -222,14 +226,37 @@ pm_status paint_atomic(pm_ctx *c, const float *x, int lo, int hi, int64_t *mesh,
 // xs (position and tag), ps, ids_tmp and the key offsets koff.  p may be
 // NULL.  The tag array itself keeps the caller's order until a readout
 // writes the particles back in sorted order.
+//
+// When the last tile readout wrote x, it also counted the keys of the
+// positions it wrote (cnt_next): the sort then skips its count pass, and a
+// check after the scatter (every key's cursor must end at the next key's
+// offset) confirms that the counts still describe x.  If the caller changed
+// x in between, the check fails and the sort is redone from a fresh count
+// (the scatter never writes past the record arrays).  The check waits for the
+// stream, so it is used only when the end-of-call guards wait anyway.
 pm_status tile_sort(pm_ctx *c, const float *x, const float *p, hipStream_t s)
 {
     const int64_t K = c->nkeys;
+    const uint8_t *tin = c->permuted ? c->ws.tags : nullptr;
+    if (c->counts_ready && x == c->counts_x && !(c->cfg.flags & PM_FLAG_NO_GUARDS)) {
+        LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt_next, c->ws.koff, K + 1, c->ws.bsum, s, c->ws.cnt));
+        LAUNCH(pm::K_SORT_SCATTER,
+               pm::launch_sort_scatter(x, p, tin, c->P, c->nseg, c->ws.seg_off, c->n, c->ws.cnt, c->ws.xs,
+                                       p ? c->ws.ps : nullptr, c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
+        LAUNCH(pm::K_SORT_VERIFY, pm::launch_sort_verify(c->ws.cnt, c->ws.koff, K, c->ws.flag, s));
+        int h = 0;
+        HIPCHK(hipMemcpyAsync(&h, c->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!(h & pm::FLAG_STALE)) return PM_OK;
+        h &= ~pm::FLAG_STALE;
+        HIPCHK(hipMemcpyAsync(c->ws.flag, &h, sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        c->counts_ready = false;
+    }
     LAUNCH(pm::K_FILL, pm::launch_fill_i32(c->ws.cnt, K + 1, s));
     LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, c->ws.cnt, s));
     // koff <- exclusive scan of the counts; cnt <- the same, as cursors
     LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt, c->ws.koff, K + 1, c->ws.bsum, s, c->ws.cnt));
-    const uint8_t *tin = c->permuted ? c->ws.tags : nullptr;
     LAUNCH(pm::K_SORT_SCATTER,
            pm::launch_sort_scatter(x, p, tin, c->P, c->nseg, c->ws.seg_off, c->n, c->ws.cnt, c->ws.xs,
                                    p ? c->ws.ps : nullptr, c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
@@ -249,7 +276,9 @@ pm_status paint_all(pm_ctx *c, const float *x, hipStream_t s)
 // spectrum is written into F0 (row stride Nhp, not a power of two, so strided
 // passes do not camp on a few HBM channels) and the axis-0 pass works in
 // place on it.
-pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s)
+// With `delta` set, the source is instead the float32 density contrast [N]^3
+// written by the tile paint (src unused).
+pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s, const float *delta = nullptr)
 {
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
@@ -263,7 +292,11 @@ pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s)
         // transforms, the N/16-point pass on the gradient of the inverse
         // Laplacian; the spectrum stays digit-reversed along axis 0 in between
         const int64_t plane = (int64_t)n * nhp;
-        LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0(lg, src, F, (int)nhp, plane, scale, -1.0, c->ws.tw, c->ws.flag, s));
+        if (delta)
+            LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0_f32(lg, delta, F, (int)nhp, plane, c->ws.tw, s));
+        else
+            LAUNCH(pm::K_R2C_X0,
+                   pm::launch_r2c_x0(lg, src, F, (int)nhp, plane, scale, -1.0, c->ws.tw, c->ws.flag, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
         // F0 <- k0 T, F1 <- T; the inverse column passes apply the k2 and
         // k1 factors: component 2 from F1 into F2 first, then 1 in place
@@ -277,7 +310,10 @@ pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s)
         return PM_OK;
     }
     // axis 2: density contrast, real-to-complex rows
-    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, src, n, F, nhp, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
+    if (delta)
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, delta, n, F, nhp, n2, c->ws.tw, s));
+    else
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, src, n, F, nhp, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
     // axis 1
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
     // axis 0 forward, gradient of the inverse Laplacian, axis 0 inverses (in place on F0)
@@ -450,6 +486,7 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
         c->ws.koff = reinterpret_cast<int *>(b + L.koff);
         c->ws.cnt = reinterpret_cast<int *>(b + L.cnt);
         c->ws.bsum = reinterpret_cast<int *>(b + L.bsum);
+        c->ws.cnt_next = reinterpret_cast<int *>(b + L.cnt_next);
     }
     if (cfg->flags & PM_FLAG_LEARNED) {
         c->ws.net_phif = reinterpret_cast<float *>(b + L.net_phif);
@@ -515,7 +552,7 @@ void pm_free(pm_ctx *ctx)
 static const char *kKernelNames[pm::K_COUNT] = {
     "fill",      "paint",        "r2c_rows",     "cols_fwd",   "axis0",      "cols_inv",   "c2r_rows",
     "readout_kick_drift", "readout", "power_bin", "power_reduce", "ic_particles", "copy", "sort_count",
-    "sort_scan", "sort_scatter", "x0_green", "r2c_x0", "c2r_x0", "adjoint", "net"};
+    "sort_scan", "sort_scatter", "x0_green", "r2c_x0", "c2r_x0", "adjoint", "net", "sort_verify"};
 
 const char *pm_kernel_name(int32_t kind)
 {
@@ -610,6 +647,7 @@ pm_status pm_kdk_factors(const pm_ctx *c, double a_force, double a_kick0, double
 static pm_status ic_impl(pm_ctx *c, const float *white, const float *u, float *x, float *p, void *stream)
 {
     c->permuted = false;
+    c->counts_ready = false;
     hipStream_t s = S(stream);
     const pm_config &g = c->cfg;
     const int nic = g.n_cdm, lg = ilog2i(nic), n = c->n;
@@ -772,17 +810,24 @@ pm_status pm_step(pm_ctx *c, float *x, float *p, double a_force, double a_kick0,
     if (sorting_on(c)) {
         // sort by tile, paint tile by tile, solve, read out tile by tile into
         // the caller's arrays, which then hold the particles in sorted order
+        // the tile paint stores each cell's exact int64 sum as its float32
+        // density contrast, the value the transform would form from it
         st = tile_sort(c, x, p, s);
         if (st != PM_OK) return st;
-        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, 0,
-                                                   c->nseg, c->n, c->ws.q, s));
-        st = solve(c, c->ws.q, s);
+        float *delta = reinterpret_cast<float *>(c->ws.q);
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles_delta(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, c->n,
+                                                         ldexp(1.0, -c->cfg.shift), -1.0, delta, c->ws.flag, s));
+        st = solve(c, nullptr, s, delta);
         if (st != PM_OK) return st;
+        int *cnt_next = (c->cfg.flags & PM_FLAG_NO_GUARDS) ? nullptr : c->ws.cnt_next;
+        if (cnt_next) LAUNCH(pm::K_FILL, pm::launch_fill_i32(cnt_next, c->nkeys + 1, s));
         LAUNCH(pm::K_READOUT_KD,
                pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * n * nhp, c->n,
                                            (float)kick, (float)drift, x, p, c->ws.tags, c->ws.ids_tmp, c->ids,
-                                           c->ws.flag, s));
+                                           c->ws.flag, cnt_next, s));
         c->permuted = true;
+        c->counts_ready = cnt_next != nullptr;
+        c->counts_x = x;
         return check_guards(c, s);
     }
     st = paint_all(c, x, s);
@@ -816,6 +861,7 @@ pm_status pm_reset_order(pm_ctx *c)
 {
     if (!c) return fail(PM_ERR_ARG, "ctx is NULL");
     c->permuted = false;
+    c->counts_ready = false;
     return PM_OK;
 }
 
@@ -1040,8 +1086,9 @@ pm_status pm_learned_step(pm_ctx *c, const float *th, float *x, float *p, double
         LAUNCH(pm::K_READOUT_KD,
                pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * n * nhp, c->n,
                                            (float)kick, (float)drift, x, p, c->ws.tags, c->ws.ids_tmp, c->ids,
-                                           c->ws.flag, s));
+                                           c->ws.flag, nullptr, s));
         c->permuted = true;
+        c->counts_ready = false;
         return check_guards(c, s);
     }
     st = paint_all(c, x, s);

@@ -106,12 +106,20 @@ __global__ __launch_bounds__(256) void k_paint_tagged(const float *__restrict__ 
 // tile's particles (one contiguous range) and the 19 neighbour ranges are
 // walked as one flat index space, four particles per thread per round, so
 // that the global loads of a thread are independent of each other.
+// Output modes.  PAINT_STORE: the int64 sums overwrite the tile.  PAINT_DELTA: the exact int64 sums are not stored; each cell is written as
+// the float32 density contrast (float)(Q scale + offset), the value the
+// real-to-complex pass would form from the int64 cell, and cells below
+// GUARD_MIN_Q raise the overflow flag (half the bytes of an int64 mesh,
+// written once and read once by the transform).
+enum { PAINT_STORE = 0, PAINT_DELTA = 2 };
 constexpr int PAINT_T = 256, NRANGE = 20, NPT = 4;   // NPT particles per thread per round
 
+template <int MODE>
 __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restrict__ xs,
                                                          const int *__restrict__ koff,
                                                          const int64_t *__restrict__ quanta, int nseg, int lo,
-                                                         int hi, int n, unsigned long long *mesh)
+                                                         int hi, int n, void *out, double scale, double offset,
+                                                         int *flag)
 {
     __shared__ unsigned long long acc[TILE * TILE * TILE];
     __shared__ long long qtab[MAX_SEG];
@@ -203,9 +211,28 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PAINT_T) {
-        const int l0 = i / (TILE * TILE), l1 = (i / TILE) % TILE, l2 = i % TILE;
-        mesh[((int64_t)(ox + l0) * n + (oy + l1)) * n + (oz + l2)] = acc[i];
+    if constexpr (MODE == PAINT_DELTA) {
+        // four cells of a row per thread: one 16-byte store
+        float *dm = static_cast<float *>(out);
+        bool bad = false;
+        for (int i = threadIdx.x; i < TILE * TILE * TILE / 4; i += PAINT_T) {
+            const int l0 = i / (TILE * TILE / 4), l1 = (i / (TILE / 4)) % TILE, l2 = 4 * (i % (TILE / 4));
+            const long long *a = reinterpret_cast<const long long *>(acc) + (l0 * TILE + l1) * TILE + l2;
+            float4 v;
+            v.x = (float)((double)a[0] * scale + offset);
+            v.y = (float)((double)a[1] * scale + offset);
+            v.z = (float)((double)a[2] * scale + offset);
+            v.w = (float)((double)a[3] * scale + offset);
+            bad |= (a[0] < GUARD_MIN_Q) | (a[1] < GUARD_MIN_Q) | (a[2] < GUARD_MIN_Q) | (a[3] < GUARD_MIN_Q);
+            *reinterpret_cast<float4 *>(dm + ((int64_t)(ox + l0) * n + (oy + l1)) * n + (oz + l2)) = v;
+        }
+        if (bad) atomicOr(flag, FLAG_OVERFLOW);
+    } else {
+        unsigned long long *mesh = static_cast<unsigned long long *>(out);
+        for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PAINT_T) {
+            const int l0 = i / (TILE * TILE), l1 = (i / TILE) % TILE, l2 = i % TILE;
+            mesh[((int64_t)(ox + l0) * n + (oy + l1)) * n + (oz + l2)] = acc[i];
+        }
     }
 }
 
@@ -238,8 +265,18 @@ hipError_t launch_paint_tiles(const float4 *xs, const int *koff, const int64_t *
 {
     const int nt = n / TILE;
     if (nt < 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_paint_tiles, dim3((unsigned)(nt * nt * nt)), dim3(PAINT_T), 0, s, xs, koff, quanta, nseg,
-                       seg_lo, seg_hi, n, reinterpret_cast<unsigned long long *>(mesh));
+    hipLaunchKernelGGL(k_paint_tiles<PAINT_STORE>, dim3((unsigned)(nt * nt * nt)), dim3(PAINT_T), 0, s, xs, koff, quanta,
+                       nseg, seg_lo, seg_hi, n, static_cast<void *>(mesh), 0.0, 0.0, static_cast<int *>(nullptr));
+    return hipGetLastError();
+}
+
+hipError_t launch_paint_tiles_delta(const float4 *xs, const int *koff, const int64_t *quanta, int nseg, int n,
+                                    double scale, double offset, float *delta, int *flag, hipStream_t s)
+{
+    const int nt = n / TILE;
+    if (nt < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_paint_tiles<PAINT_DELTA>, dim3((unsigned)(nt * nt * nt)), dim3(PAINT_T), 0, s, xs, koff, quanta,
+                       nseg, 0, nseg, n, static_cast<void *>(delta), scale, offset, flag);
     return hipGetLastError();
 }
 

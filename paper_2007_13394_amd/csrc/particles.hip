@@ -120,12 +120,13 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__
                                                                 int64_t cs, int n, float kick, float drift,
                                                                 float *x, float *p, uint8_t *tags,
                                                                 const uint32_t *__restrict__ ids_tmp,
-                                                                uint32_t *ids, int *flag)
+                                                                uint32_t *ids, int *flag, int *cnt_next)
 {
     // LDS: the (TILE + 1)^3 cells of the tile and its +1 halo, the three
     // force components of a cell interleaved in one float4
-    constexpr int H = TILE + 1, ROWS = H * H;
+    constexpr int H = TILE + 1, ROWS = H * H, NB = 27 * 8;
     __shared__ float4 fl[ROWS * H];
+    __shared__ int hist[NB];   // next-step key counts of this tile and its neighbours (cnt_next)
     const int nt = n / TILE, mask = n - 1;
     // workgroups walk the tiles in row-major order (consecutive tiles share
     // rows of the force mesh); particle ranges are looked up by Morton index
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__
         const float *src = F + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + ((o2 + TILE) & mask);
         fl[rr * H + TILE] = make_float4(src[0], src[cs], src[2 * cs], 0.f);
     }
+    if (threadIdx.x < NB) hist[threadIdx.x] = 0;
     __syncthreads();
     const float nf = (float)n;
     bool bad = false;
@@ -192,6 +194,21 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__
         const float x1 = wrapf(u1 + drift * p1, nf);
         const float x2 = wrapf(u2 + drift * p2, nf);
         bad |= !(isfinite(p0) && isfinite(p1) && isfinite(p2) && isfinite(x0) && isfinite(x1) && isfinite(x2));
+        if (cnt_next) {
+            // the next step's sort counts: keys in this tile or its 26
+            // neighbours go to the LDS histogram, the rest (mostly neutrinos
+            // that streamed far) straight to the global counts
+            const int c0 = (int)floorf(x0) & mask, c1 = (int)floorf(x1) & mask, c2 = (int)floorf(x2) & mask;
+            const int s0 = c0 / TILE, s1 = c1 / TILE, s2 = c2 / TILE;
+            const int f = ((c0 % TILE) == TILE - 1 ? 1 : 0) | ((c1 % TILE) == TILE - 1 ? 2 : 0) |
+                          ((c2 % TILE) == TILE - 1 ? 4 : 0);
+            const int e0 = (s0 - t0 + 1 + nt) & (nt - 1), e1 = (s1 - t1 + 1 + nt) & (nt - 1),
+                      e2 = (s2 - t2 + 1 + nt) & (nt - 1);
+            if (e0 < 3 && e1 < 3 && e2 < 3)
+                atomicAdd(&hist[((e0 * 3 + e1) * 3 + e2) * 8 + f], 1);
+            else
+                atomicAdd(cnt_next + tile_index(s0, s1, s2) * 8 + f, 1);
+        }
         const int inext = i + READOUT_T;
         if (inext < end) {
             ur = xs[inext];
@@ -208,6 +225,15 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__
         i = inext;
     }
     if (bad) atomicOr(flag, FLAG_NAN);
+    if (cnt_next) {
+        __syncthreads();
+        if (threadIdx.x < NB && hist[threadIdx.x] > 0) {
+            const int b = threadIdx.x, e = b / 8, f = b % 8;
+            const int s0 = (t0 + e / 9 - 1 + nt) & (nt - 1), s1 = (t1 + (e / 3) % 3 - 1 + nt) & (nt - 1),
+                      s2 = (t2 + e % 3 - 1 + nt) & (nt - 1);
+            atomicAdd(cnt_next + tile_index(s0, s1, s2) * 8 + f, hist[b]);
+        }
+    }
 }
 
 __global__ void k_fill_i32(int *p, int64_t count)
@@ -439,13 +465,13 @@ hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2
 hipError_t launch_readout_kd_tiles(const float4 *xs, const float4 *ps, int64_t P, const int *koff, const float2 *f,
                                    int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
                                    float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag,
-                                   hipStream_t s)
+                                   int *cnt_next, hipStream_t s)
 {
     const int nt = n / TILE;
     if (nt < 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_readout_kd_tiles, dim3((unsigned)(nt * nt * nt)), dim3(READOUT_T), 0, s, xs, ps, P, koff,
                        reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, x, p, tags,
-                       ids_tmp, ids, flag);
+                       ids_tmp, ids, flag, cnt_next);
     return hipGetLastError();
 }
 

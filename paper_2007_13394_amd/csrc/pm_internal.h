@@ -62,8 +62,41 @@ __device__ __forceinline__ unsigned morton_compact(unsigned v)
     return v;
 }
 
-// Device-side guard bits (workspace flag word).
-enum { FLAG_OVERFLOW = 1, FLAG_NAN = 2 };
+// Sort key of a position: 8 * (Morton index of the TILE^3-cell block holding
+// floor(u)) + face flags, bit d set when floor(u_d) is the last cell of the
+// block along axis d (its +1 cloud-in-cell corner lies in the next block).
+__device__ __forceinline__ int tile_key(float u0, float u1, float u2, int n)
+{
+    const int mask = n - 1;
+    const int c0 = (int)floorf(u0) & mask, c1 = (int)floorf(u1) & mask, c2 = (int)floorf(u2) & mask;
+    const int t = tile_index(c0 / TILE, c1 / TILE, c2 / TILE);
+    const int f = ((c0 % TILE) == TILE - 1 ? 1 : 0) | ((c1 % TILE) == TILE - 1 ? 2 : 0) |
+                  ((c2 % TILE) == TILE - 1 ? 4 : 0);
+    return t * 8 + f;
+}
+
+// Lanes of the wavefront that share this lane's key: the mask and its
+// lowest lane (ballot loop, no memory traffic).
+__device__ __forceinline__ void key_group(bool live, int k, uint64_t &group, int &leader)
+{
+    uint64_t todo = __ballot(live);
+    group = 0;
+    leader = 0;
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        const int lk = __shfl(k, l);
+        const uint64_t same = __ballot(live && k == lk);
+        if (live && k == lk) {
+            group = same;
+            leader = l;
+        }
+        todo &= ~same;
+    }
+}
+
+// Device-side guard bits (workspace flag word).  FLAG_STALE: tile counts
+// taken over from the previous step did not match the positions.
+enum { FLAG_OVERFLOW = 1, FLAG_NAN = 2, FLAG_STALE = 4 };
 // A painted cell below this many quanta has wrapped past 2^63.  Cells are
 // sums of positive particle quanta, but a particle's remainder corner (its
 // quantum minus seven rounded corners) can be a few units negative when its
@@ -88,6 +121,7 @@ struct Workspace {
     uint8_t *tags = nullptr;     // segment tag per particle in the caller's current order [P]
     uint32_t *ids_tmp = nullptr; // tile-sorted ids [P]
     int *cnt = nullptr;          // counts per key (K + 1), then the scatter's cursors (aliases the F region)
+    int *cnt_next = nullptr;     // counts per key of the positions the last tile readout wrote (K + 1)
     int *koff = nullptr;         // exclusive offsets per key (K + 1)
     int *bsum = nullptr;         // scan block sums
     // learned force correction (PM_FLAG_LEARNED)
@@ -117,7 +151,7 @@ constexpr int NW0 = 0, NB0 = NW0 + NET_H * 2, NW1 = NB0 + NET_H, NB1 = NW1 + NET
 enum KernelKind {
     K_FILL = 0, K_PAINT, K_R2C, K_COLS_FWD, K_AXIS0, K_COLS_INV, K_C2R, K_READOUT_KD, K_READOUT,
     K_POWER_BIN, K_POWER_REDUCE, K_IC_PARTICLES, K_COPY, K_SORT_COUNT, K_SORT_SCAN, K_SORT_SCATTER,
-    K_X0_GREEN, K_R2C_X0, K_C2R_X0, K_ADJOINT, K_NET, K_COUNT
+    K_X0_GREEN, K_R2C_X0, K_C2R_X0, K_ADJOINT, K_NET, K_SORT_VERIFY, K_COUNT
 };
 
 struct TraceRec {
@@ -151,6 +185,10 @@ struct Ctx {
     int64_t nkeys = 0;            // 8 x tiles when tile sorting is available, else 0
     std::vector<int64_t> segtab_host;
     uint32_t *ids = nullptr;      // caller's id array, permuted along with the particles
+    // tile counts of the positions written by the last tile readout (into the
+    // array counts_x); the next sort takes them over and verifies them
+    bool counts_ready = false;
+    const float *counts_x = nullptr;
     // launch trace
     bool tracing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -205,6 +243,9 @@ hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *ou
 // pass-A output; inverse: pass-A inverse -> real rows, in place allowed).
 hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int64_t plane, double scale,
                          double offset, const float2 *tw, int *flag, hipStream_t s);
+// The same pass on a float32 density contrast mesh (already offset and scaled).
+hipError_t launch_r2c_x0_f32(int logn, const float *src, float2 *dst, int nhp, int64_t plane, const float2 *tw,
+                             hipStream_t s);
 hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int nhp, int64_t plane,
                          const float2 *tw, hipStream_t s);
 
@@ -258,6 +299,11 @@ hipError_t launch_paint_tagged(const float *x, int64_t P, const uint8_t *tags, i
                                const int64_t *quanta, int n, int64_t *mesh, hipStream_t s);
 hipError_t launch_paint_tiles(const float4 *xs, const int *koff, const int64_t *quanta, int nseg, int seg_lo,
                               int seg_hi, int n, int64_t *mesh, hipStream_t s);
+// Tile paint of every segment, stored as the float32 density contrast
+// (float)(Q scale + offset) of each cell's exact int64 sum (overflow flag as
+// the transforms raise it).
+hipError_t launch_paint_tiles_delta(const float4 *xs, const int *koff, const int64_t *quanta, int nseg, int n,
+                                    double scale, double offset, float *delta, int *flag, hipStream_t s);
 
 // ---- launchers (sort.hip)
 // Counting sort by tile key: counts per key (cnt zeroed by the caller), an
@@ -268,6 +314,8 @@ hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipS
 hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
                                const int64_t *seg_off, int n, int *cursor, float4 *xs, float4 *ps,
                                const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s);
+// FLAG_STALE unless cursor[k] == koff[k + 1] for every key k < K.
+hipError_t launch_sort_verify(const int *cursor, const int *koff, int64_t K, int *flag, hipStream_t s);
 
 // ---- launchers (particles.hip)
 hipError_t launch_fill_i64(int64_t *p, int64_t count, hipStream_t s);
@@ -276,9 +324,10 @@ hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs
 hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f,
                                      int64_t comp_stride, int n, float kick, float drift, int *flag,
                                      hipStream_t s);
+// cnt_next (optional): counts per sort key of the positions written, added to.
 hipError_t launch_readout_kd_tiles(const float4 *xs, const float4 *ps, int64_t P, const int *koff, const float2 *f,
                                    int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
-                                   float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag,
+                                   float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag, int *cnt_next,
                                    hipStream_t s);
 hipError_t launch_fill_i32(int *p, int64_t count, hipStream_t s);
 hipError_t launch_add_i64(const int64_t *src, int64_t *dst, int64_t count, hipStream_t s);

@@ -26,39 +26,12 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536LL * 16)
     return (unsigned)b;
 }
 
-__device__ __forceinline__ int tile_key(float u0, float u1, float u2, int n)
-{
-    const int mask = n - 1;
-    const int c0 = (int)floorf(u0) & mask, c1 = (int)floorf(u1) & mask, c2 = (int)floorf(u2) & mask;
-    const int t = tile_index(c0 / TILE, c1 / TILE, c2 / TILE);
-    const int f = ((c0 % TILE) == TILE - 1 ? 1 : 0) | ((c1 % TILE) == TILE - 1 ? 2 : 0) |
-                  ((c2 % TILE) == TILE - 1 ? 4 : 0);
-    return t * 8 + f;
-}
 
 // Each workgroup takes SORT_CH consecutive particles, workgroups numbered so
 // that each XCD owns a contiguous run of chunks (the scatter of a nearly
 // sorted state then writes whole cache lines from one L2).
 constexpr int SORT_T = 256, SORT_CH = SORT_T * 8;
 
-// Lanes of the wavefront that share this lane's key: the mask and its
-// lowest lane (ballot loop, no memory traffic).
-__device__ __forceinline__ void key_group(bool live, int k, uint64_t &group, int &leader)
-{
-    uint64_t todo = __ballot(live);
-    group = 0;
-    leader = 0;
-    while (todo) {
-        const int l = __ffsll((unsigned long long)todo) - 1;
-        const int lk = __shfl(k, l);
-        const uint64_t same = __ballot(live && k == lk);
-        if (live && k == lk) {
-            group = same;
-            leader = l;
-        }
-        todo &= ~same;
-    }
-}
 
 __global__ __launch_bounds__(SORT_T) void k_sort_count(const float *__restrict__ x, int64_t P, int n, int *cnt)
 {
@@ -223,8 +196,8 @@ __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const floa
         int b = 0;
         if (live && lane == leader) b = atomicAdd(cursor + k, __popcll(group));
         b = __shfl(b, leader);
-        if (live) {
-            const int64_t d = (int64_t)b + __popcll(group & ((1ull << lane) - 1));
+        const int64_t d = (int64_t)b + __popcll(group & ((1ull << lane) - 1));
+        if (live && d < P) {   // d >= P only with counts that do not match x (k_sort_verify reports it)
             xs[d] = make_float4(u0, u1, u2, __int_as_float(t));
             if constexpr (HP) ps[d] = make_float4(b0, b1, b2, 0.f);
             if constexpr (HI) ids_out[d] = id;
@@ -263,7 +236,25 @@ __global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict
 #undef SCATTER
 }
 
+// After a scatter from counts computed elsewhere (the previous readout):
+// every key's cursor must have reached the next key's offset, else the
+// counts did not describe x and FLAG_STALE is raised.
+__global__ __launch_bounds__(256) void k_sort_verify(const int *__restrict__ cursor, const int *__restrict__ koff,
+                                                     int64_t K, int *flag)
+{
+    bool bad = false;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x)
+        bad |= cursor[k] != koff[k + 1];
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, FLAG_STALE);
+}
+
 }  // namespace
+
+hipError_t launch_sort_verify(const int *cursor, const int *koff, int64_t K, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sort_verify, dim3(grid_for(K, 256, 65536)), dim3(256), 0, s, cursor, koff, K, flag);
+    return hipGetLastError();
+}
 
 hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, hipStream_t s)
 {

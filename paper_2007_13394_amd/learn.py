@@ -290,55 +290,95 @@ def judge(coarse_name, fine_name, train_seeds, test_seeds, snap_every=5, iters=4
     calib_seeds = list(train_seeds) if calib_seeds is None else list(calib_seeds)
     assert not set(calib_seeds) & set(test_seeds) and not set(train_seeds) & set(test_seeds)
     fine_x = [simulate(ctx_f, cf, s, device, scale=ratio)[0] for s in calib_seeds]
+    del ctx_f
     theta_cal = theta.clone()   # the force-matched network; the calibration moves the filter only
     calib_hist = calibrate(cc, calib_seeds, fine_x, theta_cal, rounds=calib_rounds, device=device, log=log)
     t_cal = time.perf_counter() - t0
     del fine_x
     torch.cuda.empty_cache()
-    # held-out runs: fine (truth), calibrated, plain coarse, force-matched
+    held = heldout(cc, cf, test_seeds, theta_cal, theta, device)
+    out = {
+        "coarse": coarse_name, "fine": fine_name, "particles": held["particles"], "train_seeds": list(train_seeds),
+        "test_seeds": test_seeds, "iters": iters, "pairs_s": round(t_pairs, 2), "train_s": round(t_train, 2),
+        "force_loss": {"plain_train": base_train, "learned_train": tr_train, "plain_test": base_test,
+                       "learned_test": tr_test},
+        "calibration": {"rounds": calib_rounds, "seeds": calib_seeds, "train_seed_err": calib_hist,
+                        "seconds": round(t_cal, 2)},
+        "loss_history": [float(h) for h in hist[::10]],
+    }
+    out.update(held)
+    out["theta"] = theta_cal
+    return out
+
+
+def heldout(cc, cf, test_seeds, theta_cal, theta_fm=None, device="cuda"):
+    """Held-out comparison: from each seed, a plain fine-mesh run (the truth),
+    the learned coarse run (theta_cal), a plain coarse run and, if given, the
+    force-matched model (theta_fm), all painted on the coarse mesh at the end.
+    Reports each seed's worst |P / P_fine - 1| and smallest cross-correlation
+    over k < k_Nyq / 2, the same for the spectra averaged over the seeds, the
+    per-bin ratios, and particle-steps/s of the timed step loops."""
+    ratio = cf["n_mesh"] // cc["n_mesh"]
+    cf = dict(cf, coarse_mesh=cc["n_mesh"])
+    ctx_f = pm.Ctx(pm.make_config(cf))
     ctx_l, ctx_c, ana = make_ctx(cc, learned=True, sort=True), make_ctx(cc, sort=True), make_ctx(cc)
     nb = cc["n_mesh"] // 2
     kn = np.pi * cc["n_mesh"] / cc["box"]
-    names = ("fine", "learned", "plain_coarse", "learned_force_matched")
-    auto_sum, cross_sum, per_seed = None, None, []
+    names = ("fine", "learned", "plain_coarse") + (("learned_force_matched",) if theta_fm is not None else ())
+    auto_sum, cross_sum, per_seed, ratios = None, None, [], {}
     t_f = t_l = t_c = 0.0
     for s in test_seeds:
         x_f, dt_f, ncalls = simulate(ctx_f, cf, s, device, scale=ratio)
         x_l, dt_l, _ = simulate(ctx_l, cc, s, device, theta=theta_cal)
         x_c, dt_c, _ = simulate(ctx_c, cc, s, device)
-        x_m, _, _ = simulate(ctx_l, cc, s, device, theta=theta)
+        xs = [x_f, x_l, x_c]
+        if theta_fm is not None:
+            xs.append(simulate(ctx_l, cc, s, device, theta=theta_fm)[0])
         t_f, t_l, t_c = t_f + dt_f, t_l + dt_l, t_c + dt_c
-        k, nm, autos, cross = spectra(ana, [x_f, x_l, x_c, x_m], nb)
+        k, nm, autos, cross = spectra(ana, xs, nb)
         sel = (nm > 0) & (k > 0) & (k < kn / 2)
-        per_seed.append({names[j]: float(np.max(np.abs(autos[j][sel] / autos[0][sel] - 1))) for j in (1, 2, 3)})
+        rec = {"seed": s}
+        for j in range(1, len(names)):
+            rec[names[j]] = float(np.max(np.abs(autos[j][sel] / autos[0][sel] - 1)))
+            rec[names[j] + "_r_min"] = float(np.min(cross[j][sel] / np.sqrt(autos[0][sel] * autos[j][sel])))
+        per_seed.append(rec)
+        ratios[str(s)] = {names[j]: np.round(autos[j][sel] / autos[0][sel], 5).tolist() for j in (1, 2)}
         auto_sum = np.array(autos) if auto_sum is None else auto_sum + np.array(autos)
         cross_sum = np.array(cross) if cross_sum is None else cross_sum + np.array(cross)
         P = x_f.shape[1]
-        del x_f, x_l, x_c, x_m
+        del x_f, x_l, x_c, xs
     del ctx_f, ctx_l, ctx_c
     torch.cuda.empty_cache()
-    err = {names[j]: float(np.max(np.abs(auto_sum[j][sel] / auto_sum[0][sel] - 1))) for j in (1, 2, 3)}
+    err = {names[j]: float(np.max(np.abs(auto_sum[j][sel] / auto_sum[0][sel] - 1))) for j in range(1, len(names))}
     rmin = {names[j]: float(np.min(cross_sum[j][sel] / np.sqrt(auto_sum[0][sel] * auto_sum[j][sel])))
-            for j in (1, 2, 3)}
+            for j in range(1, len(names))}
     nt = len(test_seeds)
-    out = {
-        "coarse": coarse_name, "fine": fine_name, "particles": P, "train_seeds": list(train_seeds),
-        "test_seeds": test_seeds, "iters": iters, "pairs_s": round(t_pairs, 2), "train_s": round(t_train, 2),
-        "force_loss": {"plain_train": base_train, "learned_train": tr_train, "plain_test": base_test,
-                       "learned_test": tr_test},
+    return {
+        "particles": P,
         "pk_max_rel_err": err,
         "pk_max_rel_err_per_seed": per_seed,
         "k_range_hMpc": [float(k[sel].min()), float(k[sel].max())],
         "r_min": rmin,
-        "calibration": {"rounds": calib_rounds, "seeds": calib_seeds, "train_seed_err": calib_hist,
-                        "seconds": round(t_cal, 2)},
         "particle_steps_per_s": {"learned_coarse": P * ncalls * nt / t_l, "plain_coarse": P * ncalls * nt / t_c,
                                  "plain_fine": P * ncalls * nt / t_f},
         "speedup_vs_fine": t_f / t_l,
-        "pk": {"k": k[sel].tolist(), **{names[j]: (auto_sum[j][sel] / nt).tolist() for j in range(4)}},
-        "loss_history": [float(h) for h in hist[::10]],
+        "k": k[sel].tolist(),
+        "ratio_per_seed": ratios,
+        "pk": {names[j]: (auto_sum[j][sel] / nt).tolist() for j in range(len(names))},
     }
-    return out
+
+
+def save_params(theta, path):
+    """The flat FP32 parameter array as a .npy file."""
+    np.save(path, theta.detach().float().cpu().numpy())
+
+
+def load_params(path, device="cuda"):
+    """Parameters written by save_params (plain array; nothing is unpickled)."""
+    th = np.load(path, allow_pickle=False)
+    if th.dtype != np.float32 or th.shape != (NET_NPARAM,):
+        raise ValueError(f"{path}: expected float32 [{NET_NPARAM}], got {th.dtype} {th.shape}")
+    return torch.from_numpy(th).to(device)
 
 
 def time_steps(cfg_name, steps, device="cuda", seed=200, which=("learned", "plain")):
@@ -391,6 +431,7 @@ if __name__ == "__main__":
     ap.add_argument("--snap-every", type=int, default=5)
     ap.add_argument("--iters", type=int, default=400)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--save", default="", help="write the calibrated parameters to this .npy file")
     a = ap.parse_args()
     if a.time_steps:
         print(json.dumps(dict(time_steps(a.coarse, a.time_steps), workload=a.coarse)), flush=True)
@@ -399,4 +440,7 @@ if __name__ == "__main__":
                 [int(s) for s in a.test_seeds.split(",")], a.snap_every, a.iters,
                 a.lr, log=lambda *m: print(*m, file=sys.stderr, flush=True),
                 calib_seeds=[int(s) for s in a.calib_seeds.split(",")])
+    theta = res.pop("theta")
+    if a.save:
+        save_params(theta, a.save)
     print(json.dumps(res), flush=True)

@@ -31,7 +31,7 @@ def test_training_gain_on_held_out_seed(dev):
     say("r_min plain / learned", res["r_min"]["plain_coarse"], res["r_min"]["learned"])
     say("particle-steps/s", res["particle_steps_per_s"])
     pk_ = res["pk"]
-    for i, kk in enumerate(pk_["k"]):
+    for i, kk in enumerate(res["k"]):
         say("k %.3f learned/fine %.4f plain/fine %.4f" % (kk, pk_["learned"][i] / pk_["fine"][i],
                                                          pk_["plain_coarse"][i] / pk_["fine"][i]))
     assert np.isfinite(fl["learned_test"])

@@ -376,3 +376,28 @@ def test_device_guards_report_overflow_and_nan(dev):
     with pytest.raises(pm.PMError) as e:
         pm.pm_step(ctx2, torch.from_numpy(x2).to(dev), torch.from_numpy(p2).to(dev), *CALLS[1])
     assert e.value.status == pm.PM_ERR_NAN
+
+
+def test_sorted_step_after_caller_moves_particles(dev):
+    """A sorted step leaves the tile counts of the positions it wrote for the
+    next step's sort, which checks them after its scatter.  Here the caller
+    moves every particle between two steps (same array): the check must
+    reject the stale counts and the step must still match the oracle."""
+    pm = _pm()
+    cfg = I.config("C1")
+    n = cfg["n_mesh"]
+    ctx = pm.Ctx(pm.make_config(cfg))
+    x, p = I.synthetic_state(cfg, seed=71)
+    ids = torch.arange(ctx.P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(ctx, ids)
+    xd, pd = torch.from_numpy(x).to(dev), torch.from_numpy(p).to(dev)
+    pm.pm_step(ctx, xd, pd, *CALLS[0])
+    # move the particles in place: the counts the step left no longer match
+    xd.add_(torch.tensor([[7.25], [19.5], [3.0]], device=dev)).remainder_(n)
+    xd.masked_fill_(xd >= n, 0.0)
+    order = np.argsort(ids.cpu().numpy())
+    x1, p1 = np.ascontiguousarray(xd.cpu().numpy()[:, order]), np.ascontiguousarray(pd.cpu().numpy()[:, order])
+    pm.pm_step(ctx, xd, pd, *CALLS[1])
+    pm.pm_attach_ids(ctx, None)
+    order = np.argsort(ids.cpu().numpy())
+    _step_compare(cfg, xd.cpu().numpy()[:, order], pd.cpu().numpy()[:, order], x1, p1, CALLS[1])
