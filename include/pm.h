@@ -196,6 +196,24 @@ pm_status pm_paint_q(pm_ctx *ctx, const float *x, int64_t stride, int64_t first,
 pm_status pm_paint(pm_ctx *ctx, const float *x, int32_t seg_lo, int32_t seg_hi, int64_t *mesh_q,
                    void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pm_paint's
+ * tile-sorted path, the same integers added to mesh_q, with the sort's
+ * scratch (per-key counts and offsets, the scan's block sums, the sorted
+ * position records) in a fixed device array of the library instead of the
+ * context's workspace.  The array is about 50 MiB per device, held until the
+ * process ends; every call on a device uses that device's one array (the
+ * counts are cleared by a kernel at the start of each call), so calls that
+ * overlap on one device race and must be ordered by the caller (one stream,
+ * or events).  The call allocates nothing and issues no memset.
+ * Limits: N <= PM_STATIC_MAX_MESH and P <= PM_STATIC_MAX_PARTICLES, else
+ * PM_ERR_SIZE; a context that cannot tile-sort (N < 32) gives PM_ERR_STATE;
+ * PM_ERR_ARG for a bad segment range or NULL pointer. */
+#define PM_STATIC_MAX_MESH 512
+#define PM_STATIC_MAX_PARTICLES 3145728
+pm_status pm_paint_static(pm_ctx *ctx, const float *x, int32_t seg_lo, int32_t seg_hi, int64_t *mesh_q,
+                          void *stream);
+
 /* Forward 3D real-to-complex transform, unnormalised, X_k = sum_j x_j
  * exp(-2 pi i j.k / N).  real: device float32 [N]^3; out: device interleaved
  * complex64 [N][N][N/2 + 1].  Uses the workspace. */

@@ -4,6 +4,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <new>
 
 #include "pm_internal.h"
@@ -11,6 +12,43 @@
 struct pm_ctx : pm::Ctx {};
 
 namespace {
+
+// Fixed device scratch of pm_paint_static, for callers that cannot allocate:
+// the tile sort's counts / cursors and offsets for up to PM_STATIC_MAX_MESH^3
+// meshes (8 keys per 16^3 tile), the scan's block sums, and the sorted
+// position records of up to PM_STATIC_MAX_PARTICLES particles.  Each device
+// holds its own copy for the life of the process; host code uses only the
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t align256c(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr int64_t STATIC_KEYS = 8LL * (PM_STATIC_MAX_MESH / pm::TILE) * (PM_STATIC_MAX_MESH / pm::TILE) *
+                                (PM_STATIC_MAX_MESH / pm::TILE);
+constexpr size_t STATIC_CNT = 0, STATIC_KOFF = align256c(4 * (STATIC_KEYS + 1)),
+                 STATIC_BSUM = STATIC_KOFF + align256c(4 * (STATIC_KEYS + 1)),
+                 STATIC_XS = STATIC_BSUM + align256c(4 * ((STATIC_KEYS + 1 + 2047) / 2048 + 1)),
+                 STATIC_BYTES = STATIC_XS + 16 * (size_t)PM_STATIC_MAX_PARTICLES;
+static __device__ __align__(256) char scratch[STATIC_BYTES];
+
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[64] = {};
+
+// This device's address of `scratch`, looked up once per device (with that
+// device current).
+hipError_t static_scratch_for_current_device(char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 thread_local char g_err[512] = "no error";
 
@@ -538,6 +576,11 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
         delete c;
         return fail(PM_ERR_DEVICE, "uploading tables: %s", hipGetErrorString(e));
     }
+    e = static_scratch_for_current_device(&c->static_scratch);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(PM_ERR_DEVICE, "address of the static scratch array: %s", hipGetErrorString(e));
+    }
     *out = c;
     return PM_OK;
 }
@@ -740,6 +783,32 @@ pm_status pm_paint(pm_ctx *c, const float *x, int32_t seg_lo, int32_t seg_hi, in
         return PM_OK;
     }
     return paint_atomic(c, x, seg_lo, seg_hi, mesh_q, s);
+}
+
+pm_status pm_paint_static(pm_ctx *c, const float *x, int32_t seg_lo, int32_t seg_hi, int64_t *mesh_q, void *stream)
+{
+    if (!c || !x || !mesh_q) return fail(PM_ERR_ARG, "NULL argument to pm_paint_static");
+    if (seg_lo < 0 || seg_hi > c->nseg || seg_lo > seg_hi) return fail(PM_ERR_ARG, "bad segment range");
+    if (c->nkeys == 0) return fail(PM_ERR_STATE, "pm_paint_static needs a configuration that can tile-sort (N >= 32)");
+    if (c->n > PM_STATIC_MAX_MESH || c->P > PM_STATIC_MAX_PARTICLES)
+        return fail(PM_ERR_SIZE, "pm_paint_static takes meshes up to %d^3 and up to %d particles (got %d^3, %lld)",
+                    PM_STATIC_MAX_MESH, PM_STATIC_MAX_PARTICLES, c->n, (long long)c->P);
+    if (!c->static_scratch) return fail(PM_ERR_STATE, "no static scratch address for this context");
+    hipStream_t s = S(stream);
+    if (seg_lo == seg_hi) return PM_OK;
+    const int64_t K = c->nkeys;
+    int *cnt = reinterpret_cast<int *>(c->static_scratch + STATIC_CNT);
+    int *koff = reinterpret_cast<int *>(c->static_scratch + STATIC_KOFF);
+    int *bsum = reinterpret_cast<int *>(c->static_scratch + STATIC_BSUM);
+    float4 *xs = reinterpret_cast<float4 *>(c->static_scratch + STATIC_XS);
+    // the counts start at zero (a fill kernel, which a graph capture may hold)
+    LAUNCH(pm::K_FILL, pm::launch_fill_i32(cnt, K + 1, s));
+    LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, cnt, s));
+    LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(cnt, koff, K + 1, bsum, s, cnt));
+    LAUNCH(pm::K_SORT_SCATTER, pm::launch_sort_scatter(x, nullptr, c->permuted ? c->ws.tags : nullptr, c->P, c->nseg,
+                                                       c->ws.seg_off, c->n, cnt, xs, nullptr, nullptr, nullptr, s));
+    LAUNCH(pm::K_PAINT, pm::launch_paint_tiles_add(xs, koff, c->ws.quanta, c->nseg, seg_lo, seg_hi, c->n, mesh_q, s));
+    return PM_OK;
 }
 
 pm_status pm_fft_r2c(pm_ctx *c, const float *real, float *out, void *stream)

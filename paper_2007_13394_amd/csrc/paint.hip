@@ -106,12 +106,14 @@ __global__ __launch_bounds__(256) void k_paint_tagged(const float *__restrict__ 
 // tile's particles (one contiguous range) and the 19 neighbour ranges are
 // walked as one flat index space, four particles per thread per round, so
 // that the global loads of a thread are independent of each other.
-// Output modes.  PAINT_STORE: the int64 sums overwrite the tile.  PAINT_DELTA: the exact int64 sums are not stored; each cell is written as
+// Output modes.  PAINT_STORE: the int64 sums overwrite the tile.  PAINT_ADD:
+// they are added to the tile (tiles are disjoint, so plain loads and stores).
+// PAINT_DELTA: the exact int64 sums are not stored; each cell is written as
 // the float32 density contrast (float)(Q scale + offset), the value the
 // real-to-complex pass would form from the int64 cell, and cells below
 // GUARD_MIN_Q raise the overflow flag (half the bytes of an int64 mesh,
 // written once and read once by the transform).
-enum { PAINT_STORE = 0, PAINT_DELTA = 2 };
+enum { PAINT_STORE = 0, PAINT_ADD = 1, PAINT_DELTA = 2 };
 constexpr int PAINT_T = 256, NRANGE = 20, NPT = 4;   // NPT particles per thread per round
 
 template <int MODE>
@@ -231,7 +233,11 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
         unsigned long long *mesh = static_cast<unsigned long long *>(out);
         for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PAINT_T) {
             const int l0 = i / (TILE * TILE), l1 = (i / TILE) % TILE, l2 = i % TILE;
-            mesh[((int64_t)(ox + l0) * n + (oy + l1)) * n + (oz + l2)] = acc[i];
+            unsigned long long *cell = mesh + ((int64_t)(ox + l0) * n + (oy + l1)) * n + (oz + l2);
+            if constexpr (MODE == PAINT_ADD)
+                *cell += acc[i];
+            else
+                *cell = acc[i];
         }
     }
 }
@@ -266,6 +272,16 @@ hipError_t launch_paint_tiles(const float4 *xs, const int *koff, const int64_t *
     const int nt = n / TILE;
     if (nt < 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_paint_tiles<PAINT_STORE>, dim3((unsigned)(nt * nt * nt)), dim3(PAINT_T), 0, s, xs, koff, quanta,
+                       nseg, seg_lo, seg_hi, n, static_cast<void *>(mesh), 0.0, 0.0, static_cast<int *>(nullptr));
+    return hipGetLastError();
+}
+
+hipError_t launch_paint_tiles_add(const float4 *xs, const int *koff, const int64_t *quanta, int nseg, int seg_lo,
+                                  int seg_hi, int n, int64_t *mesh, hipStream_t s)
+{
+    const int nt = n / TILE;
+    if (nt < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_paint_tiles<PAINT_ADD>, dim3((unsigned)(nt * nt * nt)), dim3(PAINT_T), 0, s, xs, koff, quanta,
                        nseg, seg_lo, seg_hi, n, static_cast<void *>(mesh), 0.0, 0.0, static_cast<int *>(nullptr));
     return hipGetLastError();
 }

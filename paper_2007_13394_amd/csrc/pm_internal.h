@@ -189,6 +189,7 @@ struct Ctx {
     // array counts_x); the next sort takes them over and verifies them
     bool counts_ready = false;
     const float *counts_x = nullptr;
+    char *static_scratch = nullptr;   // this device's fixed scratch array (pm_paint_static)
     // launch trace
     bool tracing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -299,6 +300,9 @@ hipError_t launch_paint_tagged(const float *x, int64_t P, const uint8_t *tags, i
                                const int64_t *quanta, int n, int64_t *mesh, hipStream_t s);
 hipError_t launch_paint_tiles(const float4 *xs, const int *koff, const int64_t *quanta, int nseg, int seg_lo,
                               int seg_hi, int n, int64_t *mesh, hipStream_t s);
+// The same, added to mesh (int64 [N]^3) instead of overwriting its tiles.
+hipError_t launch_paint_tiles_add(const float4 *xs, const int *koff, const int64_t *quanta, int nseg, int seg_lo,
+                                  int seg_hi, int n, int64_t *mesh, hipStream_t s);
 // Tile paint of every segment, stored as the float32 density contrast
 // (float)(Q scale + offset) of each cell's exact int64 sum (overflow flag as
 // the transforms raise it).

@@ -75,6 +75,7 @@ _sig("pm_ic", [_vp, _vp, _vp, _vp, _vp])
 _sig("pm_ic_pseudo", [_vp, _vp, _vp, _vp, _vp, _vp])
 _sig("pm_paint_q", [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp])
 _sig("pm_paint", [_vp, _vp, _i32, _i32, _vp, _vp])
+_sig("pm_paint_static", [_vp, _vp, _i32, _i32, _vp, _vp])
 _sig("pm_fft_r2c", [_vp, _vp, _vp, _vp])
 _sig("pm_fft_c2r", [_vp, _vp, _vp, _vp])
 _sig("pm_force_mesh", [_vp, _vp, _vp, _vp])
@@ -108,7 +109,7 @@ EXPORTS = ["pm_sizes", "pm_init", "pm_free", "pm_last_error", "pm_segments", "pm
            "pm_force", "pm_step", "pm_power", "pm_trace_begin", "pm_trace_end", "pm_kernel_name", "pm_attach_ids",
            "pm_segment_tags", "pm_reset_order", "pm_density", "pm_density_vjp", "pm_force_vjp", "pm_step_vjp",
            "pm_ic_vjp", "pm_net_nparam", "pm_learned_force", "pm_learned_step", "pm_learned_loss", "pm_adam",
-           "pm_power_mesh", "pm_net_table", "pm_net_table_vjp", "pm_ic_pseudo"]
+           "pm_power_mesh", "pm_net_table", "pm_net_table_vjp", "pm_ic_pseudo", "pm_paint_static"]
 
 
 def _check(st):
@@ -234,6 +235,15 @@ def pm_paint_q(ctx, x, first, count, quantum, mesh, stream=None):
 def pm_paint(ctx, x, seg_lo, seg_hi, mesh, stream=None):
     _check(_lib.pm_paint(ctx.h, _dev(x, torch.float32, 3 * ctx.P, "x"), seg_lo, seg_hi,
                          _dev(mesh, torch.int64, ctx.n ** 3, "mesh"), _stream(stream)))
+
+
+def pm_paint_static(ctx, x, seg_lo, seg_hi, mesh, stream=None):
+    """pm_paint's tile path with the library's fixed scratch array (no workspace scratch)."""
+    _check(_lib.pm_paint_static(ctx.h, _dev(x, torch.float32, 3 * ctx.P, "x"), seg_lo, seg_hi,
+                                _dev(mesh, torch.int64, ctx.n ** 3, "mesh"), _stream(stream)))
+
+
+PM_STATIC_MAX_MESH, PM_STATIC_MAX_PARTICLES = 512, 3145728
 
 
 def pm_fft_r2c(ctx, real, out, stream=None):
