@@ -107,11 +107,13 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(float *x, float *p, 
 // +1 halo are staged in LDS, then every particle sorted into the tile is read
 // out from LDS, kicked and drifted; results go to the caller's arrays at the
 // particle's sorted index (with its id, when ids are attached).
-// 512 threads: the 77 KB LDS tile allows two workgroups per CU, so the
-// workgroup itself must carry enough waves to hide memory latency.  The
+// 1024 threads: the 77 KB LDS tile allows two workgroups per CU, so the
+// workgroup itself must carry enough waves to hide memory latency (the LDS
+// fill has four loads per thread; 1024 threads took the C3 readout from 46.0
+// to 45.3 ms against 512).  The
 // particle range and each thread's first particle are loaded before the LDS
 // fill, and the next particle is loaded before the current one is stored.
-constexpr int READOUT_T = 512;
+constexpr int READOUT_T = 1024;
 
 __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__restrict__ xs,
                                                                 const float4 *__restrict__ ps, int64_t P,
