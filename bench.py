@@ -32,8 +32,14 @@ HBM_PEAK_GBS = 8000.0
 # when the counters were taken.
 MEASURED_TRAFFIC = {
     # profiles/c3_step_hbm_counters.md
-    "c2r_x0": {"bytes_per_launch": 69389015041, "source": "paper_2007_13394_amd/csrc/fft.hip",
-               "sha256_16": "d0d708190ae9d8cb"},
+    "c2r_x0": {"bytes_per_launch": 69388687282, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "711b9957287da624"},
+    "cols_inv": {"bytes_per_launch": 70539987324, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "711b9957287da624"},
+    "x0_green": {"bytes_per_launch": 103883518347, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "711b9957287da624"},
+    "readout_kick_drift": {"bytes_per_launch": 251680478099, "source": "paper_2007_13394_amd/csrc/particles.hip",
+                           "sha256_16": "cc118edac7296599"},
 }
 
 
