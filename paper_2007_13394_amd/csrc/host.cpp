@@ -419,7 +419,9 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
 // potential, every CNN pre-activation and activation and the density
 // spectrum stay in the workspace for the reverse mode; without, the fused
 // inference CNN keeps only the filtered potential and a2.
-pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStream_t s)
+// With `delta` (inference only), the density comes as the float32 contrast
+// the tile paint writes instead of the int64 mesh in Q.
+pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStream_t s, const float *delta = nullptr)
 {
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n, cs = n2 * nhp, rs = 2 * nhp;
@@ -427,8 +429,10 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
     const double M = (double)n2 * n;
     float2 *F = c->ws.f;
     const double qs = ldexp(1.0, -c->cfg.shift);
-    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, F, nhp, n2, qs, -1.0, c->ws.tw,
-                                              c->ws.flag, s));
+    if (delta)
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, delta, n, F, nhp, n2, c->ws.tw, s));
+    else
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, F, nhp, n2, qs, -1.0, c->ws.tw, c->ws.flag, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
     if (keep) LAUNCH(pm::K_COPY, hipMemcpyAsync(c->ws.net_dk, F, (size_t)cs * 8, hipMemcpyDeviceToDevice, s));
@@ -444,8 +448,8 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
                                              c->ws.net_a2, c->ws.net_dpsi, s));
         LAUNCH(pm::K_NET, pm::launch_combine(c->ws.net_phif, c->ws.net_dpsi, rs, n, Fr, s));
     } else {
-        LAUNCH(pm::K_NET, pm::launch_cnn_inf(c->ws.q, qs, c->ws.net_phif, rs, n, th, c->ws.net_wpk, c->ws.net_a2, Fr,
-                                             s));
+        LAUNCH(pm::K_NET, pm::launch_cnn_inf(c->ws.q, qs, delta, c->ws.net_phif, rs, n, th, c->ws.net_wpk,
+                                             c->ws.net_a2, Fr, s));
     }
     LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, Fr, rs, F, nhp, n2, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
@@ -1145,19 +1149,24 @@ pm_status pm_learned_step(pm_ctx *c, const float *th, float *x, float *p, double
     hipStream_t s = S(stream);
     const int64_t n = c->n, nhp = pm::half_pad(c->n);
     if (sorting_on(c)) {
-        // as pm_step: tile sort, tile paint, (learned) solve, tile readout
+        // as pm_step: tile sort, tile paint (float32 density contrast),
+        // (learned) solve, tile readout counting the next step's keys
         st = tile_sort(c, x, p, s);
         if (st != PM_OK) return st;
-        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, 0, c->nseg, c->n,
-                                                   c->ws.q, s));
-        st = learned_solve(c, th, a_force, false, s);
+        float *delta = reinterpret_cast<float *>(c->ws.q);
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles_delta(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, c->n,
+                                                         ldexp(1.0, -c->cfg.shift), -1.0, delta, c->ws.flag, s));
+        st = learned_solve(c, th, a_force, false, s, delta);
         if (st != PM_OK) return st;
+        int *cnt_next = (c->cfg.flags & PM_FLAG_NO_GUARDS) ? nullptr : c->ws.cnt_next;
+        if (cnt_next) LAUNCH(pm::K_FILL, pm::launch_fill_i32(cnt_next, c->nkeys + 1, s));
         LAUNCH(pm::K_READOUT_KD,
                pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * n * nhp, c->n,
                                            (float)kick, (float)drift, x, p, c->ws.tags, c->ws.ids_tmp, c->ids,
-                                           c->ws.flag, nullptr, s));
+                                           c->ws.flag, cnt_next, s));
         c->permuted = true;
-        c->counts_ready = false;
+        c->counts_ready = cnt_next != nullptr;
+        c->counts_x = x;
         return check_guards(c, s);
     }
     st = paint_all(c, x, s);

@@ -9,6 +9,8 @@
 // Parameters: one flat FP32 array (offsets in pm_internal.h).  The CNN takes
 // BF16 activations and weights and accumulates in FP32; the 16 -> 16 layer,
 // 89 % of the network's arithmetic, runs on MFMA (16x16x16 BF16 tiles).
+#include <type_traits>
+
 #include "pm_internal.h"
 
 namespace pm {
@@ -431,7 +433,10 @@ __global__ __launch_bounds__(256) void k_pack_w(const float *__restrict__ th, ui
 __device__ __forceinline__ int u1_off(int t) { return ((t / 9) * U1Y + (t / 3) % 3) * U1X + t % 3; }
 __device__ __forceinline__ int x_off(int t) { return ((t / 9) * C2HY + (t / 3) % 3) * C2HX + t % 3; }
 
-__global__ __launch_bounds__(256) void k_cnn12_inf(const int64_t *__restrict__ q, double qs, int n,
+// SRC int64_t: the fixed-point density, delta = q qs - 1 formed here; SRC
+// float: the density contrast as the tile paint stores it (the same value).
+template <typename SRC>
+__global__ __launch_bounds__(256) void k_cnn12_inf(const SRC *__restrict__ q, double qs, int n,
                                                    const float *__restrict__ th, const uint16_t *__restrict__ wpk,
                                                    uint16_t *a2)
 {
@@ -457,7 +462,7 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const int64_t *__restrict__ q
         // sunk into the guarded stores
         constexpr int NU = (U1N + 255) / 256;
         static_assert(NU == 8, "eight int64 loads per thread");
-        int64_t qv[NU];
+        SRC qv[NU];
 #pragma unroll
         for (int k = 0; k < NU; k++) {
             const int e = min(tid + 256 * k, U1N - 1);
@@ -470,7 +475,11 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const int64_t *__restrict__ q
 #pragma unroll
         for (int k = 0; k < NU; k++) {
             const int e = tid + 256 * k;
-            if (e < U1N) U[e] = delta_bf16(qv[k], qs);
+            if constexpr (std::is_same<SRC, int64_t>::value) {
+                if (e < U1N) U[e] = delta_bf16(qv[k], qs);
+            } else {
+                if (e < U1N) U[e] = to_bf16(qv[k]);
+            }
         }
     }
     __syncthreads();
@@ -892,13 +901,18 @@ hipError_t launch_cnn_fwd(const int64_t *q, double qs, int n, const float *th, f
     return hipGetLastError();
 }
 
-hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *phif, int64_t rs, int n, const float *th,
-                          uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s)
+hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *delta, const float *phif, int64_t rs, int n,
+                          const float *th, uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s)
 {
     if (n < 16 || n % 16) return hipErrorInvalidValue;
     const int64_t M = (int64_t)n * n * n;
     hipLaunchKernelGGL(k_pack_w, dim3(1), dim3(256), 0, s, th, wpk);
-    hipLaunchKernelGGL(k_cnn12_inf, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, q, qs, n, th, wpk, a2);
+    if (delta)
+        hipLaunchKernelGGL(k_cnn12_inf<float>, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, delta, qs, n,
+                           th, wpk, a2);
+    else
+        hipLaunchKernelGGL(k_cnn12_inf<int64_t>, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, q, qs, n,
+                           th, wpk, a2);
     hipLaunchKernelGGL((k_conv3_inf<C3TY, C3TZ, C3ZPT>), dim3((unsigned)(M / (16 * C3TY * C3TZ))), dim3(256), 0, s, a2,
                        n, th, wpk, phif, rs, out);
     return hipGetLastError();

@@ -284,8 +284,9 @@ hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int 
 // Inference CNN fused with the combination: out = phi_f + cnn(delta) on real
 // rows; a2: BF16 [n^3][16] scratch, wpk: NET_WPK_BYTES scratch for the
 // repacked weights.  n a multiple of 16.
-hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *phif, int64_t rs, int n, const float *th,
-                          uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s);
+// delta (optional): the float32 density contrast to use instead of q.
+hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *delta, const float *phif, int64_t rs, int n,
+                          const float *th, uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s);
 hipError_t launch_cnn_bwd(const int64_t *q, double qs, const float *phibar, int64_t rs, int n, const float *th,
                           const float *z1, const uint16_t *a1, const float *z2, const uint16_t *a2, float *g1,
                           float *g2, float *dth, hipStream_t s);
