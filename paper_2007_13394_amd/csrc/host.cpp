@@ -437,24 +437,36 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
     if (keep) LAUNCH(pm::K_COPY, hipMemcpyAsync(c->ws.net_dk, F, (size_t)cs * 8, hipMemcpyDeviceToDevice, s));
     LAUNCH(pm::K_NET, pm::launch_mlp_fwd(th, a, c->ws.net_table, s));
-    LAUNCH(pm::K_NET, pm::launch_spec_filter(F, F + cs, nhp, n, c->ws.net_table, -1.5 * c->cfg.omega_m / M, s));
-    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + cs, n * nhp, nhp, n, ncb, c->ws.tw, s));
-    LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
-    LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + cs, nhp, c->ws.net_phif, rs, n2, c->ws.tw, s));
     float *Fr = reinterpret_cast<float *>(F);
     if (keep) {
-        // the reverse mode needs every pre-activation and activation
+        // the reverse mode needs phi_f in real space and every pre-activation
+        // and activation of the CNN
+        LAUNCH(pm::K_NET, pm::launch_spec_filter(F, F + cs, nhp, n, c->ws.net_table, -1.5 * c->cfg.omega_m / M, s));
+        LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + cs, n * nhp, nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F + cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F + cs, nhp, c->ws.net_phif, rs, n2, c->ws.tw, s));
         LAUNCH(pm::K_NET, pm::launch_cnn_fwd(c->ws.q, qs, n, th, c->ws.net_z1, c->ws.net_a1, c->ws.net_z2,
                                              c->ws.net_a2, c->ws.net_dpsi, s));
         LAUNCH(pm::K_NET, pm::launch_combine(c->ws.net_phif, c->ws.net_dpsi, rs, n, Fr, s));
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, Fr, rs, F, nhp, n2, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_NET, pm::launch_grad3(F, nhp, cs, n, 1.0 / M, false, s));
     } else {
-        LAUNCH(pm::K_NET, pm::launch_cnn_inf(c->ws.q, qs, delta, c->ws.net_phif, rs, n, th, c->ws.net_wpk,
-                                             c->ws.net_a2, Fr, s));
+        // inference: the filtered potential never leaves spectral space.  The
+        // forward transform of phi_f = F^-1[g G delta(k)] / M is g G delta(k)
+        // itself, so field 1 holds it with coefficient -1.5 Omega_m (no 1/M);
+        // the CNN output goes to field 2 as real rows and is transformed
+        // there; the force is -i k (field 1 + field 2) / M.
+        LAUNCH(pm::K_NET, pm::launch_spec_filter(F, F + cs, nhp, n, c->ws.net_table, -1.5 * c->cfg.omega_m, s));
+        float *F2r = reinterpret_cast<float *>(F + 2 * cs);
+        LAUNCH(pm::K_NET, pm::launch_cnn_inf(c->ws.q, qs, delta, nullptr, rs, n, th, c->ws.net_wpk, c->ws.net_a2,
+                                             F2r, s));
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, F2r, rs, F + 2 * cs, nhp, n2, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F + 2 * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F + 2 * cs, n * nhp, nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_NET, pm::launch_grad3_sum(F, nhp, cs, n, 1.0 / M, s));
     }
-    LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, Fr, rs, F, nhp, n2, c->ws.tw, s));
-    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
-    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
-    LAUNCH(pm::K_NET, pm::launch_grad3(F, nhp, cs, n, 1.0 / M, false, s));
     for (int d = 0; d < 3; d++) {
         float2 *Fd = F + d * cs;
         LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, Fd, n * nhp, nhp, n, ncb, c->ws.tw, s));

@@ -235,6 +235,24 @@ __global__ void k_grad3(float2 *F, int64_t nhp, int64_t fs, int n, float scale)
     }
 }
 
+// F_d = -i k_d (A + B) scale for the sum of two spectra A (field 1) and B
+// (field 2), written to fields 0, 1, 2 (fields fs apart); zero on the
+// Nyquist plane of d.
+__global__ void k_grad3_sum(float2 *F, int64_t nhp, int64_t fs, int n, float scale)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const Mode m = mode_of(t, nhp, n);
+        const float2 a = F[fs + t], b = F[2 * fs + t];
+        const float2 v = make_float2(a.x + b.x, a.y + b.y);
+        const float f0 = (m.pad || m.nyq0) ? 0.f : m.k0 * scale, f1 = (m.pad || m.nyq1) ? 0.f : m.k1 * scale,
+                    f2 = (m.pad || m.nyq2) ? 0.f : m.k2 * scale;
+        F[t] = make_float2(f0 * v.y, -f0 * v.x);
+        F[fs + t] = make_float2(f1 * v.y, -f1 * v.x);
+        F[2 * fs + t] = make_float2(f2 * v.y, -f2 * v.x);
+    }
+}
+
 // Transpose: phibar = sum_d i k_d Fbar_d scale into field 0.
 __global__ void k_grad3_t(float2 *F, int64_t nhp, int64_t fs, int n, float scale)
 {
@@ -567,7 +585,8 @@ __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ 
     // phi_f of the thread's voxels, loaded now rather than after the sums
     float pf[ZPT];
 #pragma unroll
-    for (int z = 0; z < ZPT; z++) pf[z] = phif[((int64_t)(z0 + zg * ZPT + z) * n + (y0 + ly)) * rs + (x0 + lx)];
+    for (int z = 0; z < ZPT; z++)
+        pf[z] = phif ? phif[((int64_t)(z0 + zg * ZPT + z) * n + (y0 + ly)) * rs + (x0 + lx)] : 0.f;
     {
         // Every load of the halo fill is issued before the first LDS store
         // (one memory round trip per tile, not one per round).  Indices past
@@ -877,6 +896,13 @@ hipError_t launch_spec_filter_bwd(const float2 *dk, const float2 *pf, int64_t nh
     hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, tbar, NET_NB);
     hipLaunchKernelGGL(k_spec_filter_bwd, dim3(grid_for(tot, 256, 1024)), dim3(256), 0, s, dk, pf, nhp, n,
                        (float)coef, tbar);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad3_sum(float2 *F, int64_t nhp, int64_t fs, int n, double scale, hipStream_t s)
+{
+    const int64_t tot = (int64_t)n * n * nhp;
+    hipLaunchKernelGGL(k_grad3_sum, dim3(grid_for(tot, 256)), dim3(256), 0, s, F, nhp, fs, n, (float)scale);
     return hipGetLastError();
 }
 

@@ -277,6 +277,8 @@ hipError_t launch_spec_filter(const float2 *in, float2 *out, int64_t nhp, int n,
 hipError_t launch_spec_filter_bwd(const float2 *dk, const float2 *pf, int64_t nhp, int n, double coef, double *tbar,
                                   hipStream_t s);
 hipError_t launch_grad3(float2 *F, int64_t nhp, int64_t fs, int n, double scale, bool transpose, hipStream_t s);
+// F_d = -i k_d (F_1 + F_2) scale into fields 0, 1, 2 (the potential given as two spectra).
+hipError_t launch_grad3_sum(float2 *F, int64_t nhp, int64_t fs, int n, double scale, hipStream_t s);
 // CNN input: the int64 density mesh q with quantum qs (delta = q qs - 1).
 hipError_t launch_cnn_fwd(const int64_t *q, double qs, int n, const float *th, float *z1, uint16_t *a1, float *z2,
                           uint16_t *a2, float *dpsi, hipStream_t s);
@@ -284,7 +286,8 @@ hipError_t launch_combine(const float *phif, const float *dpsi, int64_t rs, int 
 // Inference CNN fused with the combination: out = phi_f + cnn(delta) on real
 // rows; a2: BF16 [n^3][16] scratch, wpk: NET_WPK_BYTES scratch for the
 // repacked weights.  n a multiple of 16.
-// delta (optional): the float32 density contrast to use instead of q.
+// delta (optional): the float32 density contrast to use instead of q; phif
+// (optional): added to the CNN output (none: the output is the CNN alone).
 hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *delta, const float *phif, int64_t rs, int n,
                           const float *th, uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s);
 hipError_t launch_cnn_bwd(const int64_t *q, double qs, const float *phibar, int64_t rs, int n, const float *th,
