@@ -691,6 +691,101 @@ __global__ __launch_bounds__(X0Cfg<N>::T, 4) void k_x0_green(const float2 *src, 
     }
 }
 
+// Pass B of the learned force (the two-pass form of the potential of the
+// learned correction): the same completion of the axis-0 transform on two
+// spectra, the density srcd and the CNN output srcc (both after the rows,
+// the first axis-0 digit and axis 1), then T = i (g(|k|) gr S_d - S_c / M)
+// with gr = coef / k^2, coef = 1.5 Omega_m / M and g the radial filter
+// table: the force of the potential phi_f + cnn is F_d = k_d T, as for the
+// plain force.  Writes k0 T and T after the inverse of pass B, like
+// k_x0_green; zero at k = 0 for the filtered part and in the padding.
+template <int N>
+__global__ __launch_bounds__(X0Cfg<N>::T, 2) void k_x0_learned(const float2 *srcd, const float2 *srcc,
+                                                            float2 *out0, float2 *out1, int64_t plane, int nhp,
+                                                            float coef, float inv_m, const float *__restrict__ table,
+                                                            const float2 *__restrict__ tw)
+{
+    using X = X0Cfg<N>;
+    constexpr int N2 = X::N2, R2 = X::R2, C = X::C, SPT = X::SPT;
+    __shared__ float2 lds[16 * R2 * C];
+    __shared__ float tab[NET_NB];
+    const int m = blockIdx.y;
+    static_assert(C == 64, "one wavefront per g: g and the twiddles it selects are wave-uniform");
+    const int c = threadIdx.x % C, g = __builtin_amdgcn_readfirstlane((int)threadIdx.x / C);
+    for (int i = threadIdx.x; i < NET_NB; i += X::T) tab[i] = table[i];
+    const int64_t e = (int64_t)blockIdx.x * C + c;
+    const int64_t pbase = (int64_t)(N2 * m + g) * plane + e;
+    const int64_t pstep = (int64_t)R2 * plane;
+    const float2 *twN2 = tw + N2;
+    float2 v[16], w[16];
+    // pass B forward on one field: step 1 through LDS, step 2 in registers
+    auto forward = [&](const float2 *src, float2 (&u)[16]) {
+#pragma unroll
+        for (int i = 0; i < 16; i++) u[i] = src[pbase + i * pstep];
+        Dft<16, false>::run(u);
+        if constexpr (R2 > 1) {
+#pragma unroll
+            for (int a = 1; a < 16; a++) u[a] = cmul(u[a], twN2[g * a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 16; a++) lds[(a * R2 + g) * C + c] = u[a];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < SPT; s++) {
+            const int a = g + R2 * s;
+#pragma unroll
+            for (int l = 0; l < R2; l++) u[s * R2 + l] = lds[(a * R2 + l) * C + c];
+            Dft<R2, false>::run(u + s * R2);
+        }
+        __syncthreads();
+    };
+    forward(srcc, w);
+    forward(srcd, v);
+    const float sc = 6.28318530717958648f / (float)N;
+    const int k1i = (int)(e / nhp), k2 = (int)(e % nhp);
+    const int n1 = signed_mode(k1i, N);
+    const float k1 = sc * n1, kz = sc * k2, kperp = k1 * k1 + kz * kz;
+#pragma unroll
+    for (int s = 0; s < SPT; s++)
+#pragma unroll
+        for (int l = 0; l < R2; l++) {
+            const int k = g + R2 * s + 16 * l;
+            const int n0 = signed_mode(m + 16 * k, N);
+            const float k0 = sc * n0, kk = k0 * k0 + kperp;
+            int b;
+            float wt;
+            const float filt = table_at(tab, sqrtf(kk) * 0.31830988618379067f, b, wt);
+            const float gr = (k2 > N / 2 || kk == 0.f) ? 0.f : filt * coef / kk;
+            const float cm = k2 > N / 2 ? 0.f : inv_m;
+            const float2 x = v[s * R2 + l], y = w[s * R2 + l];
+            const float2 u = make_float2(gr * x.x - cm * y.x, gr * x.y - cm * y.y);
+            const float2 t = make_float2(-u.y, u.x);                             // T = i (g gr S_d - S_c / M)
+            w[s * R2 + l] = t;
+            const float g0 = (n0 == N / 2 || n0 == -N / 2) ? 0.f : k0;
+            v[s * R2 + l] = make_float2(g0 * t.x, g0 * t.y);                  // k0 T
+        }
+    x0_inverse_b<N>(v, lds, c, g, twN2);
+    {
+        float2 *q = out0 + pbase;
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            asm volatile("" : "+v"(q));
+            *q = v[i];
+            q += pstep;
+        }
+    }
+    x0_inverse_b<N>(w, lds, c, g, twN2);
+    {
+        float2 *q1 = out1 + pbase;
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            asm volatile("" : "+v"(q1));
+            *q1 = w[i];
+            q1 += pstep;
+        }
+    }
+}
+
 // Rows fused with pass A: one workgroup takes the 16 rows (plane j1 + N2 j,
 // row x1), j < 16, of a field, so the 16-point axis-0 DFT across them costs
 // no HBM pass of its own.  Forward: real-to-complex of the 16 int64 rows,
@@ -703,8 +798,8 @@ __global__ __launch_bounds__(X0Cfg<N>::T, 4) void k_x0_green(const float2 *src, 
 // on load (overflow flag as in the row transform); SRC float: the density
 // contrast itself, written by the tile paint.
 template <int LOGN, typename SRC>
-__global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const SRC *src, float2 *dst, int nhp, int64_t plane,
-                                                            double scale, double offset,
+__global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const SRC *src, int64_t src_rs, float2 *dst, int nhp,
+                                                            int64_t plane, double scale, double offset,
                                                             const float2 *__restrict__ tw, int *flag)
 {
     constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, PS = SWZ_ROWS;
@@ -724,7 +819,7 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const SRC *src, floa
 #pragma unroll 4
     for (int e = tid; e < RB * L; e += T) {
         const int r = e / L, m = e % L;
-        const SRC *row = src + ((int64_t)(j1 + N2 * r) * N + x1) * N + 2 * m;
+        const SRC *row = src + ((int64_t)(j1 + N2 * r) * N + x1) * src_rs + 2 * m;
         if constexpr (std::is_same<SRC, int64_t>::value) {
             const longlong2 q = *reinterpret_cast<const longlong2 *>(row);
             bad |= (q.x < GUARD_MIN_Q) | (q.y < GUARD_MIN_Q);
@@ -968,14 +1063,34 @@ hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *ou
     return hipGetLastError();
 }
 
+hipError_t launch_x0_learned(int logn, const float2 *srcd, const float2 *srcc, float2 *out0, float2 *out1,
+                             int64_t plane, int nhp, double coef, double inv_m, const float *table, const float2 *tw,
+                             hipStream_t s)
+{
+    if (logn < 8 || logn > 11 || plane % 64 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(plane / 64), 16);
+    const float fc = (float)coef, fm = (float)inv_m;
+#define X0L(NN)                                                                                      \
+    hipLaunchKernelGGL((k_x0_learned<NN>), grid, dim3(X0Cfg<NN>::T), 0, s, srcd, srcc, out0, out1, plane, nhp, fc, fm, \
+                       table, tw)
+    switch (logn) {
+    case 8: X0L(256); break;
+    case 9: X0L(512); break;
+    case 10: X0L(1024); break;
+    default: X0L(2048); break;
+    }
+#undef X0L
+    return hipGetLastError();
+}
+
 hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int64_t plane, double scale,
                          double offset, const float2 *tw, int *flag, hipStream_t s)
 {
     if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
 #define R2CX(LG)                                                                                     \
-    hipLaunchKernelGGL((k_r2c_x0<LG, int64_t>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, nhp, plane, scale, \
-                       offset, tw, flag)
+    hipLaunchKernelGGL((k_r2c_x0<LG, int64_t>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, (int64_t)1 << LG, dst, nhp, \
+                       plane, scale, offset, tw, flag)
     switch (logn) {
     case 8: R2CX(8); break;
     case 9: R2CX(9); break;
@@ -986,14 +1101,15 @@ hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int
     return hipGetLastError();
 }
 
-hipError_t launch_r2c_x0_f32(int logn, const float *src, float2 *dst, int nhp, int64_t plane, const float2 *tw,
-                             hipStream_t s)
+hipError_t launch_r2c_x0_f32(int logn, const float *src, int64_t src_rs, float2 *dst, int nhp, int64_t plane,
+                             const float2 *tw, hipStream_t s)
 {
-    if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn) || src_rs < ((int64_t)1 << logn))
+        return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
 #define R2CX(LG)                                                                                     \
-    hipLaunchKernelGGL((k_r2c_x0<LG, float>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, nhp, plane, 1.0, 0.0, \
-                       tw, static_cast<int *>(nullptr))
+    hipLaunchKernelGGL((k_r2c_x0<LG, float>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, src_rs, dst, nhp, plane, 1.0, \
+                       0.0, tw, static_cast<int *>(nullptr))
     switch (logn) {
     case 8: R2CX(8); break;
     case 9: R2CX(9); break;

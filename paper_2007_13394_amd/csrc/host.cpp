@@ -331,7 +331,7 @@ pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s, const float *delta
         // Laplacian; the spectrum stays digit-reversed along axis 0 in between
         const int64_t plane = (int64_t)n * nhp;
         if (delta)
-            LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0_f32(lg, delta, F, (int)nhp, plane, c->ws.tw, s));
+            LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0_f32(lg, delta, n, F, (int)nhp, plane, c->ws.tw, s));
         else
             LAUNCH(pm::K_R2C_X0,
                    pm::launch_r2c_x0(lg, src, F, (int)nhp, plane, scale, -1.0, c->ws.tw, c->ws.flag, s));
@@ -452,6 +452,32 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
         LAUNCH(pm::K_NET, pm::launch_grad3(F, nhp, cs, n, 1.0 / M, false, s));
+    } else if (lg >= 8) {
+        // inference on the two-pass transforms of the plain solve: rows with
+        // the first axis-0 digit and axis 1 for the density and for the CNN
+        // output (real rows in field 2, transformed in place); one pass B
+        // takes both, forms T = i (g gr S_d - S_c / M) and writes k0 T and T;
+        // the inverse passes are the plain solve's
+        const int64_t plane = (int64_t)n * nhp;
+        if (delta)
+            LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0_f32(lg, delta, n, F, (int)nhp, plane, c->ws.tw, s));
+        else
+            LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0(lg, c->ws.q, F, (int)nhp, plane, qs, -1.0, c->ws.tw, c->ws.flag, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        float *F2r = reinterpret_cast<float *>(F + 2 * cs);
+        LAUNCH(pm::K_NET, pm::launch_cnn_inf(c->ws.q, qs, delta, nullptr, rs, n, th, c->ws.net_wpk, c->ws.net_a2,
+                                             F2r, s));
+        LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0_f32(lg, F2r, rs, F + 2 * cs, (int)nhp, plane, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F + 2 * cs, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_NET, pm::launch_x0_learned(lg, F, F + 2 * cs, F, F + cs, plane, (int)nhp, 1.5 * c->cfg.omega_m / M,
+                                                1.0 / M, c->ws.net_table, c->ws.tw, s));
+        for (int d = 2; d >= 0; d--) {
+            LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, d == 0 ? F : F + cs, nhp, n * nhp, n, ncb, c->ws.tw, s,
+                                                   d, F + d * cs));
+            LAUNCH(pm::K_C2R_X0, pm::launch_c2r_x0(lg, F + d * cs, reinterpret_cast<float *>(F + d * cs), 2 * nhp,
+                                                   (int)nhp, plane, c->ws.tw, s));
+        }
+        return PM_OK;
     } else {
         // inference: the filtered potential never leaves spectral space.  The
         // forward transform of phi_f = F^-1[g G delta(k)] / M is g G delta(k)

@@ -159,14 +159,6 @@ __device__ __forceinline__ Mode mode_of(int64_t t, int64_t nhp, int n)
     return m;
 }
 
-__device__ __forceinline__ float table_at(const float *table, float kt, int &b, float &w)
-{
-    const float tt = kt * (float)(NET_NB - 1) / 1.7320508075688772f;
-    b = (int)floorf(tt);
-    if (b > NET_NB - 2) b = NET_NB - 2;
-    w = tt - (float)b;
-    return (1.f - w) * table[b] + w * table[b + 1];
-}
 
 // out = g(|k|) coef / k^2 in (k = 0 and padding -> 0).
 __global__ void k_spec_filter(const float2 *in, float2 *out, int64_t nhp, int n, const float *table, float coef)

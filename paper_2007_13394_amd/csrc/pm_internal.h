@@ -141,6 +141,18 @@ struct Workspace {
 // Learned force correction: MLP width, radial table bins, CNN channels, and
 // offsets into the flat parameter array.
 constexpr int NET_H = 96, NET_NB = 256, NET_C = 16;
+
+// The learned radial filter at kt = |k| / k_Nyq: linear interpolation in the
+// table of NET_NB bins kt_b = b sqrt(3) / (NET_NB - 1); b and w receive the
+// lower bin and the weight of the upper one.
+__device__ __forceinline__ float table_at(const float *table, float kt, int &b, float &w)
+{
+    const float tt = kt * (float)(NET_NB - 1) / 1.7320508075688772f;
+    b = (int)floorf(tt);
+    if (b > NET_NB - 2) b = NET_NB - 2;
+    w = tt - (float)b;
+    return (1.f - w) * table[b] + w * table[b + 1];
+}
 constexpr int NET_WPK_BYTES = 32768;
 constexpr int NW0 = 0, NB0 = NW0 + NET_H * 2, NW1 = NB0 + NET_H, NB1 = NW1 + NET_H * NET_H, NW2 = NB1 + NET_H,
               NB2 = NW2 + NET_H * NET_H, NW3 = NB2 + NET_H, NB3 = NW3 + NET_H, NC1W = NB3 + 1,
@@ -245,7 +257,13 @@ hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *ou
 hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int64_t plane, double scale,
                          double offset, const float2 *tw, int *flag, hipStream_t s);
 // The same pass on a float32 density contrast mesh (already offset and scaled).
-hipError_t launch_r2c_x0_f32(int logn, const float *src, float2 *dst, int nhp, int64_t plane, const float2 *tw,
+hipError_t launch_r2c_x0_f32(int logn, const float *src, int64_t src_rs, float2 *dst, int nhp, int64_t plane,
+                             const float2 *tw, hipStream_t s);
+// Pass B of the learned force on two fields after rows, first digit and axis
+// 1: the density spectrum srcd and the CNN output's srcc; writes k0 T and T
+// with T = i (g(|k|) coef / k^2 S_d - inv_m S_c) (table: the radial filter).
+hipError_t launch_x0_learned(int logn, const float2 *srcd, const float2 *srcc, float2 *out0, float2 *out1,
+                             int64_t plane, int nhp, double coef, double inv_m, const float *table, const float2 *tw,
                              hipStream_t s);
 hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int nhp, int64_t plane,
                          const float2 *tw, hipStream_t s);

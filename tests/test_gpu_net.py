@@ -180,3 +180,64 @@ def test_filter_table_and_its_vjp_vs_oracle(dev):
         e_t, e_d = np.max(np.abs(tab - ref)), rel_l2(d.cpu().numpy(), dref)
         say("a", a, "table max abs err", e_t, "vjp rel L2", e_d)
         assert e_t < 1e-5 and e_d < 1e-4
+
+
+def _golden_256():
+    import importlib.util
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_learned_force", os.path.join(here, "make_learned_force.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(here, "learned_force_256.json")) as f:
+        return mod, json.load(f)
+
+
+def test_learned_force_two_pass_transforms_vs_oracle_256(dev):
+    """On meshes of 256^3 and more the learned force runs on the two-pass
+    transforms: the density and the CNN output each through rows with the
+    first axis-0 digit and axis 1, one pass B that forms the potential's
+    gradient factor from both (radial filter on the density part), and the
+    plain solve's inverse passes.  Against the FP64 oracle's learned force at
+    4096 sampled particles (fixture of tests/golden/make_learned_force.py):
+    the force within 1e-2 and its correction over the plain force within
+    3e-2 (relative L2).  The sorted learned step (float32 density from the
+    tile paint) must then match the unsorted one."""
+    from paper_2007_13394_amd import pm
+    mod, ref = _golden_256()
+    cfg = I.config(ref["config"]["name"], n_cdm=ref["config"]["n_cdm"], n_sites=ref["config"]["n_sites"])
+    assert cfg["n_mesh"] == 256
+    n = cfg["n_mesh"]
+    th32 = mod.params(ref["theta_seed"])
+    th = torch.from_numpy(th32).to(dev)
+    x32, p32 = I.synthetic_state(cfg, seed=ref["state_seed"])
+    idx = np.array(ref["index"])
+    cu = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_LEARNED | pm.PM_FLAG_NO_SORT))
+    xu = torch.from_numpy(x32).to(dev)
+    acc = torch.empty_like(xu)
+    pm.pm_learned_force(cu, th, ref["a"], xu, acc)
+    got = acc.cpu().numpy().astype(np.float64)[:, idx]
+    want, plain = np.array(ref["force"]), np.array(ref["plain_force"])
+    e_f = rel_l2(got, want)
+    e_c = rel_l2(got - plain, want - plain)
+    say("learned force at 256^3 (two-pass transforms) vs oracle: rel L2", e_f, "; correction", e_c,
+        "; correction / plain force", rel_l2(want, plain))
+    assert e_f < 1e-2 and e_c < 3e-2
+    # sorted (float32 density, fused counts) against unsorted learned steps
+    cs = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_LEARNED))
+    ids = torch.arange(cs.P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(cs, ids)
+    xs, ps = torch.from_numpy(x32).to(dev), torch.from_numpy(p32).to(dev)
+    xu, pu = xs.clone(), ps.clone()
+    for c in [(0.5, 0.5, 0.55, 0.6), (0.6, 0.55, 0.65, 0.7)]:
+        pm.pm_learned_step(cs, th, xs, ps, *c)
+        pm.pm_learned_step(cu, th, xu, pu, *c)
+    pm.pm_attach_ids(cs, None)
+    order = torch.argsort(ids.long())
+    xo, po = xs[:, order], ps[:, order]
+    dx = (xo - xu).abs()
+    dx = torch.minimum(dx, n - dx).max().item()
+    ep = rel_l2(po.cpu().numpy(), pu.cpu().numpy())
+    say("256^3 sorted vs unsorted learned steps: max |dx|", dx, "p rel L2", ep)
+    assert dx < 1e-3 and ep < 1e-5
