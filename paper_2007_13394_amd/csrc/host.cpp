@@ -429,12 +429,16 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
     const double M = (double)n2 * n;
     float2 *F = c->ws.f;
     const double qs = ldexp(1.0, -c->cfg.shift);
-    if (delta)
-        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, delta, n, F, nhp, n2, c->ws.tw, s));
-    else
-        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, F, nhp, n2, qs, -1.0, c->ws.tw, c->ws.flag, s));
-    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
-    LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    const bool two_pass = !keep && lg >= 8;
+    if (!two_pass) {
+        // natural-order forward transform of the density
+        if (delta)
+            LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, delta, n, F, nhp, n2, c->ws.tw, s));
+        else
+            LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, F, nhp, n2, qs, -1.0, c->ws.tw, c->ws.flag, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
+    }
     if (keep) LAUNCH(pm::K_COPY, hipMemcpyAsync(c->ws.net_dk, F, (size_t)cs * 8, hipMemcpyDeviceToDevice, s));
     LAUNCH(pm::K_NET, pm::launch_mlp_fwd(th, a, c->ws.net_table, s));
     float *Fr = reinterpret_cast<float *>(F);
@@ -452,7 +456,7 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
         LAUNCH(pm::K_NET, pm::launch_grad3(F, nhp, cs, n, 1.0 / M, false, s));
-    } else if (lg >= 8) {
+    } else if (two_pass) {
         // inference on the two-pass transforms of the plain solve: rows with
         // the first axis-0 digit and axis 1 for the density and for the CNN
         // output (real rows in field 2, transformed in place); one pass B
