@@ -494,9 +494,11 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const SRC *__restrict__ q, do
     }
     __syncthreads();
     {
+        // taps 27..31 read a real voxel (tap 26's) against zero weights, so
+        // every lane's eight reads are unconditional (no exec-mask branches)
         int ou[8];
 #pragma unroll
-        for (int j = 0; j < 8; j++) ou[j] = 8 * kg + j < 27 ? u1_off(8 * kg + j) : -1;
+        for (int j = 0; j < 8; j++) ou[j] = u1_off(8 * kg + j < 27 ? 8 * kg + j : 26);
         float bias[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) bias[r] = th[NC1B + 4 * kg + r];
@@ -507,8 +509,7 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const SRC *__restrict__ q, do
             const int base = (hz * U1Y + hy) * U1X + hx;
             v8bf b;
 #pragma unroll
-            for (int j = 0; j < 8; j++)
-                b[j] = __builtin_bit_cast(__bf16, ou[j] >= 0 ? U[base + ou[j]] : (uint16_t)0);
+            for (int j = 0; j < 8; j++) b[j] = __builtin_bit_cast(__bf16, U[base + ou[j]]);
             v4f acc = {0.f, 0.f, 0.f, 0.f};
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, b, acc, 0, 0, 0);
             // lane holds D[co = 4 kg + r][vox = col]: channels 4 kg .. 4 kg + 3
