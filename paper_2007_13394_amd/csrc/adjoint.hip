@@ -131,6 +131,44 @@ __global__ __launch_bounds__(256) void k_paint_vec3(const float *__restrict__ x,
     }
 }
 
+// Largest |gscale g| over n values, as the bits of a non-negative float (their
+// order is the order of unsigned ints): a per-wavefront maximum, then one
+// atomicMax per wavefront on *out (zeroed by the caller).
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ g, int64_t count, float gscale,
+                                                unsigned *out)
+{
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(gscale * g[i]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+// One cotangent component in fixed point: Q(c) += llrint(S w_c gscale g_i)
+// with the cloud-in-cell weight w_c of particle i (the float products of the
+// FP32 form).  Integer sums do not depend on the order of the atomics, so the
+// cotangent mesh, and the gradient built from it, is the same on every run.
+__global__ __launch_bounds__(256) void k_paint_q1(const float *__restrict__ x, int64_t P,
+                                                  const float *__restrict__ gd, float gscale, double S, int n,
+                                                  unsigned long long *Q)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, n);
+        const double v = (double)(gscale * gd[i]) * S;
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    const float w = (q.w[0][a] * q.w[1][b]) * q.w[2][e];
+                    const long long iq = (long long)__builtin_rint((double)w * v);
+                    atomicAdd(Q + q.row[a][b] + q.c2[e], (unsigned long long)iq);
+                }
+    }
+}
+
 // psi(k) = -coef sum_d i k_d / k^2 G_d(k) into field 0 (natural-order half
 // spectra, row stride nhp, field stride fs); zero at k = 0 and, per term, on
 // the Nyquist plane of component d.
@@ -241,6 +279,20 @@ hipError_t launch_paint_vec3(const float *x, int64_t P, const float *g, float gs
                              int64_t cs, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_paint_vec3, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P, g, gscale, G, rs, cs, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax(const float *g, int64_t count, float gscale, unsigned *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_absmax, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, g, count, gscale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_paint_q1(const float *x, int64_t P, const float *gd, float gscale, double S, int n, int64_t *Q,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_paint_q1, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P, gd, gscale, S, n,
+                       reinterpret_cast<unsigned long long *>(Q));
     return hipGetLastError();
 }
 

@@ -3,6 +3,9 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
+
+#include <cmath>
 
 #include <mutex>
 #include <new>
@@ -395,11 +398,26 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
     if (st == PM_OK) st = solve(c, c->ws.q, s);
     if (st != PM_OK) return st;
     LAUNCH(pm::K_ADJOINT, pm::launch_readout_grad3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, xbar, s));
-    LAUNCH(pm::K_FILL, pm::launch_fill_i64(reinterpret_cast<int64_t *>(F), 3 * cs, s));
-    LAUNCH(pm::K_ADJOINT, pm::launch_paint_vec3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, s));
+    // cotangent paint in fixed point, one component at a time through Q (free
+    // after the solve): a unit of 1/S with S a power of two such that even all
+    // particles' largest cotangent in one cell stays below 2^62, so the mesh
+    // and the gradient are bit-reproducible
+    unsigned *gmax = reinterpret_cast<unsigned *>(c->ws.flag) + 8;
+    int *unused_flag = c->ws.flag + 9;
+    LAUNCH(pm::K_FILL, pm::launch_fill_i32(reinterpret_cast<int *>(gmax), 1, s));
+    LAUNCH(pm::K_ADJOINT, pm::launch_absmax(g, 3 * c->P, (float)gscale, gmax, s));
+    unsigned mbits = 0;
+    HIPCHK(hipMemcpyAsync(&mbits, gmax, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float gm;
+    memcpy(&gm, &mbits, sizeof gm);
+    if (!std::isfinite(gm)) return fail(PM_ERR_NAN, "a cotangent is not finite");
+    const double S = gm > 0 ? ldexp(1.0, 61 - (int)ceil(log2((double)c->P * (double)gm))) : 1.0;
     for (int d = 0; d < 3; d++) {
         float2 *Fd = F + d * cs;
-        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, reinterpret_cast<float *>(Fd), 2 * nhp, Fd, nhp, n2, c->ws.tw, s));
+        LAUNCH(pm::K_FILL, pm::launch_fill_i64(c->ws.q, (int64_t)n * n * n, s));
+        LAUNCH(pm::K_ADJOINT, pm::launch_paint_q1(x, c->P, g + d * c->P, (float)gscale, S, n, c->ws.q, s));
+        LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, Fd, nhp, n2, 1.0 / S, 0.0, c->ws.tw, unused_flag, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, nhp, n * nhp, n, ncb, c->ws.tw, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, n * nhp, nhp, n, ncb, c->ws.tw, s));
     }

@@ -277,6 +277,11 @@ hipError_t launch_readout_grad3(const float *x, int64_t P, const float *g, float
                                 int64_t cs, int n, float *xbar, hipStream_t s);
 hipError_t launch_paint_vec3(const float *x, int64_t P, const float *g, float gscale, float *G, int64_t rs,
                              int64_t cs, int n, hipStream_t s);
+// max |gscale g| over count values into *out as float bits (zero *out first).
+hipError_t launch_absmax(const float *g, int64_t count, float gscale, unsigned *out, hipStream_t s);
+// Q (int64 [N]^3, added to) += llrint(S w gscale g_d) per particle and corner.
+hipError_t launch_paint_q1(const float *x, int64_t P, const float *gd, float gscale, double S, int n, int64_t *Q,
+                           hipStream_t s);
 hipError_t launch_green_adj(float2 *F, int64_t nhp, int64_t fs, int n, double coef, hipStream_t s);
 hipError_t launch_density_grad(const float *x, int64_t P, const float *mesh, int64_t rs, int n, int nseg,
                                const int64_t *seg_off, const uint8_t *tags, const int64_t *quanta, float qscale,

@@ -1,8 +1,9 @@
 """GPU reverse mode (pm_*_vjp through the C ABI, and the autograd layer)
 against the FP64 oracle's reverse mode, which is itself pinned by central
 finite differences (test_oracle_adjoint.py).  Same float32 inputs on both
-sides; bar: relative L2 <= 1e-4 (FP32 state and transforms, float atomics in
-the cotangent paint, against FP64)."""
+sides; bar: relative L2 <= 1e-4 (FP32 state and transforms against FP64).
+The cotangent paint is in int64 fixed point, so the force VJP is
+bit-reproducible and independent of the particle order."""
 import sys
 
 import numpy as np
@@ -193,3 +194,30 @@ def test_chain_gradient_vs_independent_oracle_run(dev, name):
     say(name, "independent runs: loss", loss, "oracle", rloss, "gradient rel L2", e)
     assert abs(loss - rloss) / rloss < 1e-4
     assert e < 5e-4
+
+
+def test_force_vjp_bit_reproducible_and_order_independent(dev):
+    """The cotangent paint of the force VJP sums integer quanta, so the
+    gradient is identical on every run and under any permutation of the
+    particles (the permuted gradient, mapped back, equals the first bit for
+    bit)."""
+    pm, cfg, ctx, sim = _setup("C5")
+    x32, _ = I.synthetic_state(cfg, seed=31)
+    P = x32.shape[1]
+    g32 = np.random.default_rng(32).standard_normal((3, P)).astype(np.float32)
+    x, g = torch.from_numpy(x32).to(dev), torch.from_numpy(g32).to(dev)
+    xb1, xb2 = torch.zeros_like(x), torch.zeros_like(x)
+    pm.pm_force_vjp(ctx, x, g, xb1)
+    pm.pm_force_vjp(ctx, x, g, xb2)
+    assert torch.equal(xb1, xb2)
+    # permute inside each segment (masses are per segment): same gradient per particle
+    off, _, _ = pm.pm_segments(ctx)
+    rng = np.random.default_rng(33)
+    perm = np.concatenate([rng.permutation(np.arange(off[k], off[k + 1])) for k in range(len(off) - 1)])
+    pt = torch.from_numpy(perm).to(dev)
+    xb3 = torch.zeros_like(x)
+    pm.pm_force_vjp(ctx, x[:, pt].contiguous(), g[:, pt].contiguous(), xb3)
+    back = torch.empty_like(xb3)
+    back[:, pt] = xb3
+    say("force VJP: repeat identical", True, "; permuted max |diff|", float((back - xb1).abs().max()))
+    assert torch.equal(back, xb1)
