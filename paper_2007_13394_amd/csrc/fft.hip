@@ -816,18 +816,28 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const SRC *src, int6
 #pragma unroll
     for (int m = 1; m < 16; m++) tj[m] = tw[N + j1 * m];
     bool bad = false;
-#pragma unroll 4
-    for (int e = tid; e < RB * L; e += T) {
-        const int r = e / L, m = e % L;
-        const SRC *row = src + ((int64_t)(j1 + N2 * r) * N + x1) * src_rs + 2 * m;
-        if constexpr (std::is_same<SRC, int64_t>::value) {
-            const longlong2 q = *reinterpret_cast<const longlong2 *>(row);
-            bad |= (q.x < GUARD_MIN_Q) | (q.y < GUARD_MIN_Q);
-            buf[pad<PS>(e)] =
-                make_float2((float)((double)q.x * scale + offset), (float)((double)q.y * scale + offset));
-        } else {
-            buf[pad<PS>(e)] = *reinterpret_cast<const float2 *>(row);
+    // thread tid moves element tid of each of the 16 rows; all 16 loads are
+    // issued before the first LDS write (one workgroup per CU: a
+    // load-then-store loop would keep only a few requests in flight)
+    static_assert(RB * L == 16 * T, "one element per row and thread");
+    const SRC *row0 = src + ((int64_t)j1 * N + x1) * src_rs + 2 * tid;
+    const int64_t rstep = (int64_t)N2 * N * src_rs;
+    if constexpr (std::is_same<SRC, int64_t>::value) {
+        longlong2 q[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) q[r] = *reinterpret_cast<const longlong2 *>(row0 + r * rstep);
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            bad |= (q[r].x < GUARD_MIN_Q) | (q[r].y < GUARD_MIN_Q);
+            buf[pad<PS>(r * L + tid)] =
+                make_float2((float)((double)q[r].x * scale + offset), (float)((double)q[r].y * scale + offset));
         }
+    } else {
+        float2 q[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) q[r] = *reinterpret_cast<const float2 *>(row0 + r * rstep);
+#pragma unroll
+        for (int r = 0; r < 16; r++) buf[pad<PS>(r * L + tid)] = q[r];
     }
     if (bad) atomicOr(flag, FLAG_OVERFLOW);
     __syncthreads();

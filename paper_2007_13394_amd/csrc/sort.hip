@@ -143,10 +143,10 @@ __global__ void k_scan_add(int *out, int64_t n, const int *sums, int *out2)
 // Scatter into float4 records: one 16-byte store for the position and the
 // segment tag, one for the momentum, so a particle that moves far in the
 // order costs two stores instead of seven partial ones.  The optional arrays
-// are template flags, so a particle's loads are issued at once; the next
-// round's position is loaded before this round's atomic, so the two memory
-// round trips of a round overlap.  The pointers do not alias (caller arrays
-// in, workspace records out).
+// are template flags.  A thread's eight particles are loaded up front, then
+// the eight cursor atomics are issued back to back, then the stores: two
+// memory round trips per chunk instead of two per particle.  The pointers do
+// not alias (caller arrays in, workspace records out).
 template <bool HP, bool HT, bool HI>
 __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const float *__restrict__ x,
                                               const float *__restrict__ p, const uint8_t *__restrict__ tag_in,
@@ -154,53 +154,54 @@ __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const floa
                                               int *cursor, float4 *__restrict__ xs, float4 *__restrict__ ps,
                                               const uint32_t *__restrict__ ids_in, uint32_t *__restrict__ ids_out)
 {
+    constexpr int NR = SORT_CH / SORT_T;
     const int lane = threadIdx.x & 63;
-    int64_t i = c0 + threadIdx.x;
-    float a0, a1, a2;
-    {
-        const int64_t ic = i < c1 ? i : c0;
-        a0 = x[ic];
-        a1 = x[P + ic];
-        a2 = x[2 * P + ic];
-        // taken here, the first loads leave nothing for the loop head to wait on
-        asm volatile("" : "+v"(a0), "+v"(a1), "+v"(a2));
-    }
-    for (int64_t base = c0; base < c1; base += SORT_T, i += SORT_T) {
-        const bool live = i < c1;
-        const int64_t ic = live ? i : c0;
-        const float u0 = a0, u1 = a1, u2 = a2;
-        const int k = live ? tile_key(u0, u1, u2, n) : -1;
-        float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    // indices past the chunk are clamped to c0, a valid particle, and dropped
+    float a0[NR], a1[NR], a2[NR], b0[NR], b1[NR], b2[NR];
+    int t[NR];
+    uint32_t id[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const int64_t i = c0 + threadIdx.x + r * SORT_T, ic = i < c1 ? i : c0;
+        a0[r] = x[ic];
+        a1[r] = x[P + ic];
+        a2[r] = x[2 * P + ic];
         if constexpr (HP) {
-            b0 = p[ic];
-            b1 = p[P + ic];
-            b2 = p[2 * P + ic];
+            b0[r] = p[ic];
+            b1[r] = p[P + ic];
+            b2[r] = p[2 * P + ic];
+        } else {
+            b0[r] = b1[r] = b2[r] = 0.f;
         }
-        int t = 0;
         if constexpr (HT) {
-            t = tag_in[ic];
+            t[r] = tag_in[ic];
         } else {   // canonical order: segment from the offsets
-            for (int g = 1; g < nseg; g++) t += (ic >= seg_off[g]) ? 1 : 0;
+            int g0 = 0;
+            for (int g = 1; g < nseg; g++) g0 += (ic >= seg_off[g]) ? 1 : 0;
+            t[r] = g0;
         }
-        uint32_t id = 0;
-        if constexpr (HI) id = ids_in[ic];
-        {
-            const int64_t in = i + SORT_T, icn = in < c1 ? in : c0;
-            a0 = x[icn];
-            a1 = x[P + icn];
-            a2 = x[2 * P + icn];
-        }
-        uint64_t group;
-        int leader;
-        key_group(live, k, group, leader);
-        int b = 0;
-        if (live && lane == leader) b = atomicAdd(cursor + k, __popcll(group));
-        b = __shfl(b, leader);
-        const int64_t d = (int64_t)b + __popcll(group & ((1ull << lane) - 1));
+        id[r] = 0;
+        if constexpr (HI) id[r] = ids_in[ic];
+    }
+    uint64_t group[NR];
+    int leader[NR], base[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const bool live = c0 + threadIdx.x + r * SORT_T < c1;
+        const int k = live ? tile_key(a0[r], a1[r], a2[r], n) : -1;
+        key_group(live, k, group[r], leader[r]);
+        base[r] = 0;
+        if (live && lane == leader[r]) base[r] = atomicAdd(cursor + k, __popcll(group[r]));
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const bool live = c0 + threadIdx.x + r * SORT_T < c1;
+        const int b = __shfl(base[r], leader[r]);
+        const int64_t d = (int64_t)b + __popcll(group[r] & ((1ull << lane) - 1));
         if (live && d < P) {   // d >= P only with counts that do not match x (k_sort_verify reports it)
-            xs[d] = make_float4(u0, u1, u2, __int_as_float(t));
-            if constexpr (HP) ps[d] = make_float4(b0, b1, b2, 0.f);
-            if constexpr (HI) ids_out[d] = id;
+            xs[d] = make_float4(a0[r], a1[r], a2[r], __int_as_float(t[r]));
+            if constexpr (HP) ps[d] = make_float4(b0[r], b1[r], b2[r], 0.f);
+            if constexpr (HI) ids_out[d] = id[r];
         }
     }
 }
