@@ -63,7 +63,8 @@ typedef enum {
     PM_ERR_SIZE = -2,     /* workspace too small */
     PM_ERR_DEVICE = -3,   /* a HIP call failed */
     PM_ERR_OVERFLOW = -4, /* a density cell left the fixed-point range */
-    PM_ERR_NAN = -5,      /* a particle position or momentum became non-finite */
+    PM_ERR_NAN = -5,      /* a particle position or momentum became non-finite, or a
+                             cotangent passed to a reverse-mode call is */
     PM_ERR_STATE = -6     /* call not valid for this context */
 } pm_status;
 
@@ -321,7 +322,10 @@ pm_status pm_density_vjp(pm_ctx *ctx, const float *x, const float *dmesh, float 
 /* xbar += (d acc / d x)^T g, acc the force of pm_force at x and g [3][P] its
  * cotangent: the readout-derivative term plus the paint-derivative term
  * through the transpose of the gradient of the inverse Laplacian (which is
- * minus itself).  Uses the workspace mesh regions. */
+ * minus itself).  Uses the workspace mesh regions.  The cotangent is painted
+ * in int64 fixed point (a power-of-two unit set by max |g|), so the result
+ * is the same on every run and for any order of the particles.
+ * PM_ERR_NAN if any value of g is NaN or infinite; xbar is then untouched. */
 pm_status pm_force_vjp(pm_ctx *ctx, const float *x, const float *g, float *xbar, void *stream);
 
 /* Reverse mode of pm_step taken at positions x (the checkpoint: positions

@@ -131,18 +131,23 @@ __global__ __launch_bounds__(256) void k_paint_vec3(const float *__restrict__ x,
     }
 }
 
-// Largest |gscale g| over n values, as the bits of a non-negative float (their
-// order is the order of unsigned ints): a per-wavefront maximum, then one
-// atomicMax per wavefront on *out (zeroed by the caller).
+// Largest |gscale g| over count values, as the bits of a non-negative float,
+// atomicMax'ed into *out (zeroed by the caller).
 __global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ g, int64_t count, float gscale,
                                                 unsigned *out)
 {
-    float m = 0.f;
+    // The bits of |v| order like the values themselves (sign bit clear), with
+    // +inf above every finite value and NaN above +inf, so an integer maximum
+    // reports a NaN or an infinity anywhere in g.  One atomic per workgroup.
+    __shared__ unsigned wm[256 / 64];
+    unsigned m = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-        m = fmaxf(m, fabsf(gscale * g[i]));
+        m = max(m, __float_as_uint(fabsf(gscale * g[i])));
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+    for (int off = 32; off >= 1; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(out, max(max(wm[0], wm[1]), max(wm[2], wm[3])));
 }
 
 // One cotangent component in fixed point: Q(c) += llrint(S w_c gscale g_i)
@@ -284,7 +289,7 @@ hipError_t launch_paint_vec3(const float *x, int64_t P, const float *g, float gs
 
 hipError_t launch_absmax(const float *g, int64_t count, float gscale, unsigned *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_absmax, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, g, count, gscale, out);
+    hipLaunchKernelGGL(k_absmax, dim3(grid_for(count, 256, 1024)), dim3(256), 0, s, g, count, gscale, out);
     return hipGetLastError();
 }
 

@@ -397,7 +397,6 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
     pm_status st = paint_all(c, x, s);
     if (st == PM_OK) st = solve(c, c->ws.q, s);
     if (st != PM_OK) return st;
-    LAUNCH(pm::K_ADJOINT, pm::launch_readout_grad3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, xbar, s));
     // cotangent paint in fixed point, one component at a time through Q (free
     // after the solve): a unit of 1/S with S a power of two such that even all
     // particles' largest cotangent in one cell stays below 2^62, so the mesh
@@ -413,6 +412,8 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
     memcpy(&gm, &mbits, sizeof gm);
     if (!std::isfinite(gm)) return fail(PM_ERR_NAN, "a cotangent is not finite");
     const double S = gm > 0 ? ldexp(1.0, 61 - (int)ceil(log2((double)c->P * (double)gm))) : 1.0;
+    // a non-finite cotangent is reported before xbar is touched
+    LAUNCH(pm::K_ADJOINT, pm::launch_readout_grad3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, xbar, s));
     for (int d = 0; d < 3; d++) {
         float2 *Fd = F + d * cs;
         LAUNCH(pm::K_FILL, pm::launch_fill_i64(c->ws.q, (int64_t)n * n * n, s));

@@ -221,3 +221,24 @@ def test_force_vjp_bit_reproducible_and_order_independent(dev):
     back[:, pt] = xb3
     say("force VJP: repeat identical", True, "; permuted max |diff|", float((back - xb1).abs().max()))
     assert torch.equal(back, xb1)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_force_vjp_rejects_a_non_finite_cotangent(dev, bad):
+    """A NaN or infinite cotangent anywhere (here the last value of the last
+    component) is reported as PM_ERR_NAN before the fixed-point paint, whose
+    scale it would otherwise set; the call leaves xbar untouched."""
+    pm, cfg, ctx, _ = _setup("C1")
+    x32, _ = I.synthetic_state(cfg, seed=34)
+    P = x32.shape[1]
+    g32 = np.random.default_rng(35).standard_normal((3, P)).astype(np.float32)
+    g32[2, P - 1] = bad
+    x, g = torch.from_numpy(x32).to(dev), torch.from_numpy(g32).to(dev)
+    xb = torch.full_like(x, 7.0)
+    with pytest.raises(pm.PMError) as e:
+        pm.pm_force_vjp(ctx, x, g, xb)
+    assert e.value.status == pm.PM_ERR_NAN
+    assert bool((xb == 7.0).all())
+    g32[2, P - 1] = 0.0
+    pm.pm_force_vjp(ctx, x, torch.from_numpy(g32).to(dev), xb)   # the context is usable afterwards
+    assert bool(torch.isfinite(xb).all())
