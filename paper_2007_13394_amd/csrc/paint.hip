@@ -115,8 +115,9 @@ __global__ __launch_bounds__(256) void k_paint_tagged(const float *__restrict__ 
 // written once and read once by the transform).
 enum { PAINT_STORE = 0, PAINT_ADD = 1, PAINT_DELTA = 2 };
 // 512 threads, two particles each per round: the 33 KB of LDS allow four workgroups per CU, and eight
-// waves each hide the latency of the range, particle and store phases (18.2 -> 17.4 ms at C3 against
-// 256 threads with four particles each)
+// waves each hide the latency of the range, particle and store phases.  At C3 (2048^3) this takes
+// 16.7 ms against 18.6 ms for four particles per thread, 19.1 ms for 256 threads with four each and
+// 24.1 ms for 1024 threads with two; at 256^3 (19 M particles) the same order holds.
 constexpr int PAINT_T = 512, NRANGE = 20, NPT = 2;   // NPT particles per thread per round
 
 template <int MODE>
@@ -188,11 +189,20 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
         // a branch is joined with the other path's value, and the join waits
         // for it.  The empty asm takes every loaded value, so no load can be
         // sunk into the branch that uses it (one memory round trip per round).
-        float4 r0 = xs[idx[0]], r1 = xs[idx[1]];
-        asm volatile("" : "+v"(r0.x), "+v"(r0.y), "+v"(r0.z), "+v"(r0.w), "+v"(r1.x), "+v"(r1.y), "+v"(r1.z),
-                     "+v"(r1.w));
-        const float u0[NPT] = {r0.x, r1.x}, u1[NPT] = {r0.y, r1.y}, u2[NPT] = {r0.z, r1.z};
-        const int g[NPT] = {ok[0] ? __float_as_int(r0.w) : -1, ok[1] ? __float_as_int(r1.w) : -1};
+        float4 r[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; u++) r[u] = xs[idx[u]];
+#pragma unroll
+        for (int u = 0; u < NPT; u++) asm volatile("" : "+v"(r[u].x), "+v"(r[u].y), "+v"(r[u].z), "+v"(r[u].w));
+        float u0[NPT], u1[NPT], u2[NPT];
+        int g[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; u++) {
+            u0[u] = r[u].x;
+            u1[u] = r[u].y;
+            u2[u] = r[u].z;
+            g[u] = ok[u] ? __float_as_int(r[u].w) : -1;
+        }
 #pragma unroll
         for (int u = 0; u < NPT; u++) {
             if (!ok[u] || g[u] < lo || g[u] >= hi) continue;

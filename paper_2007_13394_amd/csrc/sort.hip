@@ -31,6 +31,9 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536LL * 16)
 // that each XCD owns a contiguous run of chunks (the scatter of a nearly
 // sorted state then writes whole cache lines from one L2).
 constexpr int SORT_T = 256, SORT_CH = SORT_T * 8;
+// particles per batch in the scatter: two keep it at 38 VGPRs; four and eight
+// (66, 114 VGPRs) gain nothing at 2048^3 and lose at 256^3 (lower occupancy)
+constexpr int SCATTER_SB = 2;
 
 
 __global__ __launch_bounds__(SORT_T) void k_sort_count(const float *__restrict__ x, int64_t P, int n, int *cnt)
@@ -143,11 +146,11 @@ __global__ void k_scan_add(int *out, int64_t n, const int *sums, int *out2)
 // Scatter into float4 records: one 16-byte store for the position and the
 // segment tag, one for the momentum, so a particle that moves far in the
 // order costs two stores instead of seven partial ones.  The optional arrays
-// are template flags.  A thread's eight particles are loaded up front, then
-// the eight cursor atomics are issued back to back, then the stores: two
-// memory round trips per chunk instead of two per particle.  The pointers do
-// not alias (caller arrays in, workspace records out).
-template <bool HP, bool HT, bool HI>
+// are template flags.  A thread takes its eight particles in batches of SB:
+// a batch's particles are loaded at once, then its cursor atomics are issued
+// back to back, then its stores (two memory round trips per batch).  The
+// pointers do not alias (caller arrays in, workspace records out).
+template <bool HP, bool HT, bool HI, int SB>
 __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const float *__restrict__ x,
                                               const float *__restrict__ p, const uint8_t *__restrict__ tag_in,
                                               int64_t P, int nseg, const int64_t *__restrict__ seg_off, int n,
@@ -155,53 +158,56 @@ __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const floa
                                               const uint32_t *__restrict__ ids_in, uint32_t *__restrict__ ids_out)
 {
     constexpr int NR = SORT_CH / SORT_T;
+    static_assert(NR % SB == 0, "whole batches");
     const int lane = threadIdx.x & 63;
-    // indices past the chunk are clamped to c0, a valid particle, and dropped
-    float a0[NR], a1[NR], a2[NR], b0[NR], b1[NR], b2[NR];
-    int t[NR];
-    uint32_t id[NR];
+    for (int r0 = 0; r0 < NR; r0 += SB) {
+        // indices past the chunk are clamped to c0, a valid particle, and dropped
+        float a0[SB], a1[SB], a2[SB], b0[SB], b1[SB], b2[SB];
+        int t[SB];
+        uint32_t id[SB];
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        const int64_t i = c0 + threadIdx.x + r * SORT_T, ic = i < c1 ? i : c0;
-        a0[r] = x[ic];
-        a1[r] = x[P + ic];
-        a2[r] = x[2 * P + ic];
-        if constexpr (HP) {
-            b0[r] = p[ic];
-            b1[r] = p[P + ic];
-            b2[r] = p[2 * P + ic];
-        } else {
-            b0[r] = b1[r] = b2[r] = 0.f;
+        for (int r = 0; r < SB; r++) {
+            const int64_t i = c0 + threadIdx.x + (r0 + r) * SORT_T, ic = i < c1 ? i : c0;
+            a0[r] = x[ic];
+            a1[r] = x[P + ic];
+            a2[r] = x[2 * P + ic];
+            if constexpr (HP) {
+                b0[r] = p[ic];
+                b1[r] = p[P + ic];
+                b2[r] = p[2 * P + ic];
+            } else {
+                b0[r] = b1[r] = b2[r] = 0.f;
+            }
+            if constexpr (HT) {
+                t[r] = tag_in[ic];
+            } else {   // canonical order: segment from the offsets
+                int g0 = 0;
+                for (int g = 1; g < nseg; g++) g0 += (ic >= seg_off[g]) ? 1 : 0;
+                t[r] = g0;
+            }
+            id[r] = 0;
+            if constexpr (HI) id[r] = ids_in[ic];
         }
-        if constexpr (HT) {
-            t[r] = tag_in[ic];
-        } else {   // canonical order: segment from the offsets
-            int g0 = 0;
-            for (int g = 1; g < nseg; g++) g0 += (ic >= seg_off[g]) ? 1 : 0;
-            t[r] = g0;
+        uint64_t group[SB];
+        int leader[SB], base[SB];
+#pragma unroll
+        for (int r = 0; r < SB; r++) {
+            const bool live = c0 + threadIdx.x + (r0 + r) * SORT_T < c1;
+            const int k = live ? tile_key(a0[r], a1[r], a2[r], n) : -1;
+            key_group(live, k, group[r], leader[r]);
+            base[r] = 0;
+            if (live && lane == leader[r]) base[r] = atomicAdd(cursor + k, __popcll(group[r]));
         }
-        id[r] = 0;
-        if constexpr (HI) id[r] = ids_in[ic];
-    }
-    uint64_t group[NR];
-    int leader[NR], base[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        const bool live = c0 + threadIdx.x + r * SORT_T < c1;
-        const int k = live ? tile_key(a0[r], a1[r], a2[r], n) : -1;
-        key_group(live, k, group[r], leader[r]);
-        base[r] = 0;
-        if (live && lane == leader[r]) base[r] = atomicAdd(cursor + k, __popcll(group[r]));
-    }
-#pragma unroll
-    for (int r = 0; r < NR; r++) {
-        const bool live = c0 + threadIdx.x + r * SORT_T < c1;
-        const int b = __shfl(base[r], leader[r]);
-        const int64_t d = (int64_t)b + __popcll(group[r] & ((1ull << lane) - 1));
-        if (live && d < P) {   // d >= P only with counts that do not match x (k_sort_verify reports it)
-            xs[d] = make_float4(a0[r], a1[r], a2[r], __int_as_float(t[r]));
-            if constexpr (HP) ps[d] = make_float4(b0[r], b1[r], b2[r], 0.f);
-            if constexpr (HI) ids_out[d] = id[r];
+        for (int r = 0; r < SB; r++) {
+            const bool live = c0 + threadIdx.x + (r0 + r) * SORT_T < c1;
+            const int b = __shfl(base[r], leader[r]);
+            const int64_t d = (int64_t)b + __popcll(group[r] & ((1ull << lane) - 1));
+            if (live && d < P) {   // d >= P only with counts that do not match x (k_sort_verify reports it)
+                xs[d] = make_float4(a0[r], a1[r], a2[r], __int_as_float(t[r]));
+                if constexpr (HP) ps[d] = make_float4(b0[r], b1[r], b2[r], 0.f);
+                if constexpr (HI) ids_out[d] = id[r];
+            }
         }
     }
 }
@@ -216,7 +222,7 @@ __global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict
     const int64_t c1 = c0 + SORT_CH < P ? c0 + SORT_CH : P;
     if (c0 >= c1) return;
 #define SCATTER(HP, HT, HI) \
-    scatter_chunk<HP, HT, HI>(c0, c1, x, p, tag_in, P, nseg, seg_off, n, cursor, xs, ps, ids_in, ids_out)
+    scatter_chunk<HP, HT, HI, SCATTER_SB>(c0, c1, x, p, tag_in, P, nseg, seg_off, n, cursor, xs, ps, ids_in, ids_out)
     if (p) {
         if (tag_in) {
             if (ids_in) SCATTER(true, true, true);
