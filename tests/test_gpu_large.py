@@ -177,3 +177,61 @@ def test_multi_mode_force_mesh(dev, n):
     gc.collect()
     torch.cuda.empty_cache()
     assert max(err) / rms < 5e-5
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_power_mesh_single_mode_closed_form(dev, n):
+    """Binned power (Sec. 3) of one real mode A cos(2 pi n.u / N) at full
+    size: the modes +n and -n of the full mesh land in bin floor(|n|), which
+    holds P n_modes = A^2 L^3 / 2; every other bin is empty up to float32
+    rounding of the transform."""
+    from paper_2007_13394_amd import pm
+    cfg = I.config("C3", n_mesh=n, n_sites=0, n_cdm=8)
+    ctx = pm.Ctx(pm.make_config(cfg))
+    nv = (-(3 * n // 10 + 1), 77, 13)
+    A, L = 0.25, cfg["box"]
+    d = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    i = torch.arange(n, device=dev, dtype=torch.float64)
+    for a in range(n):
+        ph = (2 * np.pi / n) * (nv[0] * a + nv[1] * i[:, None] + nv[2] * i[None, :])
+        d[a] = (A * torch.cos(ph)).to(torch.float32)
+    nb = 1024
+    k, pk, nm = pm.pm_power_mesh(ctx, d.reshape(-1), d.reshape(-1), nb)
+    b = int(np.floor(np.sqrt(sum(v * v for v in nv))))
+    expect = A * A / 2 * L ** 3
+    others = np.delete(np.abs(pk * nm), b)
+    say("power_mesh", n, "bin", b, "P n_modes / (A^2 L^3 / 2) - 1 =", pk[b] * nm[b] / expect - 1,
+        "largest other bin / expected", others.max() / expect)
+    assert abs(pk[b] * nm[b] / expect - 1) < 1e-5
+    assert others.max() < 1e-6 * expect
+    if n == nb:   # bins up to |n| < N cover every mode of the mesh once
+        assert nm.sum() == n ** 3 - 1
+    kf = 2 * np.pi / L
+    assert b * kf <= k[b] < (b + 1) * kf
+
+
+def test_power_particle_comb_closed_form_1024(dev):
+    """pm_power of particles at every even lattice point (spacing 2 cells):
+    the cloud-in-cell paint puts each on one cell, so delta is 7 on those
+    cells and -1 elsewhere, whose only nonzero modes are the 7 corners with
+    every n_d in {0, N/2} except k = 0, each |delta_k| = M: power L^3 per
+    mode, three modes in bin N/2, three in bin floor(sqrt(2) N/2), one in bin
+    floor(sqrt(3) N/2)."""
+    from paper_2007_13394_amd import pm
+    n = 1024
+    cfg = I.config("C3", n_mesh=n, n_cdm=n // 2, n_sites=0)
+    ctx = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_NO_SORT))
+    h = n // 2
+    x = torch.empty((3, ctx.P), dtype=torch.float32, device=dev)
+    j = torch.arange(ctx.P, device=dev, dtype=torch.int64)
+    x[0] = (2 * (j // (h * h))).to(torch.float32)
+    x[1] = (2 * ((j // h) % h)).to(torch.float32)
+    x[2] = (2 * (j % h)).to(torch.float32)
+    del j
+    L = cfg["box"]
+    k, pk, nm = pm.pm_power(ctx, x, 0, 1, nbins=2048)
+    tot = pk * nm / L ** 3
+    b1, b2, b3 = h, int(np.floor(np.sqrt(2) * h)), int(np.floor(np.sqrt(3) * h))
+    say("comb power, modes per bin at", (b1, b2, b3), ":", tot[b1], tot[b2], tot[b3])
+    assert abs(tot[b1] - 3) < 1e-5 and abs(tot[b2] - 3) < 1e-5 and abs(tot[b3] - 1) < 1e-5
+    assert np.abs(np.delete(tot, [b1, b2, b3])).max() < 1e-6
