@@ -31,15 +31,24 @@ HBM_PEAK_GBS = 8000.0
 # is reported only while the kernel's source file still has the hash it had
 # when the counters were taken.
 MEASURED_TRAFFIC = {
-    # profiles/c3_step_hbm_counters.md
-    "c2r_x0": {"bytes_per_launch": 69388687282, "source": "paper_2007_13394_amd/csrc/fft.hip",
-               "sha256_16": "711b9957287da624"},
-    "cols_inv": {"bytes_per_launch": 70539987324, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "711b9957287da624"},
-    "x0_green": {"bytes_per_launch": 103883518347, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "711b9957287da624"},
-    "readout_kick_drift": {"bytes_per_launch": 251680478099, "source": "paper_2007_13394_amd/csrc/particles.hip",
+    # profiles/c3_step_hbm_counters.md (averages over the profiled launches;
+    # the scatter's include the first sort from canonical order)
+    "c2r_x0": {"bytes_per_launch": 69390439143, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "effecff1b1096e79"},
+    "cols_inv": {"bytes_per_launch": 70562374765, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "effecff1b1096e79"},
+    "cols_fwd": {"bytes_per_launch": 70557425698, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "effecff1b1096e79"},
+    "x0_green": {"bytes_per_launch": 103884761380, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "effecff1b1096e79"},
+    "r2c_x0": {"bytes_per_launch": 69289622562, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "effecff1b1096e79"},
+    "readout_kick_drift": {"bytes_per_launch": 251600635499, "source": "paper_2007_13394_amd/csrc/particles.hip",
                            "sha256_16": "cc118edac7296599"},
+    "paint": {"bytes_per_launch": 54944914052, "source": "paper_2007_13394_amd/csrc/paint.hip",
+              "sha256_16": "6808153d780ceb72"},
+    "sort_scatter": {"bytes_per_launch": 80770064499, "source": "paper_2007_13394_amd/csrc/sort.hip",
+                     "sha256_16": "e91a7151ef9d4eb0"},
 }
 
 
@@ -59,21 +68,6 @@ def measured_traffic(kernel):
         if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_16"]:
             return None
     return rec["bytes_per_launch"]
-
-
-def copy_calibration():
-    """A plain device-to-device copy of exactly 1 GiB (reads 1 GiB, writes
-    1 GiB): the reference against which FETCH_SIZE and WRITE_SIZE are scaled
-    when this command runs under rocprofv3 --pmc."""
-    import torch
-    a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
-    a.fill_(1.0)
-    b = torch.empty_like(a)
-    torch.cuda.synchronize()
-    b.copy_(a)
-    torch.cuda.synchronize()
-    del a, b
-    torch.cuda.empty_cache()
 
 
 def model_bytes(P, n):
@@ -276,7 +270,7 @@ def main():
     from paper_2007_13394_amd import run as R
 
     if args.copy_calibration:
-        copy_calibration()
+        pm.copy_calibration()
         log("[bench] copy calibration: 1 GiB device-to-device copy done")
     cfg = I.config(args.config)
     n = cfg["n_mesh"]
@@ -336,6 +330,9 @@ def main():
         b = per_launch.get(k)
         if b:
             v["gbs"] = round(b / (v["avg_ms"] * 1e-3) / 1e9, 1)
+        t = measured_traffic(k) if args.config == "C3" else None
+        if t:
+            v["traffic_gb"] = round(t / 1e9, 2)
     ms_per_step = elapsed / K * 1e3
     value = P * K / elapsed
     out = {

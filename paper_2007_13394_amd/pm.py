@@ -421,3 +421,17 @@ def pm_power_mesh(ctx, da, db, nbins, compensate=False, stream=None):
                               _stream(stream)))
     return k, pk, nm
 
+
+def copy_calibration():
+    """A plain device-to-device copy of exactly 1 GiB (reads 1 GiB, writes
+    1 GiB): the reference against which the FETCH_SIZE and WRITE_SIZE
+    counters of the library's kernels are scaled when a command runs under
+    rocprofv3 --pmc."""
+    a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()

@@ -89,6 +89,16 @@ def reconstruct(cfg_name="C5", target_seed=301, iters=100, lr=0.01, pool=4, devi
 
 
 if __name__ == "__main__":
+    import argparse
     import json
     import sys
-    print(json.dumps(reconstruct(log=lambda *m: print(*m, file=sys.stderr, flush=True))), flush=True)
+    ap = argparse.ArgumentParser(description="reconstruct the initial modes of a seeded run from its final density")
+    ap.add_argument("--config", default="C5")
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration under rocprofv3 --pmc)")
+    a = ap.parse_args()
+    if a.copy_calibration:
+        pm.copy_calibration()
+    res = reconstruct(cfg_name=a.config, iters=a.iters, log=lambda *m: print(*m, file=sys.stderr, flush=True))
+    print(json.dumps(res), flush=True)
