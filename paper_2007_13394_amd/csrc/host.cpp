@@ -144,7 +144,7 @@ Layout layout(const pm_config &c)
         L.xs = off;
         off = align256(off + (size_t)(16 * P));
         L.ps = off;
-        off = align256(off + (size_t)(16 * P));
+        off = align256(off + (size_t)(12 * P));
         L.tags = off;
         off = align256(off + (size_t)P);
         L.ids = off;
@@ -583,7 +583,7 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
     c->nkeys = L.nkeys;
     if (L.nkeys > 0) {
         c->ws.xs = reinterpret_cast<float4 *>(b + L.xs);
-        c->ws.ps = reinterpret_cast<float4 *>(b + L.ps);
+        c->ws.ps = reinterpret_cast<pm::Mom3 *>(b + L.ps);
         c->ws.tags = reinterpret_cast<uint8_t *>(b + L.tags);
         c->ws.ids_tmp = reinterpret_cast<uint32_t *>(b + L.ids);
         c->ws.koff = reinterpret_cast<int *>(b + L.koff);

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(float *x, float *p, 
 constexpr int READOUT_T = 1024;
 
 __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__restrict__ xs,
-                                                                const float4 *__restrict__ ps, int64_t P,
+                                                                const Mom3 *__restrict__ ps, int64_t P,
                                                                 const int *__restrict__ koff,
                                                                 const float *__restrict__ F, int64_t rs,
                                                                 int64_t cs, int n, float kick, float drift,
@@ -138,7 +138,8 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__
     const int o0 = t0 * TILE, o1 = t1 * TILE, o2 = t2 * TILE;
     const int beg = koff[t * 8], end = koff[t * 8 + 8];
     int i = beg + threadIdx.x;
-    float4 ur = make_float4(0.f, 0.f, 0.f, 0.f), vr = ur;
+    float4 ur = make_float4(0.f, 0.f, 0.f, 0.f);
+    Mom3 vr{0.f, 0.f, 0.f};
     if (i < end) {
         ur = xs[i];
         vr = ps[i];
@@ -464,7 +465,7 @@ hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2
     return hipGetLastError();
 }
 
-hipError_t launch_readout_kd_tiles(const float4 *xs, const float4 *ps, int64_t P, const int *koff, const float2 *f,
+hipError_t launch_readout_kd_tiles(const float4 *xs, const Mom3 *ps, int64_t P, const int *koff, const float2 *f,
                                    int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
                                    float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag,
                                    int *cnt_next, hipStream_t s)

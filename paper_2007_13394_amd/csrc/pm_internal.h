@@ -105,6 +105,13 @@ enum { FLAG_OVERFLOW = 1, FLAG_NAN = 2, FLAG_STALE = 4 };
 // can be particles, independent of the fixed-point shift.
 constexpr long long GUARD_MIN_Q = -(1LL << 36);
 
+// A sorted momentum record: three floats, 12 bytes (no padding lane), moved
+// with one dwordx3 access.
+struct Mom3 {
+    float x, y, z;
+};
+static_assert(sizeof(Mom3) == 12, "packed momentum record");
+
 struct Workspace {
     char *base = nullptr;
     size_t bytes = 0;
@@ -117,7 +124,7 @@ struct Workspace {
     int64_t *seg_off = nullptr;  // device copy of the segment offsets (MAX_SEG + 1)
     int64_t *quanta = nullptr;   // device copy of the segment mass quanta (MAX_SEG)
     float4 *xs = nullptr;        // tile-sorted records (u0, u1, u2, segment tag as int bits) [P]
-    float4 *ps = nullptr;        // tile-sorted momenta (p0, p1, p2, 0) [P]
+    Mom3 *ps = nullptr;          // tile-sorted momenta (p0, p1, p2) [P], 12 bytes each
     uint8_t *tags = nullptr;     // segment tag per particle in the caller's current order [P]
     uint32_t *ids_tmp = nullptr; // tile-sorted ids [P]
     int *cnt = nullptr;          // counts per key (K + 1), then the scatter's cursors (aliases the F region)
@@ -343,7 +350,7 @@ hipError_t launch_paint_tiles_delta(const float4 *xs, const int *koff, const int
 hipError_t launch_sort_count(const float *x, int64_t P, int n, int *cnt, hipStream_t s);
 hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipStream_t s, int *out2 = nullptr);
 hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
-                               const int64_t *seg_off, int n, int *cursor, float4 *xs, float4 *ps,
+                               const int64_t *seg_off, int n, int *cursor, float4 *xs, Mom3 *ps,
                                const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s);
 // FLAG_STALE unless cursor[k] == koff[k + 1] for every key k < K.
 hipError_t launch_sort_verify(const int *cursor, const int *koff, int64_t K, int *flag, hipStream_t s);
@@ -356,7 +363,7 @@ hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2
                                      int64_t comp_stride, int n, float kick, float drift, int *flag,
                                      hipStream_t s);
 // cnt_next (optional): counts per sort key of the positions written, added to.
-hipError_t launch_readout_kd_tiles(const float4 *xs, const float4 *ps, int64_t P, const int *koff, const float2 *f,
+hipError_t launch_readout_kd_tiles(const float4 *xs, const Mom3 *ps, int64_t P, const int *koff, const float2 *f,
                                    int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
                                    float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag, int *cnt_next,
                                    hipStream_t s);

@@ -154,7 +154,7 @@ template <bool HP, bool HT, bool HI, int SB>
 __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const float *__restrict__ x,
                                               const float *__restrict__ p, const uint8_t *__restrict__ tag_in,
                                               int64_t P, int nseg, const int64_t *__restrict__ seg_off, int n,
-                                              int *cursor, float4 *__restrict__ xs, float4 *__restrict__ ps,
+                                              int *cursor, float4 *__restrict__ xs, Mom3 *__restrict__ ps,
                                               const uint32_t *__restrict__ ids_in, uint32_t *__restrict__ ids_out)
 {
     constexpr int NR = SORT_CH / SORT_T;
@@ -205,7 +205,7 @@ __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const floa
             const int64_t d = (int64_t)b + __popcll(group[r] & ((1ull << lane) - 1));
             if (live && d < P) {   // d >= P only with counts that do not match x (k_sort_verify reports it)
                 xs[d] = make_float4(a0[r], a1[r], a2[r], __int_as_float(t[r]));
-                if constexpr (HP) ps[d] = make_float4(b0[r], b1[r], b2[r], 0.f);
+                if constexpr (HP) ps[d] = Mom3{b0[r], b1[r], b2[r]};
                 if constexpr (HI) ids_out[d] = id[r];
             }
         }
@@ -215,7 +215,7 @@ __device__ __forceinline__ void scatter_chunk(int64_t c0, int64_t c1, const floa
 __global__ __launch_bounds__(SORT_T) void k_sort_scatter(const float *__restrict__ x, const float *__restrict__ p,
                                                          const uint8_t *__restrict__ tag_in, int64_t P, int nseg,
                                                          const int64_t *__restrict__ seg_off, int n, int *cursor,
-                                                         float4 *xs, float4 *ps, const uint32_t *ids_in,
+                                                         float4 *xs, Mom3 *ps, const uint32_t *ids_in,
                                                          uint32_t *ids_out)
 {
     const int64_t c0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * SORT_CH;
@@ -282,7 +282,7 @@ hipError_t launch_scan(const int *in, int *out, int64_t n, int *block_sums, hipS
 }
 
 hipError_t launch_sort_scatter(const float *x, const float *p, const uint8_t *tag_in, int64_t P, int nseg,
-                               const int64_t *seg_off, int n, int *cursor, float4 *xs, float4 *ps,
+                               const int64_t *seg_off, int n, int *cursor, float4 *xs, Mom3 *ps,
                                const uint32_t *ids_in, uint32_t *ids_out, hipStream_t s)
 {
     const int64_t nb = (P + SORT_CH - 1) / SORT_CH;
