@@ -174,6 +174,64 @@ __global__ __launch_bounds__(256) void k_paint_q1(const float *__restrict__ x, i
     }
 }
 
+// The same integers by 16^3 tile, from the tile-sorted records (positions
+// xs, cotangent components vals): one workgroup per tile sums, in LDS, the
+// corners of its own particles and of the 19 neighbour ranges whose face
+// flags say a +1 corner crosses in, then writes the tile once (no zero fill,
+// no global atomics).  Each corner value is formed exactly as in k_paint_q1.
+constexpr int PQT = 512;
+__global__ __launch_bounds__(PQT) void k_paint_q1_tiles(const float4 *__restrict__ xs, const Mom3 *__restrict__ vals,
+                                                       int comp, const int *__restrict__ koff, float gscale, double S,
+                                                       int n, unsigned long long *Q)
+{
+    __shared__ unsigned long long acc[TILE * TILE * TILE];
+    __shared__ int rbeg[NRANGE], rpre[NRANGE + 1];
+    const int nt = n / TILE, mask = n - 1;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int t2 = (int)morton_compact((unsigned)t), t1 = (int)morton_compact((unsigned)t >> 1),
+              t0 = (int)morton_compact((unsigned)t >> 2);
+    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PQT) acc[i] = 0;
+    tile_ranges(koff, t, t0, t1, t2, nt, rbeg, rpre);
+    const int total = rpre[NRANGE];
+    const int o[3] = {t0 * TILE, t1 * TILE, t2 * TILE};
+    for (int k = threadIdx.x; k < total; k += PQT) {
+        const int idx = tile_range_index(k, rbeg, rpre);
+        const float4 r = xs[idx];
+        const Mom3 g = vals[idx];
+        const float gd = comp == 0 ? g.x : (comp == 1 ? g.y : g.z);
+        const double v = (double)(gscale * gd) * S;
+        const float u[3] = {r.x, r.y, r.z};
+        float w[3][2];
+        int l[3][2];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const float f = floorf(u[d]);
+            const int i = (int)f;
+            w[d][1] = u[d] - f;
+            w[d][0] = 1.f - w[d][1];
+            l[d][0] = ((i & mask) - o[d]) & mask;
+            l[d][1] = (((i + 1) & mask) - o[d]) & mask;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    if (l[0][a] < TILE && l[1][b] < TILE && l[2][e] < TILE) {
+                        const float wc = (w[0][a] * w[1][b]) * w[2][e];
+                        const long long iq = (long long)__builtin_rint((double)wc * v);
+                        atomicAdd(&acc[(l[0][a] * TILE + l[1][b]) * TILE + l[2][e]], (unsigned long long)iq);
+                    }
+                }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PQT) {
+        const int a = i / (TILE * TILE), b = (i / TILE) % TILE, e = i % TILE;
+        Q[((int64_t)(o[0] + a) * n + (o[1] + b)) * n + (o[2] + e)] = acc[i];
+    }
+}
+
 // psi(k) = -coef sum_d i k_d / k^2 G_d(k) into field 0 (natural-order half
 // spectra, row stride nhp, field stride fs); zero at k = 0 and, per term, on
 // the Nyquist plane of component d.
@@ -298,6 +356,16 @@ hipError_t launch_paint_q1(const float *x, int64_t P, const float *gd, float gsc
 {
     hipLaunchKernelGGL(k_paint_q1, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P, gd, gscale, S, n,
                        reinterpret_cast<unsigned long long *>(Q));
+    return hipGetLastError();
+}
+
+hipError_t launch_paint_q1_tiles(const float4 *xs, const Mom3 *vals, int comp, const int *koff, float gscale,
+                                 double S, int n, int64_t *Q, hipStream_t s)
+{
+    const int nt = n / TILE;
+    if (nt < 2 || comp < 0 || comp > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_paint_q1_tiles, dim3((unsigned)(nt * nt * nt)), dim3(PQT), 0, s, xs, vals, comp, koff, gscale,
+                       S, n, reinterpret_cast<unsigned long long *>(Q));
     return hipGetLastError();
 }
 

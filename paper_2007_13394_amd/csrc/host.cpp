@@ -414,10 +414,30 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
     const double S = gm > 0 ? ldexp(1.0, 61 - (int)ceil(log2((double)c->P * (double)gm))) : 1.0;
     // a non-finite cotangent is reported before xbar is touched
     LAUNCH(pm::K_ADJOINT, pm::launch_readout_grad3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, xbar, s));
+    // With the tile-sort workspace, the particles and their cotangents are
+    // sorted into the record arrays (the caller's order is untouched; the
+    // count scratch aliases the force meshes, dead after the readout term)
+    // and each component is painted by tile; otherwise with global atomics.
+    // Both form the same integers.
+    const bool tiles = c->nkeys > 0;
+    if (tiles) {
+        const int64_t K = c->nkeys;
+        LAUNCH(pm::K_FILL, pm::launch_fill_i32(c->ws.cnt, K + 1, s));
+        LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, c->ws.cnt, s));
+        LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt, c->ws.koff, K + 1, c->ws.bsum, s, c->ws.cnt));
+        LAUNCH(pm::K_SORT_SCATTER,
+               pm::launch_sort_scatter(x, g, c->permuted ? c->ws.tags : nullptr, c->P, c->nseg, c->ws.seg_off, c->n,
+                                       c->ws.cnt, c->ws.xs, c->ws.ps, nullptr, nullptr, s));
+    }
     for (int d = 0; d < 3; d++) {
         float2 *Fd = F + d * cs;
-        LAUNCH(pm::K_FILL, pm::launch_fill_i64(c->ws.q, (int64_t)n * n * n, s));
-        LAUNCH(pm::K_ADJOINT, pm::launch_paint_q1(x, c->P, g + d * c->P, (float)gscale, S, n, c->ws.q, s));
+        if (tiles) {
+            LAUNCH(pm::K_ADJOINT, pm::launch_paint_q1_tiles(c->ws.xs, c->ws.ps, d, c->ws.koff, (float)gscale, S, n,
+                                                            c->ws.q, s));
+        } else {
+            LAUNCH(pm::K_FILL, pm::launch_fill_i64(c->ws.q, (int64_t)n * n * n, s));
+            LAUNCH(pm::K_ADJOINT, pm::launch_paint_q1(x, c->P, g + d * c->P, (float)gscale, S, n, c->ws.q, s));
+        }
         LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, c->ws.q, n, Fd, nhp, n2, 1.0 / S, 0.0, c->ws.tw, unused_flag, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, nhp, n * nhp, n, ncb, c->ws.tw, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, Fd, n * nhp, nhp, n, ncb, c->ws.tw, s));

@@ -118,7 +118,7 @@ enum { PAINT_STORE = 0, PAINT_ADD = 1, PAINT_DELTA = 2 };
 // waves each hide the latency of the range, particle and store phases.  At C3 (2048^3) this takes
 // 16.7 ms against 18.6 ms for four particles per thread, 19.1 ms for 256 threads with four each and
 // 24.1 ms for 1024 threads with two; at 256^3 (19 M particles) the same order holds.
-constexpr int PAINT_T = 512, NRANGE = 20, NPT = 2;   // NPT particles per thread per round
+constexpr int PAINT_T = 512, NPT = 2;   // NPT particles per thread per round
 
 template <int MODE>
 __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restrict__ xs,
@@ -139,36 +139,7 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
               t0 = (int)morton_compact((unsigned)t >> 2);
     for (int i = threadIdx.x; i < TILE * TILE * TILE; i += PAINT_T) acc[i] = 0;
     for (int i = threadIdx.x; i < nseg; i += PAINT_T) qtab[i] = quanta[i];
-    // range 0: the own tile (all flags); ranges 1..19: lower neighbour e != 0,
-    // flags f containing e, in (e, f) order
-    if (threadIdx.x < 64) {
-        const int e = threadIdx.x >> 3, f = threadIdx.x & 7;
-        int slot = -1, b = 0, len = 0;
-        if (e == 0 && f == 0) {
-            slot = 0;
-            b = koff[t * 8];
-            len = koff[t * 8 + 8] - b;
-        } else if (e != 0 && (f & e) == e) {
-            slot = 1;
-            for (int ee = 1; ee < e; ee++) slot += 1 << (3 - __popc(ee));
-            for (int ff = 0; ff < f; ff++) slot += ((ff & e) == e) ? 1 : 0;
-            const int s0 = (t0 - (e & 1) + nt) % nt, s1 = (t1 - ((e >> 1) & 1) + nt) % nt,
-                      s2 = (t2 - ((e >> 2) & 1) + nt) % nt;
-            const int tn = tile_index(s0, s1, s2);
-            b = koff[tn * 8 + f];
-            len = koff[tn * 8 + f + 1] - b;
-        }
-        if (slot >= 0) {
-            rbeg[slot] = b;
-            rpre[slot + 1] = len;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        rpre[0] = 0;
-        for (int r = 1; r <= NRANGE; r++) rpre[r] += rpre[r - 1];
-    }
-    __syncthreads();
+    tile_ranges(koff, t, t0, t1, t2, nt, rbeg, rpre);
     const int total = rpre[NRANGE];
     const int ox = t0 * TILE, oy = t1 * TILE, oz = t2 * TILE;
     for (int k0 = threadIdx.x; k0 < total; k0 += NPT * PAINT_T) {
@@ -178,11 +149,7 @@ __global__ __launch_bounds__(PAINT_T) void k_paint_tiles(const float4 *__restric
         for (int u = 0; u < NPT; u++) {
             const int k = k0 + u * PAINT_T;
             ok[u] = k < total;
-            int r = 0;   // last range whose prefix is <= k
-#pragma unroll
-            for (int step = 16; step >= 1; step >>= 1)
-                if (r + step < NRANGE && rpre[r + step] <= k) r += step;
-            idx[u] = ok[u] ? rbeg[r] + (k - rpre[r]) : 0;
+            idx[u] = ok[u] ? tile_range_index(k, rbeg, rpre) : 0;
         }
         // All loads unconditional (idx 0, a valid particle whenever the loop
         // runs, stands in past the end) and issued back to back: a load under

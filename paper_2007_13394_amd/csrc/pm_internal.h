@@ -75,6 +75,56 @@ __device__ __forceinline__ int tile_key(float u0, float u1, float u2, int n)
     return t * 8 + f;
 }
 
+// Particle ranges of a tile paint: range 0 is the tile's own particles (all
+// flags), ranges 1..19 the particles of the lower neighbour e != 0 (bit d of
+// e: one tile lower along axis d) whose face flags f contain e, in (e, f)
+// order: exactly those with a +1 corner inside this tile.  rbeg[r] is the
+// first sorted index of range r, rpre the exclusive prefix of the lengths
+// (rpre[NRANGE] = total).  Called by the whole workgroup; ends with a barrier.
+constexpr int NRANGE = 20;
+__device__ __forceinline__ void tile_ranges(const int *__restrict__ koff, int t, int t0, int t1, int t2, int nt,
+                                            int *rbeg, int *rpre)
+{
+    if (threadIdx.x < 64) {
+        const int e = threadIdx.x >> 3, f = threadIdx.x & 7;
+        int slot = -1, b = 0, len = 0;
+        if (e == 0 && f == 0) {
+            slot = 0;
+            b = koff[t * 8];
+            len = koff[t * 8 + 8] - b;
+        } else if (e != 0 && (f & e) == e) {
+            slot = 1;
+            for (int ee = 1; ee < e; ee++) slot += 1 << (3 - __popc(ee));
+            for (int ff = 0; ff < f; ff++) slot += ((ff & e) == e) ? 1 : 0;
+            const int s0 = (t0 - (e & 1) + nt) % nt, s1 = (t1 - ((e >> 1) & 1) + nt) % nt,
+                      s2 = (t2 - ((e >> 2) & 1) + nt) % nt;
+            const int tn = tile_index(s0, s1, s2);
+            b = koff[tn * 8 + f];
+            len = koff[tn * 8 + f + 1] - b;
+        }
+        if (slot >= 0) {
+            rbeg[slot] = b;
+            rpre[slot + 1] = len;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        rpre[0] = 0;
+        for (int r = 1; r <= NRANGE; r++) rpre[r] += rpre[r - 1];
+    }
+    __syncthreads();
+}
+
+// Sorted index of the k-th particle (0 <= k < rpre[NRANGE]) of the ranges.
+__device__ __forceinline__ int tile_range_index(int k, const int *rbeg, const int *rpre)
+{
+    int r = 0;   // last range whose prefix is <= k
+#pragma unroll
+    for (int step = 16; step >= 1; step >>= 1)
+        if (r + step < NRANGE && rpre[r + step] <= k) r += step;
+    return rbeg[r] + (k - rpre[r]);
+}
+
 // Lanes of the wavefront that share this lane's key: the mask and its
 // lowest lane (ballot loop, no memory traffic).
 __device__ __forceinline__ void key_group(bool live, int k, uint64_t &group, int &leader)
@@ -287,6 +337,8 @@ hipError_t launch_paint_vec3(const float *x, int64_t P, const float *g, float gs
 // max |gscale g| over count values into *out as float bits (zero *out first).
 hipError_t launch_absmax(const float *g, int64_t count, float gscale, unsigned *out, hipStream_t s);
 // Q (int64 [N]^3, added to) += llrint(S w gscale g_d) per particle and corner.
+hipError_t launch_paint_q1_tiles(const float4 *xs, const Mom3 *vals, int comp, const int *koff, float gscale,
+                                 double S, int n, int64_t *Q, hipStream_t s);
 hipError_t launch_paint_q1(const float *x, int64_t P, const float *gd, float gscale, double S, int n, int64_t *Q,
                            hipStream_t s);
 hipError_t launch_green_adj(float2 *F, int64_t nhp, int64_t fs, int n, double coef, hipStream_t s);
