@@ -394,7 +394,27 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
     const int ncb = (int)(nhp / pm::TILE_W);
     float2 *F = c->ws.f;
     float *Fr = reinterpret_cast<float *>(F);
-    pm_status st = paint_all(c, x, s);
+    // With the tile-sort workspace, the particles and their cotangents are
+    // first sorted into the record arrays (the caller's order is untouched;
+    // the count scratch aliases the F region, written only by the solve that
+    // follows): the density and each cotangent component are then painted
+    // by tile.  Otherwise both use global atomics.  Either way the integers
+    // are the same.
+    const bool tiles = c->nkeys > 0;
+    pm_status st = PM_OK;
+    if (tiles) {
+        const int64_t K = c->nkeys;
+        LAUNCH(pm::K_FILL, pm::launch_fill_i32(c->ws.cnt, K + 1, s));
+        LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, c->ws.cnt, s));
+        LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt, c->ws.koff, K + 1, c->ws.bsum, s, c->ws.cnt));
+        LAUNCH(pm::K_SORT_SCATTER,
+               pm::launch_sort_scatter(x, g, c->permuted ? c->ws.tags : nullptr, c->P, c->nseg, c->ws.seg_off, c->n,
+                                       c->ws.cnt, c->ws.xs, c->ws.ps, nullptr, nullptr, s));
+        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, 0, c->nseg, c->n,
+                                                   c->ws.q, s));
+    } else {
+        st = paint_all(c, x, s);
+    }
     if (st == PM_OK) st = solve(c, c->ws.q, s);
     if (st != PM_OK) return st;
     // cotangent paint in fixed point, one component at a time through Q (free
@@ -414,21 +434,6 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
     const double S = gm > 0 ? ldexp(1.0, 61 - (int)ceil(log2((double)c->P * (double)gm))) : 1.0;
     // a non-finite cotangent is reported before xbar is touched
     LAUNCH(pm::K_ADJOINT, pm::launch_readout_grad3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, xbar, s));
-    // With the tile-sort workspace, the particles and their cotangents are
-    // sorted into the record arrays (the caller's order is untouched; the
-    // count scratch aliases the force meshes, dead after the readout term)
-    // and each component is painted by tile; otherwise with global atomics.
-    // Both form the same integers.
-    const bool tiles = c->nkeys > 0;
-    if (tiles) {
-        const int64_t K = c->nkeys;
-        LAUNCH(pm::K_FILL, pm::launch_fill_i32(c->ws.cnt, K + 1, s));
-        LAUNCH(pm::K_SORT_COUNT, pm::launch_sort_count(x, c->P, c->n, c->ws.cnt, s));
-        LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt, c->ws.koff, K + 1, c->ws.bsum, s, c->ws.cnt));
-        LAUNCH(pm::K_SORT_SCATTER,
-               pm::launch_sort_scatter(x, g, c->permuted ? c->ws.tags : nullptr, c->P, c->nseg, c->ws.seg_off, c->n,
-                                       c->ws.cnt, c->ws.xs, c->ws.ps, nullptr, nullptr, s));
-    }
     for (int d = 0; d < 3; d++) {
         float2 *Fd = F + d * cs;
         if (tiles) {
