@@ -33,22 +33,22 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     # profiles/c3_step_hbm_counters.md (averages over the profiled launches;
     # the scatter's include the first sort from canonical order)
-    "c2r_x0": {"bytes_per_launch": 69390439143, "source": "paper_2007_13394_amd/csrc/fft.hip",
+    "c2r_x0": {"bytes_per_launch": 69389447263, "source": "paper_2007_13394_amd/csrc/fft.hip",
                "sha256_16": "effecff1b1096e79"},
-    "cols_inv": {"bytes_per_launch": 70562374765, "source": "paper_2007_13394_amd/csrc/fft.hip",
+    "cols_inv": {"bytes_per_launch": 70555279954, "source": "paper_2007_13394_amd/csrc/fft.hip",
                  "sha256_16": "effecff1b1096e79"},
-    "cols_fwd": {"bytes_per_launch": 70557425698, "source": "paper_2007_13394_amd/csrc/fft.hip",
+    "cols_fwd": {"bytes_per_launch": 70562707400, "source": "paper_2007_13394_amd/csrc/fft.hip",
                  "sha256_16": "effecff1b1096e79"},
-    "x0_green": {"bytes_per_launch": 103884761380, "source": "paper_2007_13394_amd/csrc/fft.hip",
+    "x0_green": {"bytes_per_launch": 103884628287, "source": "paper_2007_13394_amd/csrc/fft.hip",
                  "sha256_16": "effecff1b1096e79"},
-    "r2c_x0": {"bytes_per_launch": 69289622562, "source": "paper_2007_13394_amd/csrc/fft.hip",
+    "r2c_x0": {"bytes_per_launch": 69292611392, "source": "paper_2007_13394_amd/csrc/fft.hip",
                "sha256_16": "effecff1b1096e79"},
-    "readout_kick_drift": {"bytes_per_launch": 251600635499, "source": "paper_2007_13394_amd/csrc/particles.hip",
-                           "sha256_16": "cc118edac7296599"},
-    "paint": {"bytes_per_launch": 54944914052, "source": "paper_2007_13394_amd/csrc/paint.hip",
-              "sha256_16": "6808153d780ceb72"},
-    "sort_scatter": {"bytes_per_launch": 80770064499, "source": "paper_2007_13394_amd/csrc/sort.hip",
-                     "sha256_16": "e91a7151ef9d4eb0"},
+    "readout_kick_drift": {"bytes_per_launch": 236309479374, "source": "paper_2007_13394_amd/csrc/particles.hip",
+                           "sha256_16": "831cd1c301e74525"},
+    "paint": {"bytes_per_launch": 54965991753, "source": "paper_2007_13394_amd/csrc/paint.hip",
+              "sha256_16": "82f0a8b345f2e4e7"},
+    "sort_scatter": {"bytes_per_launch": 77639712518, "source": "paper_2007_13394_amd/csrc/sort.hip",
+                     "sha256_16": "94773051a338481b"},
 }
 
 
