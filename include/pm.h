@@ -322,9 +322,12 @@ pm_status pm_density_vjp(pm_ctx *ctx, const float *x, const float *dmesh, float 
 /* xbar += (d acc / d x)^T g, acc the force of pm_force at x and g [3][P] its
  * cotangent: the readout-derivative term plus the paint-derivative term
  * through the transpose of the gradient of the inverse Laplacian (which is
- * minus itself).  Uses the workspace mesh regions.  The cotangent is painted
- * in int64 fixed point (a power-of-two unit set by max |g|), so the result
- * is the same on every run and for any order of the particles.
+ * minus itself).  Uses the workspace mesh regions; where the configuration
+ * tile-sorts (N >= 32, P < 2^31) it also sorts x and g into the workspace's
+ * record arrays and paints the density and the cotangent by tile (the
+ * caller's arrays keep their order).  The cotangent is painted in int64 fixed
+ * point (a power-of-two unit set by max |g|), so the result is the same on
+ * every run and for any order of the particles.
  * PM_ERR_NAN if any value of g is NaN or infinite; xbar is then untouched. */
 pm_status pm_force_vjp(pm_ctx *ctx, const float *x, const float *g, float *xbar, void *stream);
 
@@ -332,7 +335,9 @@ pm_status pm_force_vjp(pm_ctx *ctx, const float *x, const float *g, float *xbar,
  * before the step) with the same four scale factors.  On entry xbar, pbar
  * hold the cotangents of the positions and momenta after the step; on exit,
  * those of the positions and momenta before it (updated in place):
- * pbar += drift xbar, then xbar += kick (dF/dx)^T pbar. */
+ * pbar += drift xbar, then xbar += kick (dF/dx)^T pbar.  PM_ERR_NAN if a
+ * resulting pbar value is NaN or infinite (pbar then holds the drift term
+ * and xbar is untouched). */
 pm_status pm_step_vjp(pm_ctx *ctx, const float *x, double a_force, double a_kick0, double a_kick1,
                       double a_drift1, float *xbar, float *pbar, void *stream);
 
