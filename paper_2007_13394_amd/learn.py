@@ -9,7 +9,7 @@ side), started from seeded white noise: at every `snap_every`-th force
 evaluation the particle positions and the fine-mesh forces are kept, both
 rescaled to coarse-mesh units (positions / 4, forces / 4: a force in grid
 units scales with the number of cells per side for the same physical force).
-The network is trained by force matching on the coarse mesh, and judged by
+The network is trained by force matching on the coarse mesh, and evaluated by
 running coarse learned and plain simulations and a fine plain simulation from
 a held-out seed and comparing their power spectra at the end, all painted on
 the coarse mesh.
@@ -225,7 +225,7 @@ def calibrate(cc, seeds, fine_x, theta, rounds=48, power=0.3, fit_steps=1000, de
     k, nm = Pf[0][0], Pf[0][2]
     sel = (nm > 0) & (k > 0)
     kt = k[sel] / kN
-    judged = kt < 0.5
+    in_range = kt < 0.5
     a_fit = sorted(set([c[0] for c in _calls(cc)][::3] + [1.0]))
     kt_b = np.arange(NET_NB_TABLE) * np.sqrt(3.0) / (NET_NB_TABLE - 1)
     lnPf = np.mean([np.log(np.maximum(pf[sel], 1e-30)) for (_, pf, _) in Pf], axis=0)
@@ -240,7 +240,7 @@ def calibrate(cc, seeds, fine_x, theta, rounds=48, power=0.3, fit_steps=1000, de
             _, pl, _ = _spectrum(ana, x)
             lnP.append(np.log(np.maximum(pl[sel], 1e-30)))
         lnR = lnPf - np.mean(lnP, axis=0)
-        err = float(np.max(np.abs(np.exp(-lnR[judged]) - 1.0)))
+        err = float(np.max(np.abs(np.exp(-lnR[in_range]) - 1.0)))
         hist.append(err)
         if err < best[0]:
             best = (err, theta.clone())
@@ -257,7 +257,7 @@ def calibrate(cc, seeds, fine_x, theta, rounds=48, power=0.3, fit_steps=1000, de
     return hist
 
 
-def judge(coarse_name, fine_name, train_seeds, test_seeds, snap_every=5, iters=400, lr=2e-3, device="cuda",
+def evaluate(coarse_name, fine_name, train_seeds, test_seeds, snap_every=5, iters=400, lr=2e-3, device="cuda",
           log=print, calib_rounds=48, calib_seeds=None):
     """Train the network on fine-mesh force pairs (force matching), then
     calibrate its radial filter on fine-mesh spectra of the calibration
@@ -420,7 +420,7 @@ if __name__ == "__main__":
     import argparse
     import json
     import sys
-    ap = argparse.ArgumentParser(description="train and judge the learned force correction")
+    ap = argparse.ArgumentParser(description="train, calibrate and evaluate the learned force correction")
     ap.add_argument("--time-steps", type=int, default=0,
                     help="only time this many learned and plain steps on the coarse workload")
     ap.add_argument("--coarse", default="C4_coarse")
@@ -436,7 +436,7 @@ if __name__ == "__main__":
     if a.time_steps:
         print(json.dumps(dict(time_steps(a.coarse, a.time_steps), workload=a.coarse)), flush=True)
         sys.exit(0)
-    res = judge(a.coarse, a.fine, [int(s) for s in a.train_seeds.split(",")],
+    res = evaluate(a.coarse, a.fine, [int(s) for s in a.train_seeds.split(",")],
                 [int(s) for s in a.test_seeds.split(",")], a.snap_every, a.iters,
                 a.lr, log=lambda *m: print(*m, file=sys.stderr, flush=True),
                 calib_seeds=[int(s) for s in a.calib_seeds.split(",")])

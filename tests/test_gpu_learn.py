@@ -20,7 +20,7 @@ def say(*a):
 
 def test_training_gain_on_held_out_seed(dev):
     from paper_2007_13394_amd import learn
-    res = learn.judge("C4s_coarse", "C4s_fine", [151, 152, 153], 160, snap_every=2, iters=200,
+    res = learn.evaluate("C4s_coarse", "C4s_fine", [151, 152, 153], 160, snap_every=2, iters=200,
                       log=lambda *m: say(*m), calib_rounds=4)
     fl, pk = res["force_loss"], res["pk_max_rel_err"]
     say("force loss plain/learned (train)", fl["plain_train"], fl["learned_train"])
