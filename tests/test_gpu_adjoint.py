@@ -93,6 +93,44 @@ def test_step_vjp_refuses_sorted_context(dev):
     assert e.value.status == pm.PM_ERR_STATE
 
 
+def test_force_vjp_on_a_sorted_context_vs_oracle(dev):
+    """pm_force_vjp on a tile-sorting context after two sorted steps: the
+    particles are permuted and carry segment tags, which the VJP's internal
+    sort and its density-derivative term take from the context.  Mapped back
+    to canonical order by the attached ids, the result matches the oracle's
+    VJP at the same positions, and the caller's arrays keep their order."""
+    from paper_2007_13394_amd import pm
+    cfg = I.config("C5")
+    sim = O.make_sim(cfg)
+    ctx = pm.Ctx(pm.make_config(cfg))
+    assert ctx.sorts
+    x32, p32 = I.synthetic_state(cfg, seed=36)
+    P = ctx.P
+    ids = torch.arange(P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(ctx, ids)
+    x, p = torch.from_numpy(x32).to(dev), torch.from_numpy(p32).to(dev)
+    pm.pm_step(ctx, x, p, 0.406, 0.3565, 0.4555, 0.505)
+    pm.pm_step(ctx, x, p, 0.505, 0.4555, 0.5545, 0.604)
+    order = ids.cpu().numpy().astype(np.int64)
+    assert not np.array_equal(order, np.arange(P))
+    g32 = np.random.default_rng(37).standard_normal((3, P)).astype(np.float32)
+    g = torch.from_numpy(g32).to(dev)              # cotangent of particle order[j] at slot j
+    x_before = x.clone()
+    xb = torch.zeros_like(x)
+    pm.pm_force_vjp(ctx, x, g, xb)
+    assert torch.equal(x, x_before) and torch.equal(ids.cpu(), torch.from_numpy(order.astype(np.int32)))
+    inv = np.empty(P, dtype=np.int64)
+    inv[order] = np.arange(P)
+    xc = x.cpu().numpy()[:, inv].astype(np.float64)   # canonical order
+    gc_ = g32[:, inv].astype(np.float64)
+    ref = O.force_vjp(sim, np.ascontiguousarray(xc), np.ascontiguousarray(gc_))
+    got = xb.cpu().numpy()[:, inv]
+    e = rel_l2(got, ref)
+    say("force vjp on a sorted context: rel L2", e)
+    pm.pm_attach_ids(ctx, None)
+    assert e < TOL
+
+
 @pytest.mark.parametrize("name", ["C5_fd16", "C5_fd32", "C5"])
 def test_ic_vjp_vs_oracle(dev, name):
     pm, cfg, ctx, sim = _setup(name)
