@@ -404,8 +404,8 @@ __global__ __launch_bounds__(256) void k_conv3_fwd(const uint16_t *__restrict__ 
 // ---- inference path: no pre-activations kept, a1 never leaves LDS
 // conv1 + conv2 on v_mfma_f32_16x16x32_bf16 (K = 32; lane l holds
 // A[row l % 16][k 8 (l / 16) + j], B[k 8 (l / 16) + j][col l % 16] and
-// D[row 4 (l / 16) + r][col l % 16]).  The 16 x 8 x 4 output tile of conv2
-// needs a1 on the tile and its one-voxel halo (C2HALO voxels); conv1 computes
+// D[row 4 (l / 16) + r][col l % 16]).  The 16 x 8 x IZ output tile of conv2
+// needs a1 on the tile and its one-voxel halo (IHALO voxels); conv1 computes
 // those from delta on a two-voxel halo staged in LDS as BF16, one MFMA per 16
 // halo voxels: D[co][vox] = W1[co][tap] U[tap][vox] over 32 taps (27 real,
 // weights zero past 26).  a1 sits in LDS as two planes of 8 channels (16 bytes
@@ -413,8 +413,15 @@ __global__ __launch_bounds__(256) void k_conv3_fwd(const uint16_t *__restrict__ 
 // takes two taps per MFMA: k = 8 kg + j is tap 2 p + kg / 2, channel
 // 8 (kg % 2) + j, so 14 MFMAs cover 27 taps (the 28th has zero weights); the
 // 14 weight fragments live in registers.  Only a2 (BF16) is written.
-constexpr int U1X = C2X + 4, U1Y = C2Y + 4, U1Z = C2Z + 4, U1N = U1X * U1Y * U1Z;
-constexpr int NG1 = (C2HALO + 15) / 16, NPAIR = 14;
+#ifndef INF_Z
+#define INF_Z 8
+#endif
+// Inference tile: 16 x 8 x IZ outputs on IZ wavefronts (one per z plane of
+// conv2's output); the deeper the tile, the less of conv1's two-voxel halo is
+// recomputed (2.1x the tile's voxels at IZ = 4, 1.76x at IZ = 8).
+constexpr int IZ = INF_Z, INF_T = 64 * IZ, IHZ = IZ + 2, IHALO = C2HX * C2HY * IHZ;
+constexpr int U1X = C2X + 4, U1Y = C2Y + 4, U1Z = IZ + 4, U1N = U1X * U1Y * U1Z;
+constexpr int NG1 = (IHALO + 15) / 16, NPAIR = 14;
 // Inference weights repacked once per call (byte offsets in wpk): conv2 as
 // MFMA A fragments [pair][co][kg][8] BF16, conv1 [co][32 taps] BF16, conv3
 // [t][ci] BF16.
@@ -446,18 +453,19 @@ __device__ __forceinline__ int x_off(int t) { return ((t / 9) * C2HY + (t / 3) %
 // SRC int64_t: the fixed-point density, delta = q qs - 1 formed here; SRC
 // float: the density contrast as the tile paint stores it (the same value).
 template <typename SRC>
-__global__ __launch_bounds__(256) void k_cnn12_inf(const SRC *__restrict__ q, double qs, int n,
+__global__ __launch_bounds__(INF_T) void k_cnn12_inf(const SRC *__restrict__ q, double qs, int n,
                                                    const float *__restrict__ th, const uint16_t *__restrict__ wpk,
                                                    uint16_t *a2)
 {
     __shared__ __align__(16) uint16_t U[U1N];
-    __shared__ __align__(16) uint4 X[2 * C2HALO];   // channel planes 0-7 and 8-15
+    __shared__ __align__(16) uint4 X[2 * IHALO];   // channel planes 0-7 and 8-15
     const int tid = threadIdx.x;
     const int ntx = n / C2X, nty = n / C2Y;
     const int tile = blockIdx.x;
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-    const int x0 = tx * C2X, y0 = ty * C2Y, z0 = tz * C2Z, m = n - 1;
+    const int x0 = tx * C2X, y0 = ty * C2Y, z0 = tz * IZ, m = n - 1;
     const int lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = INF_T / 64;   // wavefronts
     const int col = lane & 15, kg = lane >> 4;
     // weight fragments straight from the packed buffer (L2-resident)
     const v8bf w1 = *reinterpret_cast<const v8bf *>(wpk + WPK_W1 / 2 + col * 32 + 8 * kg);
@@ -470,21 +478,20 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const SRC *__restrict__ q, do
         // memory round trip per tile rather than one per round); indices past
         // the end are clamped, and the empty asm keeps the loads from being
         // sunk into the guarded stores
-        constexpr int NU = (U1N + 255) / 256;
-        static_assert(NU == 8, "eight int64 loads per thread");
+        constexpr int NU = (U1N + INF_T - 1) / INF_T;
         SRC qv[NU];
 #pragma unroll
         for (int k = 0; k < NU; k++) {
-            const int e = min(tid + 256 * k, U1N - 1);
+            const int e = min(tid + INF_T * k, U1N - 1);
             const int ux = e % U1X, uy = (e / U1X) % U1Y, uz = e / (U1X * U1Y);
             const int64_t row = (int64_t)((z0 + uz - 2) & m) * n + ((y0 + uy - 2) & m);
             qv[k] = q[row * n + ((x0 + ux - 2) & m)];
         }
-        asm volatile("" : "+v"(qv[0]), "+v"(qv[1]), "+v"(qv[2]), "+v"(qv[3]), "+v"(qv[4]), "+v"(qv[5]), "+v"(qv[6]),
-                     "+v"(qv[7]));
+#pragma unroll
+        for (int k = 0; k < NU; k++) asm volatile("" : "+v"(qv[k]));
 #pragma unroll
         for (int k = 0; k < NU; k++) {
-            const int e = tid + 256 * k;
+            const int e = tid + INF_T * k;
             if constexpr (std::is_same<SRC, int64_t>::value) {
                 if (e < U1N) U[e] = delta_bf16(qv[k], qs);
             } else {
@@ -502,9 +509,9 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const SRC *__restrict__ q, do
         float bias[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) bias[r] = th[NC1B + 4 * kg + r];
-        for (int g = wave; g < NG1; g += 4) {
+        for (int g = wave; g < NG1; g += NW) {
             const int hv = g * 16 + col;
-            const int hc = hv < C2HALO ? hv : C2HALO - 1;
+            const int hc = hv < IHALO ? hv : IHALO - 1;
             const int hx = hc % C2HX, hy = (hc / C2HX) % C2HY, hz = hc / (C2HX * C2HY);
             const int base = (hz * U1Y + hy) * U1X + hx;
             v8bf b;
@@ -513,11 +520,11 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const SRC *__restrict__ q, do
             v4f acc = {0.f, 0.f, 0.f, 0.f};
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, b, acc, 0, 0, 0);
             // lane holds D[co = 4 kg + r][vox = col]: channels 4 kg .. 4 kg + 3
-            if (hv < C2HALO) {
+            if (hv < IHALO) {
                 uint16_t aa[4];
 #pragma unroll
                 for (int r = 0; r < 4; r++) aa[r] = to_bf16(silu(acc[r] + bias[r]));
-                reinterpret_cast<uint2 *>(X + (kg >> 1) * C2HALO + hv)[kg & 1] =
+                reinterpret_cast<uint2 *>(X + (kg >> 1) * IHALO + hv)[kg & 1] =
                     make_uint2((uint32_t)aa[0] | ((uint32_t)aa[1] << 16), (uint32_t)aa[2] | ((uint32_t)aa[3] << 16));
             }
         }
@@ -529,11 +536,11 @@ __global__ __launch_bounds__(256) void k_cnn12_inf(const SRC *__restrict__ q, do
         const int t = 2 * pr + (kg >> 1);
         ox[pr] = x_off(t < 27 ? t : 26);   // the 28th tap reads real data against zero weights
     }
-    const uint4 *Xp = X + (kg & 1) * C2HALO + col;
+    const uint4 *Xp = X + (kg & 1) * IHALO + col;
     float bias[4];
 #pragma unroll
     for (int r = 0; r < 4; r++) bias[r] = th[NC2B + 4 * kg + r];
-    for (int row = wave; row < C2Y * C2Z; row += 4) {
+    for (int row = wave; row < C2Y * IZ; row += NW) {
         const int ry = row % C2Y, rz = row / C2Y;
         const uint4 *xr = Xp + (rz * C2HY + ry) * C2HX;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
@@ -927,10 +934,10 @@ hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *delta, const
     const int64_t M = (int64_t)n * n * n;
     hipLaunchKernelGGL(k_pack_w, dim3(1), dim3(256), 0, s, th, wpk);
     if (delta)
-        hipLaunchKernelGGL(k_cnn12_inf<float>, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, delta, qs, n,
+        hipLaunchKernelGGL(k_cnn12_inf<float>, dim3((unsigned)(M / (C2X * C2Y * IZ))), dim3(INF_T), 0, s, delta, qs, n,
                            th, wpk, a2);
     else
-        hipLaunchKernelGGL(k_cnn12_inf<int64_t>, dim3((unsigned)(M / (C2X * C2Y * C2Z))), dim3(256), 0, s, q, qs, n,
+        hipLaunchKernelGGL(k_cnn12_inf<int64_t>, dim3((unsigned)(M / (C2X * C2Y * IZ))), dim3(INF_T), 0, s, q, qs, n,
                            th, wpk, a2);
     hipLaunchKernelGGL((k_conv3_inf<C3TY, C3TZ, C3ZPT>), dim3((unsigned)(M / (16 * C3TY * C3TZ))), dim3(256), 0, s, a2,
                        n, th, wpk, phif, rs, out);
