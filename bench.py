@@ -28,27 +28,28 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # on this workload, each scaled by what the counter reads for a plain device
 # copy of known size (profiles/ has the summaries and the commands).  A figure
-# is reported only while the kernel's source file still has the hash it had
-# when the counters were taken.
+# is reported only while the kernel's source file and the layout header (row
+# strides, tile sizes) still hash as they did when the counters were taken.
+LAYOUT_HEADER = "paper_2007_13394_amd/csrc/pm_internal.h"
 MEASURED_TRAFFIC = {
     # profiles/c3_step_hbm_counters.md (averages over the profiled launches;
     # the scatter's include the first sort from canonical order)
-    "c2r_x0": {"bytes_per_launch": 69389447263, "source": "paper_2007_13394_amd/csrc/fft.hip",
-               "sha256_16": "effecff1b1096e79"},
-    "cols_inv": {"bytes_per_launch": 70555279954, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "effecff1b1096e79"},
-    "cols_fwd": {"bytes_per_launch": 70562707400, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "effecff1b1096e79"},
-    "x0_green": {"bytes_per_launch": 103884628287, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "effecff1b1096e79"},
-    "r2c_x0": {"bytes_per_launch": 69292611392, "source": "paper_2007_13394_amd/csrc/fft.hip",
-               "sha256_16": "effecff1b1096e79"},
-    "readout_kick_drift": {"bytes_per_launch": 236309479374, "source": "paper_2007_13394_amd/csrc/particles.hip",
-                           "sha256_16": "831cd1c301e74525"},
-    "paint": {"bytes_per_launch": 54965991753, "source": "paper_2007_13394_amd/csrc/paint.hip",
-              "sha256_16": "82f0a8b345f2e4e7"},
-    "sort_scatter": {"bytes_per_launch": 77639712518, "source": "paper_2007_13394_amd/csrc/sort.hip",
-                     "sha256_16": "94773051a338481b"},
+    "c2r_x0": {"bytes_per_launch": 69259793757, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "ba5762b5367e4fef"},
+    "cols_inv": {"bytes_per_launch": 70099128986, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "ba5762b5367e4fef"},
+    "cols_fwd": {"bytes_per_launch": 70033709946, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "ba5762b5367e4fef"},
+    "x0_green": {"bytes_per_launch": 104689658098, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "ba5762b5367e4fef"},
+    "r2c_x0": {"bytes_per_launch": 69283727200, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "ba5762b5367e4fef"},
+    "readout_kick_drift": {"bytes_per_launch": 189388380528, "source": "paper_2007_13394_amd/csrc/particles.hip",
+                           "sha256_16": "fcdcf464308d68e7"},
+    "paint": {"bytes_per_launch": 54960245954, "source": "paper_2007_13394_amd/csrc/paint.hip",
+              "sha256_16": "f0b91ef195fb40f0"},
+    "sort_scatter": {"bytes_per_launch": 77575576666, "source": "paper_2007_13394_amd/csrc/sort.hip",
+                     "sha256_16": "663fa3b7292fa6b1"},
 }
 
 
@@ -63,10 +64,13 @@ def measured_traffic(kernel):
     rec = MEASURED_TRAFFIC.get(kernel)
     if rec is None:
         return None
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), rec["source"])
-    with open(path, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_16"]:
-            return None
+    root = os.path.dirname(os.path.abspath(__file__))
+    data = b""
+    for rel in (rec["source"], LAYOUT_HEADER):
+        with open(os.path.join(root, rel), "rb") as f:
+            data += f.read()
+    if hashlib.sha256(data).hexdigest()[:16] != rec["sha256_16"]:
+        return None
     return rec["bytes_per_launch"]
 
 

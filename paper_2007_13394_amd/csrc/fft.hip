@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_r2c_rows(const SRC *src, int64_t src_st
         const float2 sum = cadd(zk, zc), t = cmul(w, csub(zk, zc));
         dst[(row0 + r) * dst_stride + k] = make_float2(0.5f * (sum.x + t.y), 0.5f * (sum.y - t.x));
     }
-    constexpr int PADC = (int)half_pad(N) - (L + 1);
+    constexpr int PADC = (int)half_cols(N) - (L + 1);   // the last column tile's unused columns
     for (int e = tid; e < RB * PADC; e += T) {
         const int r = e / PADC, k = L + 1 + e % PADC;
         dst[(row0 + r) * dst_stride + k] = make_float2(0.f, 0.f);

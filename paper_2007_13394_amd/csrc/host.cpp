@@ -323,7 +323,7 @@ pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s, const float *delta
 {
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     float2 *F = c->ws.f;
     const int64_t cs = n2 * nhp;
     const double scale = ldexp(1.0, -c->cfg.shift);
@@ -374,7 +374,7 @@ pm_status forward_density(pm_ctx *c, int64_t *q, double scale, hipStream_t s)
 {
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     float2 *S = reinterpret_cast<float2 *>(q);
     LAUNCH(pm::K_R2C, pm::launch_r2c_rows_i64(lg, q, n, S, n, n2, scale, -1.0, c->ws.tw, c->ws.flag, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
@@ -391,7 +391,7 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
 {
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n, cs = n2 * nhp;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     float2 *F = c->ws.f;
     float *Fr = reinterpret_cast<float *>(F);
     // With the tile-sort workspace, the particles and their cotangents are
@@ -469,7 +469,7 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
 {
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n, cs = n2 * nhp, rs = 2 * nhp;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     const double M = (double)n2 * n;
     float2 *F = c->ws.f;
     const double qs = ldexp(1.0, -c->cfg.shift);
@@ -785,7 +785,7 @@ static pm_status ic_impl(pm_ctx *c, const float *white, const float *u, float *x
     const pm_config &g = c->cfg;
     const int nic = g.n_cdm, lg = ilog2i(nic), n = c->n;
     const int64_t nhp = pm::half_pad(nic), n2 = (int64_t)nic * nic;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(nic) / pm::TILE_W);
     float2 *S0 = reinterpret_cast<float2 *>(c->ws.q);
     float2 *F = c->ws.f;
     const int64_t cs = n2 * nhp;
@@ -907,7 +907,7 @@ pm_status pm_fft_r2c(pm_ctx *c, const float *real, float *out, void *stream)
     hipStream_t s = S(stream);
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     float2 *S0 = reinterpret_cast<float2 *>(c->ws.q);
     LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, real, n, S0, n, n2, c->ws.tw, s));
     LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S0, n, n2, n, ncb, c->ws.tw, s));
@@ -922,7 +922,7 @@ pm_status pm_fft_c2r(pm_ctx *c, const float *spec, float *real, void *stream)
     hipStream_t s = S(stream);
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     float2 *F = c->ws.f;
     LAUNCH(pm::K_COPY, pm::launch_load_half(reinterpret_cast<const float2 *>(spec), n, F, nhp, s));
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
@@ -1077,7 +1077,7 @@ pm_status pm_power_mesh(pm_ctx *c, const float *da, const float *db, int32_t nbi
     hipStream_t s = S(stream);
     const int n = c->n, lg = c->logn;
     const int64_t M = (int64_t)n * n * n, n2 = (int64_t)n * n, nhp = pm::half_pad(n);
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     auto spectrum = [&](const float *d, float2 *S) -> pm_status {
         LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, d, n, S, n, n2, c->ws.tw, s));
         LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, S, n, n2, n, ncb, c->ws.tw, s));
@@ -1165,7 +1165,7 @@ pm_status pm_ic_vjp(pm_ctx *c, const float *xbar, const float *pbar, float *wbar
     const pm_config &g = c->cfg;
     const int nic = g.n_cdm, lg = ilog2i(nic), n = c->n;
     const int64_t nhp = pm::half_pad(nic), n2 = (int64_t)nic * nic, cs = n2 * nhp;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(nic) / pm::TILE_W);
     float2 *F = c->ws.f;
     float *Fr = reinterpret_cast<float *>(F);
     float2 *A = reinterpret_cast<float2 *>(c->ws.q);
@@ -1272,7 +1272,7 @@ pm_status pm_learned_loss(pm_ctx *c, const float *th, double a, const float *x, 
     hipStream_t s = S(stream);
     const int n = c->n, lg = c->logn;
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n, cs = n2 * nhp, rs = 2 * nhp;
-    const int ncb = (int)(nhp / pm::TILE_W);
+    const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     const double M = (double)n2 * n;
     float2 *F = c->ws.f;
     float *Fr = reinterpret_cast<float *>(F);
