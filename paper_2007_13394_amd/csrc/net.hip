@@ -447,6 +447,30 @@ __global__ __launch_bounds__(256) void k_pack_w(const float *__restrict__ th, ui
     }
 }
 
+// x / D for 0 <= x < N as one 24-bit multiply and a shift: v_mul_u32_u24 is
+// full rate, while the 32-bit multiplies that a division by a constant
+// otherwise becomes are quarter rate.  Exactness on the range is checked at
+// compile time.
+template <unsigned D, unsigned N>
+struct Div24 {
+    static constexpr unsigned M = (65536u + D - 1) / D;
+    static constexpr bool exact()
+    {
+        for (unsigned x = 0; x < N; x++)
+            if (((x * M) >> 16) != x / D) return false;
+        return (unsigned long long)N * M < (1ull << 32);
+    }
+    static_assert(exact(), "multiply-shift division not exact on the range");
+    __device__ static __forceinline__ int div(int x)
+    {
+        // written out, since the compiler turns a 24-bit multiply whose
+        // operands it can bound back into the quarter-rate v_mul_lo_u32
+        unsigned r;
+        asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(M), "v"((unsigned)x));
+        return (int)(r >> 16);
+    }
+};
+
 __device__ __forceinline__ int u1_off(int t) { return ((t / 9) * U1Y + (t / 3) % 3) * U1X + t % 3; }
 __device__ __forceinline__ int x_off(int t) { return ((t / 9) * C2HY + (t / 3) % 3) * C2HX + t % 3; }
 
@@ -483,7 +507,8 @@ __global__ __launch_bounds__(INF_T) void k_cnn12_inf(const SRC *__restrict__ q, 
 #pragma unroll
         for (int k = 0; k < NU; k++) {
             const int e = min(tid + INF_T * k, U1N - 1);
-            const int ux = e % U1X, uy = (e / U1X) % U1Y, uz = e / (U1X * U1Y);
+            const int eq = Div24<U1X, U1N>::div(e), uz = Div24<U1Y, U1N / U1X>::div(eq);
+            const int ux = e - __mul24(eq, U1X), uy = eq - __mul24(uz, U1Y);
             const int64_t row = (int64_t)((z0 + uz - 2) & m) * n + ((y0 + uy - 2) & m);
             qv[k] = q[row * n + ((x0 + ux - 2) & m)];
         }
@@ -512,8 +537,9 @@ __global__ __launch_bounds__(INF_T) void k_cnn12_inf(const SRC *__restrict__ q, 
         for (int g = wave; g < NG1; g += NW) {
             const int hv = g * 16 + col;
             const int hc = hv < IHALO ? hv : IHALO - 1;
-            const int hx = hc % C2HX, hy = (hc / C2HX) % C2HY, hz = hc / (C2HX * C2HY);
-            const int base = (hz * U1Y + hy) * U1X + hx;
+            const int hq = Div24<C2HX, IHALO>::div(hc), hz = Div24<C2HY, IHALO / C2HX>::div(hq);
+            const int hx = hc - __mul24(hq, C2HX), hy = hq - __mul24(hz, C2HY);
+            const int base = __mul24(__mul24(hz, U1Y) + hy, U1X) + hx;
             v8bf b;
 #pragma unroll
             for (int j = 0; j < 8; j++) b[j] = __builtin_bit_cast(__bf16, U[base + ou[j]]);
@@ -536,25 +562,31 @@ __global__ __launch_bounds__(INF_T) void k_cnn12_inf(const SRC *__restrict__ q, 
         const int t = 2 * pr + (kg >> 1);
         ox[pr] = x_off(t < 27 ? t : 26);   // the 28th tap reads real data against zero weights
     }
-    const uint4 *Xp = X + (kg & 1) * IHALO + col;
+    // wavefront w computes the output rows y = w of every z plane: with the
+    // loop unrolled, a row's LDS offsets are the loop-invariant lane offsets
+    // plus an immediate, and the output pointer steps by one plane
+    static_assert(NW == C2Y, "one wavefront per output row of a plane");
+    const uint4 *Xp = X + (kg & 1) * IHALO + wave * C2HX + col;
     float bias[4];
 #pragma unroll
     for (int r = 0; r < 4; r++) bias[r] = th[NC2B + 4 * kg + r];
-    for (int row = wave; row < C2Y * IZ; row += NW) {
-        const int ry = row % C2Y, rz = row / C2Y;
-        const uint4 *xr = Xp + (rz * C2HY + ry) * C2HX;
+    uint16_t *out = a2 + ((((int64_t)z0 * n + (y0 + wave)) * n + (x0 + col)) * NET_C + 4 * kg);
+    const int64_t plane_step = (int64_t)n * n * NET_C;
+#pragma unroll
+    for (int rz = 0; rz < IZ; rz++) {
+        const uint4 *xr = Xp + rz * (C2HY * C2HX);
         v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int pr = 0; pr < NPAIR; pr++) {
             const v8bf xb = __builtin_bit_cast(v8bf, xr[ox[pr]]);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[pr], xb, acc, 0, 0, 0);
         }
-        const int64_t v = ((int64_t)(z0 + rz) * n + (y0 + ry)) * n + (x0 + col);
         uint16_t aa[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) aa[r] = to_bf16(silu(acc[r] + bias[r]));
-        *reinterpret_cast<uint2 *>(a2 + v * NET_C + 4 * kg) =
+        *reinterpret_cast<uint2 *>(out) =
             make_uint2((uint32_t)aa[0] | ((uint32_t)aa[1] << 16), (uint32_t)aa[2] | ((uint32_t)aa[3] << 16));
+        out += plane_step;
     }
 }
 
