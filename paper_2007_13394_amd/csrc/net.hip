@@ -471,6 +471,13 @@ struct Div24 {
     }
 };
 
+// Index of voxel (z, y, x) of an n^3 mesh (n <= 4096): the row index in 24-bit
+// arithmetic, then one 64-bit multiply-add.
+__device__ __forceinline__ int64_t vox_index(int z, int y, int x, int n)
+{
+    return (int64_t)(unsigned)(__mul24(z, n) + y) * (unsigned)n + (unsigned)x;
+}
+
 __device__ __forceinline__ int u1_off(int t) { return ((t / 9) * U1Y + (t / 3) % 3) * U1X + t % 3; }
 __device__ __forceinline__ int x_off(int t) { return ((t / 9) * C2HY + (t / 3) % 3) * C2HX + t % 3; }
 
@@ -509,8 +516,7 @@ __global__ __launch_bounds__(INF_T) void k_cnn12_inf(const SRC *__restrict__ q, 
             const int e = min(tid + INF_T * k, U1N - 1);
             const int eq = Div24<U1X, U1N>::div(e), uz = Div24<U1Y, U1N / U1X>::div(eq);
             const int ux = e - __mul24(eq, U1X), uy = eq - __mul24(uz, U1Y);
-            const int64_t row = (int64_t)((z0 + uz - 2) & m) * n + ((y0 + uy - 2) & m);
-            qv[k] = q[row * n + ((x0 + ux - 2) & m)];
+            qv[k] = q[vox_index((z0 + uz - 2) & m, (y0 + uy - 2) & m, (x0 + ux - 2) & m, n)];
         }
 #pragma unroll
         for (int k = 0; k < NU; k++) asm volatile("" : "+v"(qv[k]));
@@ -631,8 +637,9 @@ __global__ __launch_bounds__(256) void k_conv3_inf(const uint16_t *__restrict__ 
         for (int k = 0; k < NX; k++) {
             const int e = min(tid + 256 * k, HALO * 2 - 1);
             const int hv = e >> 1, half = e & 1;
-            const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-            const int64_t g = ((int64_t)((z0 + hz - 1) & m) * n + ((y0 + hy - 1) & m)) * n + ((x0 + hx - 1) & m);
+            const int hq = Div24<HX, HALO>::div(hv), hz = Div24<HY, HALO / HX>::div(hq);
+            const int hx = hv - __mul24(hq, HX), hy = hq - __mul24(hz, HY);
+            const int64_t g = vox_index((z0 + hz - 1) & m, (y0 + hy - 1) & m, (x0 + hx - 1) & m, n);
             xv[k] = reinterpret_cast<const uint4 *>(a2 + g * NET_C)[half];
         }
         // the conv3 weights, one 16-byte row per thread, unconditional like
@@ -962,7 +969,7 @@ hipError_t launch_cnn_fwd(const int64_t *q, double qs, int n, const float *th, f
 hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *delta, const float *phif, int64_t rs, int n,
                           const float *th, uint16_t *wpk, uint16_t *a2, float *out, hipStream_t s)
 {
-    if (n < 16 || n % 16) return hipErrorInvalidValue;
+    if (n < 16 || n % 16 || n > 4096) return hipErrorInvalidValue;
     const int64_t M = (int64_t)n * n * n;
     hipLaunchKernelGGL(k_pack_w, dim3(1), dim3(256), 0, s, th, wpk);
     if (delta)
