@@ -34,22 +34,22 @@ LAYOUT_HEADER = "paper_2007_13394_amd/csrc/pm_internal.h"
 MEASURED_TRAFFIC = {
     # profiles/c3_step_hbm_counters.md (averages over the profiled launches;
     # the scatter's include the first sort from canonical order)
-    "c2r_x0": {"bytes_per_launch": 69259793757, "source": "paper_2007_13394_amd/csrc/fft.hip",
-               "sha256_16": "ba5762b5367e4fef"},
-    "cols_inv": {"bytes_per_launch": 70099128986, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "ba5762b5367e4fef"},
-    "cols_fwd": {"bytes_per_launch": 70033709946, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "ba5762b5367e4fef"},
-    "x0_green": {"bytes_per_launch": 104689658098, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "ba5762b5367e4fef"},
-    "r2c_x0": {"bytes_per_launch": 69283727200, "source": "paper_2007_13394_amd/csrc/fft.hip",
-               "sha256_16": "ba5762b5367e4fef"},
-    "readout_kick_drift": {"bytes_per_launch": 189388380528, "source": "paper_2007_13394_amd/csrc/particles.hip",
-                           "sha256_16": "fcdcf464308d68e7"},
-    "paint": {"bytes_per_launch": 54960245954, "source": "paper_2007_13394_amd/csrc/paint.hip",
-              "sha256_16": "f0b91ef195fb40f0"},
-    "sort_scatter": {"bytes_per_launch": 77575576666, "source": "paper_2007_13394_amd/csrc/sort.hip",
-                     "sha256_16": "663fa3b7292fa6b1"},
+    "c2r_x0": {"bytes_per_launch": 69351056942, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "6fb66d6c3e23e7ed"},
+    "cols_inv": {"bytes_per_launch": 70469866434, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "6fb66d6c3e23e7ed"},
+    "cols_fwd": {"bytes_per_launch": 70584598231, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "6fb66d6c3e23e7ed"},
+    "x0_green": {"bytes_per_launch": 103884583390, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "6fb66d6c3e23e7ed"},
+    "r2c_x0": {"bytes_per_launch": 69054353803, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "6fb66d6c3e23e7ed"},
+    "readout_kick_drift": {"bytes_per_launch": 192225836542, "source": "paper_2007_13394_amd/csrc/particles.hip",
+                           "sha256_16": "a58c23458bfaf350"},
+    "paint": {"bytes_per_launch": 54968320253, "source": "paper_2007_13394_amd/csrc/paint.hip",
+              "sha256_16": "28ef60e3e26e0897"},
+    "sort_scatter": {"bytes_per_launch": 77631125591, "source": "paper_2007_13394_amd/csrc/sort.hip",
+                     "sha256_16": "b06dbf2b3ae7d01e"},
 }
 
 

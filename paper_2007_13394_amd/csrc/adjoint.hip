@@ -32,7 +32,8 @@ struct Cic {
     float w[3][2];
 };
 
-__device__ __forceinline__ Cic cic_at(float u0, float u1, float u2, int n, int64_t rs)
+// Row offsets on a mesh of row stride rs and plane stride ps.
+__device__ __forceinline__ Cic cic_at(float u0, float u1, float u2, int n, int64_t rs, int64_t ps)
 {
     Cic r;
     const int mask = n - 1;
@@ -50,7 +51,7 @@ __device__ __forceinline__ Cic cic_at(float u0, float u1, float u2, int n, int64
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int b = 0; b < 2; b++) r.row[a][b] = ((int64_t)c[0][a] * n + c[1][b]) * rs;
+        for (int b = 0; b < 2; b++) r.row[a][b] = (int64_t)c[0][a] * ps + (int64_t)c[1][b] * rs;
     r.c2[0] = c[2][0];
     r.c2[1] = c[2][1];
     return r;
@@ -95,11 +96,11 @@ __global__ void k_axpy(float *y, const float *x, float a, int64_t n)
 // Readout term: xbar_i += gscale * sum_d g_{i,d} grad interp(F_d)(x_i).
 __global__ __launch_bounds__(256) void k_readout_grad3(const float *__restrict__ x, int64_t P,
                                                        const float *__restrict__ g, float gscale,
-                                                       const float *__restrict__ F, int64_t rs, int64_t cs, int n,
-                                                       float *xbar)
+                                                       const float *__restrict__ F, int64_t rs, int64_t ps,
+                                                       int64_t cs, int n, float *xbar)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
-        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, rs);
+        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, rs, ps);
         const float v[3] = {gscale * g[i], gscale * g[P + i], gscale * g[2 * P + i]};
         float out[3];
         interp_grad<3>(q, F, cs, v, out);
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256) void k_paint_vec3(const float *__restrict__ x,
                                                     int64_t cs, int n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
-        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, rs);
+        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, rs, (int64_t)n * rs);
         const float v[3] = {gscale * g[i], gscale * g[P + i], gscale * g[2 * P + i]};
 #pragma unroll
         for (int a = 0; a < 2; a++)
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void k_paint_q1(const float *__restrict__ x, i
                                                   unsigned long long *Q)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
-        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, n);
+        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, n, (int64_t)n * n);
         const double v = (double)(gscale * gd[i]) * S;
 #pragma unroll
         for (int a = 0; a < 2; a++)
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(256) void k_density_grad(const float *__restrict__ 
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
         const int g = segment_of(i, nseg, seg_off, tags);
         const float m = (float)quanta[g] * qscale * scale;
-        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, rs);
+        const Cic q = cic_at(x[i], x[P + i], x[2 * P + i], n, rs, (int64_t)n * rs);
         const float v[1] = {m};
         float out[3];
         interp_grad<1>(q, mesh, 0, v, out);
@@ -332,9 +333,10 @@ hipError_t launch_axpy(float *y, const float *x, float a, int64_t n, hipStream_t
 }
 
 hipError_t launch_readout_grad3(const float *x, int64_t P, const float *g, float gscale, const float *F, int64_t rs,
-                                int64_t cs, int n, float *xbar, hipStream_t s)
+                                int64_t ps, int64_t cs, int n, float *xbar, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_readout_grad3, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P, g, gscale, F, rs, cs, n, xbar);
+    hipLaunchKernelGGL(k_readout_grad3, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P, g, gscale, F, rs, ps, cs, n,
+                       xbar);
     return hipGetLastError();
 }
 

@@ -870,7 +870,8 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_r2c_x0(const SRC *src, int6
 
 template <int LOGN>
 __global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, float *dst, int64_t dst_stride,
-                                                            int nhp, int64_t plane, const float2 *__restrict__ tw)
+                                                            int64_t dst_plane, int nhp, int64_t plane,
+                                                            const float2 *__restrict__ tw)
 {
     constexpr int N = 1 << LOGN, L = N / 2, T = L, N2 = N / 16, RB = 16, LS = L, PS = SWZ_ROWS;
     __shared__ float2 buf[padded(RB * LS, PS)];
@@ -936,7 +937,7 @@ __global__ __launch_bounds__(1 << (LOGN - 1)) void k_c2r_x0(const float2 *src, f
     for (int e = tid; e < RB * L / 2; e += T) {
         const int r = e / (L / 2), m = 2 * (e % (L / 2));
         const float2 a = buf[pad<PS>(r * LS + m)], b = buf[pad<PS>(r * LS + m + 1)];
-        *reinterpret_cast<float4 *>(dst + ((int64_t)(j1 + N2 * r) * N + x1) * dst_stride + 2 * m) =
+        *reinterpret_cast<float4 *>(dst + (int64_t)(j1 + N2 * r) * dst_plane + (int64_t)x1 * dst_stride + 2 * m) =
             make_float4(a.x, a.y, b.x, b.y);
     }
 }
@@ -1058,8 +1059,9 @@ hipError_t launch_axis0(int logn, int mode, const float2 *src, int64_t s_l, int6
 hipError_t launch_x0_green(int logn, const float2 *src, float2 *out0, float2 *out1, int64_t plane, int nhp,
                            double coef, const float2 *tw, hipStream_t s)
 {
-    if (logn < 8 || logn > 11 || plane % 64 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(plane / 64), 16);
+    // planes hold N rows of nhp values and may be followed by padding
+    if (logn < 8 || logn > 11 || plane < ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(((int64_t)nhp << logn) / 64), 16);
     const float fc = (float)coef;
 #define X0B(NN)                                                                                      \
     hipLaunchKernelGGL((k_x0_green<NN>), grid, dim3(X0Cfg<NN>::T), 0, s, src, out0, out1, plane, nhp, fc, tw)
@@ -1077,8 +1079,8 @@ hipError_t launch_x0_learned(int logn, const float2 *srcd, const float2 *srcc, f
                              int64_t plane, int nhp, double coef, double inv_m, const float *table, const float2 *tw,
                              hipStream_t s)
 {
-    if (logn < 8 || logn > 11 || plane % 64 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(plane / 64), 16);
+    if (logn < 8 || logn > 11 || plane < ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(((int64_t)nhp << logn) / 64), 16);
     const float fc = (float)coef, fm = (float)inv_m;
 #define X0L(NN)                                                                                      \
     hipLaunchKernelGGL((k_x0_learned<NN>), grid, dim3(X0Cfg<NN>::T), 0, s, srcd, srcc, out0, out1, plane, nhp, fc, fm, \
@@ -1096,7 +1098,7 @@ hipError_t launch_x0_learned(int logn, const float2 *srcd, const float2 *srcc, f
 hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int64_t plane, double scale,
                          double offset, const float2 *tw, int *flag, hipStream_t s)
 {
-    if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    if (logn < 8 || logn > 11 || plane < ((int64_t)nhp << logn)) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
 #define R2CX(LG)                                                                                     \
     hipLaunchKernelGGL((k_r2c_x0<LG, int64_t>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, (int64_t)1 << LG, dst, nhp, \
@@ -1114,7 +1116,7 @@ hipError_t launch_r2c_x0(int logn, const int64_t *src, float2 *dst, int nhp, int
 hipError_t launch_r2c_x0_f32(int logn, const float *src, int64_t src_rs, float2 *dst, int nhp, int64_t plane,
                              const float2 *tw, hipStream_t s)
 {
-    if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn) || src_rs < ((int64_t)1 << logn))
+    if (logn < 8 || logn > 11 || plane < ((int64_t)nhp << logn) || src_rs < ((int64_t)1 << logn))
         return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
 #define R2CX(LG)                                                                                     \
@@ -1130,15 +1132,18 @@ hipError_t launch_r2c_x0_f32(int logn, const float *src, int64_t src_rs, float2 
     return hipGetLastError();
 }
 
-hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int nhp, int64_t plane,
-                         const float2 *tw, hipStream_t s)
+hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int64_t dst_plane, int nhp,
+                         int64_t plane, const float2 *tw, hipStream_t s)
 {
-    if (logn < 8 || logn > 11 || plane != ((int64_t)nhp << logn)) return hipErrorInvalidValue;
+    if (logn < 8 || logn > 11 || plane < ((int64_t)nhp << logn)) return hipErrorInvalidValue;
     // the rows are stored 16 bytes at a time
-    if ((reinterpret_cast<uintptr_t>(dst) & 15) != 0 || dst_stride % 4 != 0) return hipErrorInvalidValue;
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) != 0 || dst_stride % 4 != 0 || dst_plane % 4 != 0 ||
+        dst_plane < (dst_stride << logn))
+        return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((1 << logn) / 16) << logn;
 #define C2RX(LG)                                                                                     \
-    hipLaunchKernelGGL((k_c2r_x0<LG>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, dst_stride, nhp, plane, tw)
+    hipLaunchKernelGGL((k_c2r_x0<LG>), dim3(nb), dim3(1 << (LG - 1)), 0, s, src, dst, dst_stride, dst_plane, nhp, \
+                       plane, tw)
     switch (logn) {
     case 8: C2RX(8); break;
     case 9: C2RX(9); break;

@@ -126,7 +126,8 @@ Layout layout(const pm_config &c)
     L.q = off;
     off = align256(off + (size_t)(8 * n * n * n));
     L.f = off;
-    const size_t fbytes = (size_t)(3 * n * n * nhp * 8);
+    const size_t fbytes = (size_t)(3 * n * pm::force_plane((int)n) * 8);
+    (void)nhp;
     off = align256(off + fbytes);
     L.tw = off;
     off = align256(off + (size_t)(2 * n * 8));
@@ -325,31 +326,33 @@ pm_status solve(pm_ctx *c, const int64_t *src, hipStream_t s, const float *delta
     const int64_t nhp = pm::half_pad(n), n2 = (int64_t)n * n;
     const int ncb = (int)(pm::half_cols(n) / pm::TILE_W);
     float2 *F = c->ws.f;
-    const int64_t cs = n2 * nhp;
+    // component stride: N planes of force_plane(N) (N half_pad rows below the
+    // padding threshold, which the row path below relies on)
+    const int64_t plane = pm::force_plane(n), cs = n * plane;
     const double scale = ldexp(1.0, -c->cfg.shift);
     const double coef = 1.5 * c->cfg.omega_m / ((double)n2 * n);
     if (lg >= 8) {
         // axis 0 as 16 x N/16 (four-step): the 16-point pass rides on the row
         // transforms, the N/16-point pass on the gradient of the inverse
         // Laplacian; the spectrum stays digit-reversed along axis 0 in between
-        const int64_t plane = (int64_t)n * nhp;
         if (delta)
             LAUNCH(pm::K_R2C_X0, pm::launch_r2c_x0_f32(lg, delta, n, F, (int)nhp, plane, c->ws.tw, s));
         else
             LAUNCH(pm::K_R2C_X0,
                    pm::launch_r2c_x0(lg, src, F, (int)nhp, plane, scale, -1.0, c->ws.tw, c->ws.flag, s));
-        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
+        LAUNCH(pm::K_COLS_FWD, pm::launch_cols(lg, false, F, nhp, plane, n, ncb, c->ws.tw, s));
         // F0 <- k0 T, F1 <- T; the inverse column passes apply the k2 and
         // k1 factors: component 2 from F1 into F2 first, then 1 in place
         LAUNCH(pm::K_X0_GREEN, pm::launch_x0_green(lg, F, F, F + cs, plane, (int)nhp, coef, c->ws.tw, s));
         for (int d = 2; d >= 0; d--) {
-            LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, d == 0 ? F : F + cs, nhp, n * nhp, n, ncb, c->ws.tw, s,
+            LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, d == 0 ? F : F + cs, nhp, plane, n, ncb, c->ws.tw, s,
                                                    d, F + d * cs));
             LAUNCH(pm::K_C2R_X0, pm::launch_c2r_x0(lg, F + d * cs, reinterpret_cast<float *>(F + d * cs), 2 * nhp,
-                                                   (int)nhp, plane, c->ws.tw, s));
+                                                   2 * plane, (int)nhp, plane, c->ws.tw, s));
         }
         return PM_OK;
     }
+    if (plane != n * nhp) return fail(PM_ERR_STATE, "padded planes on the row path");
     // axis 2: density contrast, real-to-complex rows
     if (delta)
         LAUNCH(pm::K_R2C, pm::launch_r2c_rows_f32(lg, delta, n, F, nhp, n2, c->ws.tw, s));
@@ -433,7 +436,9 @@ pm_status force_vjp(pm_ctx *c, const float *x, const float *g, double gscale, fl
     if (!std::isfinite(gm)) return fail(PM_ERR_NAN, "a cotangent is not finite");
     const double S = gm > 0 ? ldexp(1.0, 61 - (int)ceil(log2((double)c->P * (double)gm))) : 1.0;
     // a non-finite cotangent is reported before xbar is touched
-    LAUNCH(pm::K_ADJOINT, pm::launch_readout_grad3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * cs, n, xbar, s));
+    const int64_t fp = pm::force_plane(n);   // the force meshes' plane stride
+    LAUNCH(pm::K_ADJOINT,
+           pm::launch_readout_grad3(x, c->P, g, (float)gscale, Fr, 2 * nhp, 2 * fp, 2 * n * fp, n, xbar, s));
     for (int d = 0; d < 3; d++) {
         float2 *Fd = F + d * cs;
         if (tiles) {
@@ -523,7 +528,7 @@ pm_status learned_solve(pm_ctx *c, const float *th, double a, bool keep, hipStre
             LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, d == 0 ? F : F + cs, nhp, n * nhp, n, ncb, c->ws.tw, s,
                                                    d, F + d * cs));
             LAUNCH(pm::K_C2R_X0, pm::launch_c2r_x0(lg, F + d * cs, reinterpret_cast<float *>(F + d * cs), 2 * nhp,
-                                                   (int)nhp, plane, c->ws.tw, s));
+                                                   2 * plane, (int)nhp, plane, c->ws.tw, s));
         }
         return PM_OK;
     } else {
@@ -928,7 +933,7 @@ pm_status pm_fft_c2r(pm_ctx *c, const float *spec, float *real, void *stream)
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, n * nhp, nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, F, nhp, n * nhp, n, ncb, c->ws.tw, s));
     LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, F, nhp, reinterpret_cast<float *>(F), 2 * nhp, n2, c->ws.tw, s));
-    LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(F), 2 * nhp, n, real, s));
+    LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(F), 2 * nhp, 2 * n * nhp, n, real, s));
     return PM_OK;
 }
 
@@ -938,10 +943,10 @@ pm_status pm_force_mesh(pm_ctx *c, const int64_t *mesh_q, float *out, void *stre
     hipStream_t s = S(stream);
     pm_status st = solve(c, mesh_q, s);
     if (st != PM_OK) return st;
-    const int64_t n = c->n, nhp = pm::half_pad(c->n), cs = n * n * nhp;
+    const int64_t n = c->n, nhp = pm::half_pad(c->n), fp = pm::force_plane(c->n), cs = n * fp;
     for (int d = 0; d < 3; d++)
-        LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(c->ws.f + d * cs), 2 * nhp, c->n,
-                                    out + d * n * n * n, s));
+        LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(c->ws.f + d * cs), 2 * nhp, 2 * fp,
+                                                c->n, out + d * n * n * n, s));
     return check_guards(c, s);
 }
 
@@ -952,8 +957,8 @@ pm_status pm_force(pm_ctx *c, const float *x, float *acc, void *stream)
     pm_status st = paint_all(c, x, s);
     if (st == PM_OK) st = solve(c, c->ws.q, s);
     if (st != PM_OK) return st;
-    const int64_t n = c->n, nhp = pm::half_pad(c->n);
-    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, c->ws.f, nhp, n * n * nhp, c->n, acc, s));
+    const int64_t n = c->n, nhp = pm::half_pad(c->n), fp = pm::force_plane(c->n);
+    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, c->ws.f, nhp, fp, n * fp, c->n, acc, s));
     return check_guards(c, s);
 }
 
@@ -965,7 +970,7 @@ pm_status pm_step(pm_ctx *c, float *x, float *p, double a_force, double a_kick0,
     pm_status st = pm_kdk_factors(c, a_force, a_kick0, a_kick1, a_drift1, &kick, &drift);
     if (st != PM_OK) return st;
     hipStream_t s = S(stream);
-    const int64_t n = c->n, nhp = pm::half_pad(c->n);
+    const int64_t n = c->n, nhp = pm::half_pad(c->n), fp = pm::force_plane(c->n);
     if (sorting_on(c)) {
         // sort by tile, paint tile by tile, solve, read out tile by tile into
         // the caller's arrays, which then hold the particles in sorted order
@@ -981,7 +986,7 @@ pm_status pm_step(pm_ctx *c, float *x, float *p, double a_force, double a_kick0,
         int *cnt_next = (c->cfg.flags & PM_FLAG_NO_GUARDS) ? nullptr : c->ws.cnt_next;
         if (cnt_next) LAUNCH(pm::K_FILL, pm::launch_fill_i32(cnt_next, c->nkeys + 1, s));
         LAUNCH(pm::K_READOUT_KD,
-               pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * n * nhp, c->n,
+               pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, fp, n * fp, c->n,
                                            (float)kick, (float)drift, x, p, c->ws.tags, c->ws.ids_tmp, c->ids,
                                            c->ws.flag, cnt_next, s));
         c->permuted = true;
@@ -992,7 +997,7 @@ pm_status pm_step(pm_ctx *c, float *x, float *p, double a_force, double a_kick0,
     st = paint_all(c, x, s);
     if (st == PM_OK) st = solve(c, c->ws.q, s);
     if (st != PM_OK) return st;
-    LAUNCH(pm::K_READOUT_KD, pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, n * n * nhp, c->n, (float)kick,
+    LAUNCH(pm::K_READOUT_KD, pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, fp, n * fp, c->n, (float)kick,
                                                            (float)drift, c->ws.flag, s));
     return check_guards(c, s);
 }
@@ -1201,7 +1206,7 @@ pm_status pm_ic_vjp(pm_ctx *c, const float *xbar, const float *pbar, float *wbar
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, A, nic * nhp, nhp, nic, ncb, c->ws.tw, s));
     LAUNCH(pm::K_COLS_INV, pm::launch_cols(lg, true, A, nhp, nic * nhp, nic, ncb, c->ws.tw, s));
     LAUNCH(pm::K_C2R, pm::launch_c2r_rows(lg, A, nhp, reinterpret_cast<float *>(A), 2 * nhp, n2, c->ws.tw, s));
-    LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(A), 2 * nhp, nic, wbar, s));
+    LAUNCH(pm::K_COPY, pm::launch_copy_real(reinterpret_cast<const float *>(A), 2 * nhp, 2 * nic * nhp, nic, wbar, s));
     return PM_OK;
 }
 
@@ -1219,7 +1224,7 @@ pm_status pm_learned_force(pm_ctx *c, const float *th, double a, const float *x,
     if (st == PM_OK) st = learned_solve(c, th, a, false, s);
     if (st != PM_OK) return st;
     const int64_t n = c->n, nhp = pm::half_pad(c->n);
-    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, c->ws.f, nhp, n * n * nhp, c->n, acc, s));
+    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, c->ws.f, nhp, n * nhp, n * n * nhp, c->n, acc, s));
     return check_guards(c, s);
 }
 
@@ -1247,7 +1252,7 @@ pm_status pm_learned_step(pm_ctx *c, const float *th, float *x, float *p, double
         int *cnt_next = (c->cfg.flags & PM_FLAG_NO_GUARDS) ? nullptr : c->ws.cnt_next;
         if (cnt_next) LAUNCH(pm::K_FILL, pm::launch_fill_i32(cnt_next, c->nkeys + 1, s));
         LAUNCH(pm::K_READOUT_KD,
-               pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * n * nhp, c->n,
+               pm::launch_readout_kd_tiles(c->ws.xs, c->ws.ps, c->P, c->ws.koff, c->ws.f, nhp, n * nhp, n * n * nhp, c->n,
                                            (float)kick, (float)drift, x, p, c->ws.tags, c->ws.ids_tmp, c->ids,
                                            c->ws.flag, cnt_next, s));
         c->permuted = true;
@@ -1258,7 +1263,7 @@ pm_status pm_learned_step(pm_ctx *c, const float *th, float *x, float *p, double
     st = paint_all(c, x, s);
     if (st == PM_OK) st = learned_solve(c, th, a_force, false, s);
     if (st != PM_OK) return st;
-    LAUNCH(pm::K_READOUT_KD, pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, n * n * nhp, c->n, (float)kick,
+    LAUNCH(pm::K_READOUT_KD, pm::launch_readout_kick_drift(x, p, c->P, c->ws.f, nhp, n * nhp, n * n * nhp, c->n, (float)kick,
                                                            (float)drift, c->ws.flag, s));
     return check_guards(c, s);
 }
@@ -1279,7 +1284,7 @@ pm_status pm_learned_loss(pm_ctx *c, const float *th, double a, const float *x, 
     st = paint_all(c, x, s);
     if (st == PM_OK) st = learned_solve(c, th, a, dth != nullptr, s);
     if (st != PM_OK) return st;
-    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, F, nhp, cs, n, c->ws.net_acc, s));
+    LAUNCH(pm::K_READOUT, pm::launch_readout(x, c->P, F, nhp, n * nhp, cs, n, c->ws.net_acc, s));
     LAUNCH(pm::K_NET, pm::launch_force_loss(c->ws.net_acc, target, 3 * c->P, c->ws.net_red, s));
     double red[2];
     if (hipMemcpyAsync(red, c->ws.net_red, sizeof(red), hipMemcpyDeviceToHost, s) != hipSuccess ||

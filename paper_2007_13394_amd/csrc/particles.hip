@@ -24,8 +24,8 @@ __global__ void k_fill_i64(int64_t *p, int64_t count)
 
 // Cloud-in-cell interpolation of the three force meshes at u (float32
 // weights; the force field is float32).
-__device__ __forceinline__ void cic_gather(const float *__restrict__ F, int64_t rs, int64_t cs, int n, float u0,
-                                           float u1, float u2, float out[3])
+__device__ __forceinline__ void cic_gather(const float *__restrict__ F, int64_t rs, int64_t ps, int64_t cs, int n,
+                                           float u0, float u1, float u2, float out[3])
 {
     const int mask = n - 1;
     const float f0 = floorf(u0), f1 = floorf(u1), f2 = floorf(u2);
@@ -39,7 +39,7 @@ __device__ __forceinline__ void cic_gather(const float *__restrict__ F, int64_t 
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++) {
-            const int64_t row = ((int64_t)i0[a] * n + i1[b]) * rs;
+            const int64_t row = (int64_t)i0[a] * ps + (int64_t)i1[b] * rs;
             const float wab = w0[a] * w1[b];
 #pragma unroll
             for (int c = 0; c < 2; c++) {
@@ -64,11 +64,11 @@ __device__ __forceinline__ float wrapf(float v, float nf)
 }
 
 __global__ __launch_bounds__(256) void k_readout(const float *__restrict__ x, int64_t P, const float *__restrict__ F,
-                                                 int64_t rs, int64_t cs, int n, float *acc)
+                                                 int64_t rs, int64_t ps, int64_t cs, int n, float *acc)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
         float f[3];
-        cic_gather(F, rs, cs, n, x[i], x[P + i], x[2 * P + i], f);
+        cic_gather(F, rs, ps, cs, n, x[i], x[P + i], x[2 * P + i], f);
         acc[i] = f[0];
         acc[P + i] = f[1];
         acc[2 * P + i] = f[2];
@@ -77,15 +77,15 @@ __global__ __launch_bounds__(256) void k_readout(const float *__restrict__ x, in
 
 // p += kick F(x); x += drift p; x wrapped into [0, n).
 __global__ __launch_bounds__(256) void k_readout_kick_drift(float *x, float *p, int64_t P,
-                                                            const float *__restrict__ F, int64_t rs, int64_t cs,
-                                                            int n, float kick, float drift, int *flag)
+                                                            const float *__restrict__ F, int64_t rs, int64_t ps,
+                                                            int64_t cs, int n, float kick, float drift, int *flag)
 {
     const float nf = (float)n;
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
         const float u0 = x[i], u1 = x[P + i], u2 = x[2 * P + i];
         float f[3];
-        cic_gather(F, rs, cs, n, u0, u1, u2, f);
+        cic_gather(F, rs, ps, cs, n, u0, u1, u2, f);
         const float p0 = p[i] + kick * f[0];
         const float p1 = p[P + i] + kick * f[1];
         const float p2 = p[2 * P + i] + kick * f[2];
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__
                                                                 const Mom3 *__restrict__ ps, int64_t P,
                                                                 const int *__restrict__ koff,
                                                                 const float *__restrict__ F, int64_t rs,
-                                                                int64_t cs, int n, float kick, float drift,
+                                                                int64_t fps, int64_t cs, int n, float kick, float drift,
                                                                 float *x, float *p, uint8_t *tags,
                                                                 const uint32_t *__restrict__ ids_tmp,
                                                                 uint32_t *ids, int *flag, int *cnt_next)
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__
     // aligned), four cells written; then one task per row for the halo cell
     for (int e = threadIdx.x; e < ROWS * 4; e += READOUT_T) {
         const int rr = e >> 2, j = e & 3, a = rr / H, b = rr % H;
-        const float *src = F + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + o2 + 4 * j;
+        const float *src = F + (int64_t)((o0 + a) & mask) * fps + (int64_t)((o1 + b) & mask) * rs + o2 + 4 * j;
         const float4 fx = *reinterpret_cast<const float4 *>(src);
         const float4 fy = *reinterpret_cast<const float4 *>(src + cs);
         const float4 fz = *reinterpret_cast<const float4 *>(src + 2 * cs);
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(READOUT_T) void k_readout_kd_tiles(const float4 *__
     }
     for (int rr = threadIdx.x; rr < ROWS; rr += READOUT_T) {
         const int a = rr / H, b = rr % H;
-        const float *src = F + ((int64_t)((o0 + a) & mask) * n + ((o1 + b) & mask)) * rs + ((o2 + TILE) & mask);
+        const float *src = F + (int64_t)((o0 + a) & mask) * fps + (int64_t)((o1 + b) & mask) * rs + ((o2 + TILE) & mask);
         fl[rr * H + TILE] = make_float4(src[0], src[cs], src[2 * cs], 0.f);
     }
     if (threadIdx.x < NB) hist[threadIdx.x] = 0;
@@ -260,11 +260,11 @@ __global__ void k_tags_canonical(uint8_t *tags, int64_t P, int nseg, const int64
     }
 }
 
-__global__ void k_copy_real(const float *src, int64_t rs, int n, float *dst)
+__global__ void k_copy_real(const float *src, int64_t rs, int64_t ps, int n, float *dst)
 {
-    const int64_t m = (int64_t)n * n * n;
+    const int64_t m = (int64_t)n * n * n, n2 = (int64_t)n * n;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
-        dst[t] = src[(t / n) * rs + t % n];
+        dst[t] = src[(t / n2) * ps + ((t / n) % n) * rs + t % n];
 }
 
 __global__ void k_copy_half(const float2 *src, int64_t rs, int n, float2 *dst)
@@ -449,31 +449,31 @@ hipError_t launch_fill_i64(int64_t *p, int64_t count, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs_f, int64_t comp_stride, int n,
-                          float *acc, hipStream_t s)
+hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs_f, int64_t ps_f, int64_t comp_stride,
+                          int n, float *acc, hipStream_t s)
 {
     hipLaunchKernelGGL(k_readout, dim3(grid_for(P, 256)), dim3(256), 0, s, x, P,
-                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, acc);
+                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * ps_f, 2 * comp_stride, n, acc);
     return hipGetLastError();
 }
 
-hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f,
+hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f, int64_t ps_f,
                                      int64_t comp_stride, int n, float kick, float drift, int *flag, hipStream_t s)
 {
     hipLaunchKernelGGL(k_readout_kick_drift, dim3(grid_for(P, 256)), dim3(256), 0, s, x, p, P,
-                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, flag);
+                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * ps_f, 2 * comp_stride, n, kick, drift, flag);
     return hipGetLastError();
 }
 
 hipError_t launch_readout_kd_tiles(const float4 *xs, const Mom3 *ps, int64_t P, const int *koff, const float2 *f,
-                                   int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
-                                   float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag,
+                                   int64_t rs_f, int64_t ps_f, int64_t comp_stride, int n, float kick, float drift,
+                                   float *x, float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag,
                                    int *cnt_next, hipStream_t s)
 {
     const int nt = n / TILE;
     if (nt < 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_readout_kd_tiles, dim3((unsigned)(nt * nt * nt)), dim3(READOUT_T), 0, s, xs, ps, P, koff,
-                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * comp_stride, n, kick, drift, x, p, tags,
+                       reinterpret_cast<const float *>(f), 2 * rs_f, 2 * ps_f, 2 * comp_stride, n, kick, drift, x, p, tags,
                        ids_tmp, ids, flag, cnt_next);
     return hipGetLastError();
 }
@@ -496,10 +496,10 @@ hipError_t launch_tags_canonical(uint8_t *tags, int64_t P, int nseg, const int64
     return hipGetLastError();
 }
 
-hipError_t launch_copy_real(const float *src, int64_t rs, int n, float *dst, hipStream_t s)
+hipError_t launch_copy_real(const float *src, int64_t rs, int64_t ps, int n, float *dst, hipStream_t s)
 {
     const int64_t m = (int64_t)n * n * n;
-    hipLaunchKernelGGL(k_copy_real, dim3(grid_for(m, 256)), dim3(256), 0, s, src, rs, n, dst);
+    hipLaunchKernelGGL(k_copy_real, dim3(grid_for(m, 256)), dim3(256), 0, s, src, rs, ps, n, dst);
     return hipGetLastError();
 }
 

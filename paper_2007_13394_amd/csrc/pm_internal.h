@@ -18,20 +18,34 @@ constexpr int TILE_W = 8;
 // compact row stride of N (the white-noise and power spectra) hold them for
 // every N >= 8.
 constexpr int64_t half_cols(int n) { return ((n / 2 + 1 + TILE_W - 1) / TILE_W) * TILE_W; }
-// Row stride of the padded half spectra and force meshes: half_cols plus
-// PM_ROW_PAD columns for N >= PM_ROW_PAD_FROM.  The stride decides how the
-// rows and planes fall on HBM channels.  At N = 2048, 1040 complex values
-// (8320 bytes) against the bare 1032 made the readout 18 % and the Green pass
-// 19 % faster and the column passes 7 % slower, 3 % of the whole step; 1048,
-// 1056, 1072, 1088 and 1152 were no better.  At N = 256 the padding made the
-// step 2 % slower, so smaller meshes keep the bare stride.
+// Row stride of the half spectra and force meshes: half_cols plus PM_ROW_PAD
+// columns for N >= PM_PAD_FROM (none by default).
 #ifndef PM_ROW_PAD
-#define PM_ROW_PAD 8
+#define PM_ROW_PAD 0
 #endif
-#ifndef PM_ROW_PAD_FROM
-#define PM_ROW_PAD_FROM 2048
+#ifndef PM_PAD_FROM
+#define PM_PAD_FROM 2048
 #endif
-constexpr int64_t half_pad(int n) { return half_cols(n) + (n >= PM_ROW_PAD_FROM ? PM_ROW_PAD : 0); }
+constexpr int64_t half_pad(int n) { return half_cols(n) + (n >= PM_PAD_FROM ? PM_ROW_PAD : 0); }
+// Plane stride (complex values) of the force solve's spectra and real force
+// meshes: N rows of half_pad(N), plus PM_PLANE_PAD values for N >= PM_PAD_FROM.
+// Every other use of the F region keeps N half_pad rows per plane.  The
+// strides decide how rows and planes fall on HBM channels and banks.  At
+// N = 2048 (C3 step, 8 timed steps per variant, two sweeps on two boxes):
+//   rows 1032, planes unpadded   248.8 ms
+//   rows 1040, planes unpadded   238.2 ms (readout 48.4 -> 40.3 ms, Green
+//                                pass 25.8 -> 21.0 ms, column passes 67.4 -> 72.3 ms)
+//   rows 1032, planes + 16384    233.0 ms
+//   rows 1032, planes + 81920    231.0 ms
+//   rows 1032, planes + 163840   228.4 ms (the default; 1.25 MB per plane)
+//   rows 1032, planes + 245760   232.2 ms
+// Row strides of 1048 to 1152 were no better than 1040.  At N = 256 a padded
+// row cost 2 % of the learned step, so smaller meshes keep the bare layout.
+#ifndef PM_PLANE_PAD
+#define PM_PLANE_PAD 163840
+#endif
+static_assert(PM_PLANE_PAD % 64 == 0, "planes stay whole 64-value groups");
+constexpr int64_t force_plane(int n) { return (int64_t)n * half_pad(n) + (n >= PM_PAD_FROM ? PM_PLANE_PAD : 0); }
 
 // Particles are sorted by TILE^3-cell blocks of the mesh for the tiled paint
 // and readout (meshes of at least 2 TILE cells per side).
@@ -338,15 +352,15 @@ hipError_t launch_r2c_x0_f32(int logn, const float *src, int64_t src_rs, float2 
 hipError_t launch_x0_learned(int logn, const float2 *srcd, const float2 *srcc, float2 *out0, float2 *out1,
                              int64_t plane, int nhp, double coef, double inv_m, const float *table, const float2 *tw,
                              hipStream_t s);
-hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int nhp, int64_t plane,
-                         const float2 *tw, hipStream_t s);
+hipError_t launch_c2r_x0(int logn, const float2 *src, float *dst, int64_t dst_stride, int64_t dst_plane, int nhp,
+                         int64_t plane, const float2 *tw, hipStream_t s);
 
 hipError_t launch_ic_adj_mult(const float2 *G, int64_t nhp, int64_t fs, int n, const IcParams *ic, float2 *acc,
                               bool accumulate, hipStream_t s);
 
 // ---- launchers (adjoint.hip)
 hipError_t launch_axpy(float *y, const float *x, float a, int64_t n, hipStream_t s);
-hipError_t launch_readout_grad3(const float *x, int64_t P, const float *g, float gscale, const float *F, int64_t rs,
+hipError_t launch_readout_grad3(const float *x, int64_t P, const float *g, float gscale, const float *F, int64_t rs, int64_t ps,
                                 int64_t cs, int n, float *xbar, hipStream_t s);
 hipError_t launch_paint_vec3(const float *x, int64_t P, const float *g, float gscale, float *G, int64_t rs,
                              int64_t cs, int n, hipStream_t s);
@@ -425,20 +439,22 @@ hipError_t launch_sort_verify(const int *cursor, const int *koff, int64_t K, int
 
 // ---- launchers (particles.hip)
 hipError_t launch_fill_i64(int64_t *p, int64_t count, hipStream_t s);
-hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs_f, int64_t comp_stride,
+// rs_f, ps_f, comp_stride: row, plane and component strides of the force
+// meshes in complex values (real rows of 2 rs_f floats).
+hipError_t launch_readout(const float *x, int64_t P, const float2 *f, int64_t rs_f, int64_t ps_f, int64_t comp_stride,
                           int n, float *acc, hipStream_t s);
-hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f,
+hipError_t launch_readout_kick_drift(float *x, float *p, int64_t P, const float2 *f, int64_t rs_f, int64_t ps_f,
                                      int64_t comp_stride, int n, float kick, float drift, int *flag,
                                      hipStream_t s);
 // cnt_next (optional): counts per sort key of the positions written, added to.
 hipError_t launch_readout_kd_tiles(const float4 *xs, const Mom3 *ps, int64_t P, const int *koff, const float2 *f,
-                                   int64_t rs_f, int64_t comp_stride, int n, float kick, float drift, float *x,
-                                   float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag, int *cnt_next,
-                                   hipStream_t s);
+                                   int64_t rs_f, int64_t ps_f, int64_t comp_stride, int n, float kick, float drift,
+                                   float *x, float *p, uint8_t *tags, const uint32_t *ids_tmp, uint32_t *ids, int *flag,
+                                   int *cnt_next, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int64_t count, hipStream_t s);
 hipError_t launch_add_i64(const int64_t *src, int64_t *dst, int64_t count, hipStream_t s);
 hipError_t launch_tags_canonical(uint8_t *tags, int64_t P, int nseg, const int64_t *seg_off, hipStream_t s);
-hipError_t launch_copy_real(const float *src, int64_t rs, int n, float *dst, hipStream_t s);
+hipError_t launch_copy_real(const float *src, int64_t rs, int64_t ps, int n, float *dst, hipStream_t s);
 hipError_t launch_copy_half(const float2 *src, int64_t rs, int n, float2 *dst, hipStream_t s);
 hipError_t launch_load_half(const float2 *src, int n, float2 *dst, int64_t rs, hipStream_t s);
 hipError_t launch_ic_cdm(const float2 *f, int64_t rs, int64_t comp_stride, int nic, int n, double vfac,
