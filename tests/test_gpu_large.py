@@ -235,3 +235,65 @@ def test_power_particle_comb_closed_form_1024(dev):
     say("comb power, modes per bin at", (b1, b2, b3), ":", tot[b1], tot[b2], tot[b3])
     assert abs(tot[b1] - 3) < 1e-5 and abs(tot[b2] - 3) < 1e-5 and abs(tot[b3] - 1) < 1e-5
     assert np.abs(np.delete(tot, [b1, b2, b3])).max() < 1e-6
+
+
+def test_force_vjp_finite_differences_2048(dev):
+    """Reverse mode of the force at 2048^3, whose force meshes have padded
+    planes: L(x) = <g, F(x)> is quadratic in one coordinate while every
+    cloud-in-cell corner stays put (the painted density and the readout
+    weights are both affine in it), so a central difference with steps that
+    stay inside the cell is exact up to rounding.  The particles sit at
+    fractions 0.3-0.7 of their cells and the steps are 1/8 cell (exact in
+    float32 at these coordinates)."""
+    from paper_2007_13394_amd import pm
+    gc.collect()
+    torch.cuda.empty_cache()
+    n = 2048
+    # 64^3 particles carry 2^15 cells of mass each (a few point masses of
+    # 2^24 cells would dominate the float32 force meshes around them): a
+    # shift of 36 keeps their quanta (2^51) and any cell sum inside int64
+    cfg = I.config("C1", n_mesh=n, n_cdm=64, n_sites=0, shift=36)
+    ctx = pm.Ctx(pm.make_config(cfg))
+    P = ctx.P
+    rng = np.random.default_rng(4096)
+    # a loose clump so that the particles feel each other, cells and
+    # in-cell fractions drawn separately
+    cells = rng.integers(960, 1088, size=(3, P))
+    frac = rng.uniform(0.3, 0.7, size=(3, P))
+    x = torch.from_numpy((cells + frac).astype(np.float32)).to(dev)
+    # a sparse cotangent: the float32 rounding of the transforms changes
+    # from one force evaluation to the next, and a dense one would sum it
+    # over every particle into the differences
+    S = rng.choice(P, size=32, replace=False)
+    g32 = np.zeros((3, P), dtype=np.float32)
+    g32[:, S] = rng.standard_normal((3, 32)).astype(np.float32)
+    g = torch.from_numpy(g32).to(dev)
+    xb = torch.zeros_like(x)
+    pm.pm_force_vjp(ctx, x, g, xb)
+    acc = torch.empty_like(x)
+
+    def loss(xx):
+        pm.pm_force(ctx, xx, acc)
+        return float((acc.double() * g.double()).sum())
+
+    eps = 0.125
+    # coordinates of particles inside the cotangent's support (readout and
+    # density terms) and outside it (density term only)
+    picks = [(int(rng.integers(0, 3)), int(i)) for i in S[:4]]
+    picks += [(int(rng.integers(0, 3)), int(rng.integers(0, P))) for _ in range(4)]
+    got, want = [], []
+    for d, i in picks:
+        xp, xm = x.clone(), x.clone()
+        xp[d, i] += eps
+        xm[d, i] -= eps
+        want.append((loss(xp) - loss(xm)) / (2 * eps))
+        got.append(float(xb[d, i]))
+    got, want = np.array(got), np.array(want)
+    scale = np.abs(want).max()
+    say("force VJP at 2048^3: reverse mode", got, "central differences", want,
+        "max |diff| / max |FD|", np.abs(got - want).max() / scale)
+    del ctx, x, g, xb, acc
+    gc.collect()
+    torch.cuda.empty_cache()
+    assert scale > 0
+    assert np.abs(got - want).max() < 1e-3 * scale
