@@ -126,8 +126,8 @@ Layout layout(const pm_config &c)
     L.q = off;
     off = align256(off + (size_t)(8 * n * n * n));
     L.f = off;
+    // three components of N planes; the force solve's planes may be padded
     const size_t fbytes = (size_t)(3 * n * pm::force_plane((int)n) * 8);
-    (void)nhp;
     off = align256(off + fbytes);
     L.tw = off;
     off = align256(off + (size_t)(2 * n * 8));
