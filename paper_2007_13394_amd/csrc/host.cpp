@@ -276,16 +276,27 @@ pm_status paint_atomic(pm_ctx *c, const float *x, int lo, int hi, int64_t *mesh,
 // x in between, the check fails and the sort is redone from a fresh count
 // (the scatter never writes past the record arrays).  The check waits for the
 // stream, so it is used only when the end-of-call guards wait anyway.
-pm_status tile_sort(pm_ctx *c, const float *x, const float *p, hipStream_t s)
+// With `defer`, a verification of taken-over counts is left in flight (the
+// flag word on its way to pinned host memory) and finish_sort settles it: the
+// caller may queue work that writes only the workspace in between, which is
+// redone when the counts were stale.
+pm_status tile_sort(pm_ctx *c, const float *x, const float *p, hipStream_t s, bool defer = false)
 {
     const int64_t K = c->nkeys;
     const uint8_t *tin = c->permuted ? c->ws.tags : nullptr;
+    c->verify_pending = false;
     if (c->counts_ready && x == c->counts_x && !(c->cfg.flags & PM_FLAG_NO_GUARDS)) {
         LAUNCH(pm::K_SORT_SCAN, pm::launch_scan(c->ws.cnt_next, c->ws.koff, K + 1, c->ws.bsum, s, c->ws.cnt));
         LAUNCH(pm::K_SORT_SCATTER,
                pm::launch_sort_scatter(x, p, tin, c->P, c->nseg, c->ws.seg_off, c->n, c->ws.cnt, c->ws.xs,
                                        p ? c->ws.ps : nullptr, c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
         LAUNCH(pm::K_SORT_VERIFY, pm::launch_sort_verify(c->ws.cnt, c->ws.koff, K, c->ws.flag, s));
+        if (defer) {
+            HIPCHK(hipMemcpyAsync(c->verify_host, c->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(c->verify_ev, s));
+            c->verify_pending = true;
+            return PM_OK;
+        }
         int h = 0;
         HIPCHK(hipMemcpyAsync(&h, c->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -303,6 +314,27 @@ pm_status tile_sort(pm_ctx *c, const float *x, const float *p, hipStream_t s)
            pm::launch_sort_scatter(x, p, tin, c->P, c->nseg, c->ws.seg_off, c->n, c->ws.cnt, c->ws.xs,
                                    p ? c->ws.ps : nullptr, c->ids, c->ids ? c->ws.ids_tmp : nullptr, s));
     return PM_OK;
+}
+
+// Settles a deferred verification.  Stale counts: the stale bit is cleared
+// (with any guard bit that the work queued on the stale sort set) and the
+// particles are sorted again from a fresh count; *redo tells the caller to
+// queue that work again.  The flag value restored is the one read at the
+// verification, so guard bits from before it survive.
+pm_status finish_sort(pm_ctx *c, const float *x, const float *p, hipStream_t s, bool *redo)
+{
+    *redo = false;
+    if (!c->verify_pending) return PM_OK;
+    c->verify_pending = false;
+    HIPCHK(hipEventSynchronize(c->verify_ev));
+    int h = *c->verify_host;
+    if (!(h & pm::FLAG_STALE)) return PM_OK;
+    h &= ~pm::FLAG_STALE;
+    HIPCHK(hipMemcpyAsync(c->ws.flag, &h, sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->counts_ready = false;
+    *redo = true;
+    return tile_sort(c, x, p, s);
 }
 
 // Paint every segment of x into the Q mesh (overwritten).
@@ -676,6 +708,12 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
         delete c;
         return fail(PM_ERR_DEVICE, "address of the static scratch array: %s", hipGetErrorString(e));
     }
+    e = hipHostMalloc(reinterpret_cast<void **>(&c->verify_host), sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->verify_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        pm_free(c);
+        return fail(PM_ERR_DEVICE, "pinned flag copy: %s", hipGetErrorString(e));
+    }
     *out = c;
     return PM_OK;
 }
@@ -684,6 +722,8 @@ void pm_free(pm_ctx *ctx)
 {
     if (!ctx) return;
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->verify_ev) (void)hipEventDestroy(ctx->verify_ev);
+    if (ctx->verify_host) (void)hipHostFree(ctx->verify_host);
     delete ctx;
 }
 
@@ -976,13 +1016,18 @@ pm_status pm_step(pm_ctx *c, float *x, float *p, double a_force, double a_kick0,
         // the caller's arrays, which then hold the particles in sorted order
         // the tile paint stores each cell's exact int64 sum as its float32
         // density contrast, the value the transform would form from it
-        st = tile_sort(c, x, p, s);
+        // the paint and the solve write only the workspace, so they are queued
+        // before a deferred check of taken-over counts and redone if stale
+        st = tile_sort(c, x, p, s, true);
         if (st != PM_OK) return st;
         float *delta = reinterpret_cast<float *>(c->ws.q);
-        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles_delta(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, c->n,
-                                                         ldexp(1.0, -c->cfg.shift), -1.0, delta, c->ws.flag, s));
-        st = solve(c, nullptr, s, delta);
-        if (st != PM_OK) return st;
+        for (bool redo = true; redo;) {
+            LAUNCH(pm::K_PAINT, pm::launch_paint_tiles_delta(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, c->n,
+                                                             ldexp(1.0, -c->cfg.shift), -1.0, delta, c->ws.flag, s));
+            st = solve(c, nullptr, s, delta);
+            if (st == PM_OK) st = finish_sort(c, x, p, s, &redo);
+            if (st != PM_OK) return st;
+        }
         int *cnt_next = (c->cfg.flags & PM_FLAG_NO_GUARDS) ? nullptr : c->ws.cnt_next;
         if (cnt_next) LAUNCH(pm::K_FILL, pm::launch_fill_i32(cnt_next, c->nkeys + 1, s));
         LAUNCH(pm::K_READOUT_KD,
@@ -1242,13 +1287,16 @@ pm_status pm_learned_step(pm_ctx *c, const float *th, float *x, float *p, double
     if (sorting_on(c)) {
         // as pm_step: tile sort, tile paint (float32 density contrast),
         // (learned) solve, tile readout counting the next step's keys
-        st = tile_sort(c, x, p, s);
+        st = tile_sort(c, x, p, s, true);
         if (st != PM_OK) return st;
         float *delta = reinterpret_cast<float *>(c->ws.q);
-        LAUNCH(pm::K_PAINT, pm::launch_paint_tiles_delta(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, c->n,
-                                                         ldexp(1.0, -c->cfg.shift), -1.0, delta, c->ws.flag, s));
-        st = learned_solve(c, th, a_force, false, s, delta);
-        if (st != PM_OK) return st;
+        for (bool redo = true; redo;) {
+            LAUNCH(pm::K_PAINT, pm::launch_paint_tiles_delta(c->ws.xs, c->ws.koff, c->ws.quanta, c->nseg, c->n,
+                                                             ldexp(1.0, -c->cfg.shift), -1.0, delta, c->ws.flag, s));
+            st = learned_solve(c, th, a_force, false, s, delta);
+            if (st == PM_OK) st = finish_sort(c, x, p, s, &redo);
+            if (st != PM_OK) return st;
+        }
         int *cnt_next = (c->cfg.flags & PM_FLAG_NO_GUARDS) ? nullptr : c->ws.cnt_next;
         if (cnt_next) LAUNCH(pm::K_FILL, pm::launch_fill_i32(cnt_next, c->nkeys + 1, s));
         LAUNCH(pm::K_READOUT_KD,

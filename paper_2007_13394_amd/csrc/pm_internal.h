@@ -288,6 +288,11 @@ struct Ctx {
     // array counts_x); the next sort takes them over and verifies them
     bool counts_ready = false;
     const float *counts_x = nullptr;
+    // a verification of taken-over counts still in flight: the flag word is
+    // copied to pinned verify_host and verify_ev marks the copy's end
+    bool verify_pending = false;
+    int *verify_host = nullptr;
+    hipEvent_t verify_ev = nullptr;
     char *static_scratch = nullptr;   // this device's fixed scratch array (pm_paint_static)
     // launch trace
     bool tracing = false;

@@ -165,6 +165,42 @@ def test_learned_step_sorted_and_unsorted_agree(dev):
     assert dx < 1e-4 and ep < 1e-5
 
 
+def test_learned_step_after_caller_moves_particles(dev):
+    """A sorted learned step leaves the next step's tile counts; here the
+    caller moves every particle in place before the second step, so the
+    counts taken over are stale.  The sorted context must find that out after
+    its scatter, redo the sort, the paint and the learned solve queued on the
+    stale one, and agree with an unsorted context given the same moves."""
+    from paper_2007_13394_amd import pm
+    cfg = I.config("C1")
+    n = cfg["n_mesh"]
+    th = torch.from_numpy(_params(43)).to(dev)
+    calls = [(0.5, 0.5, 0.55, 0.6), (0.6, 0.55, 0.65, 0.7)]
+    x32, p32 = I.synthetic_state(cfg, seed=44)
+    cs = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_LEARNED))
+    cu = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_LEARNED | pm.PM_FLAG_NO_SORT))
+    ids = torch.arange(cs.P, dtype=torch.int32, device=dev)
+    pm.pm_attach_ids(cs, ids)
+    xs, ps = torch.from_numpy(x32).to(dev), torch.from_numpy(p32).to(dev)
+    xu, pu = xs.clone(), ps.clone()
+    shift = torch.tensor([[5.5], [11.25], [2.0]], device=dev)
+    for i, c in enumerate(calls):
+        if i == 1:
+            for xx in (xs, xu):   # same move on both, in place
+                xx.add_(shift).remainder_(n)
+                xx.masked_fill_(xx >= n, 0.0)
+        pm.pm_learned_step(cs, th, xs, ps, *c)
+        pm.pm_learned_step(cu, th, xu, pu, *c)
+    pm.pm_attach_ids(cs, None)
+    order = torch.argsort(ids.long())
+    xo, po = xs[:, order], ps[:, order]
+    dx = (xo - xu).abs()
+    dx = torch.minimum(dx, n - dx).max().item()
+    ep = rel_l2(po.cpu().numpy(), pu.cpu().numpy())
+    say("learned steps with stale counts, sorted vs unsorted: max |dx|", dx, "p rel L2", ep)
+    assert dx < 1e-4 and ep < 1e-5
+
+
 def test_filter_table_and_its_vjp_vs_oracle(dev):
     from paper_2007_13394_amd import pm
     th32 = _params(51)
