@@ -236,9 +236,11 @@ inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 pm_status check_guards(pm_ctx *c, hipStream_t s)
 {
     if (c->cfg.flags & PM_FLAG_NO_GUARDS) return PM_OK;
-    int h = 0;
-    HIPCHK(hipMemcpyAsync(&h, c->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    // through the pinned word (free here: a deferred sort verification is
+    // settled before any readout)
+    HIPCHK(hipMemcpyAsync(c->verify_host, c->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    const int h = *c->verify_host;
     if (h) {
         HIPCHK(hipMemsetAsync(c->ws.flag, 0, sizeof(int), s));
         HIPCHK(hipStreamSynchronize(s));
