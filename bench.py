@@ -34,22 +34,22 @@ LAYOUT_HEADER = "paper_2007_13394_amd/csrc/pm_internal.h"
 MEASURED_TRAFFIC = {
     # profiles/c3_step_hbm_counters.md (averages over the profiled launches;
     # the scatter's include the first sort from canonical order)
-    "c2r_x0": {"bytes_per_launch": 69351056942, "source": "paper_2007_13394_amd/csrc/fft.hip",
-               "sha256_16": "6fb66d6c3e23e7ed"},
-    "cols_inv": {"bytes_per_launch": 70469866434, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "6fb66d6c3e23e7ed"},
-    "cols_fwd": {"bytes_per_launch": 70584598231, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "6fb66d6c3e23e7ed"},
-    "x0_green": {"bytes_per_launch": 103884583390, "source": "paper_2007_13394_amd/csrc/fft.hip",
-                 "sha256_16": "6fb66d6c3e23e7ed"},
-    "r2c_x0": {"bytes_per_launch": 69054353803, "source": "paper_2007_13394_amd/csrc/fft.hip",
-               "sha256_16": "6fb66d6c3e23e7ed"},
-    "readout_kick_drift": {"bytes_per_launch": 192225836542, "source": "paper_2007_13394_amd/csrc/particles.hip",
-                           "sha256_16": "a58c23458bfaf350"},
-    "paint": {"bytes_per_launch": 54968320253, "source": "paper_2007_13394_amd/csrc/paint.hip",
-              "sha256_16": "28ef60e3e26e0897"},
-    "sort_scatter": {"bytes_per_launch": 77631125591, "source": "paper_2007_13394_amd/csrc/sort.hip",
-                     "sha256_16": "b06dbf2b3ae7d01e"},
+    "c2r_x0": {"bytes_per_launch": 69351596441, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "b1f48405701c827b"},
+    "cols_inv": {"bytes_per_launch": 70472608091, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "b1f48405701c827b"},
+    "cols_fwd": {"bytes_per_launch": 70586034592, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "b1f48405701c827b"},
+    "x0_green": {"bytes_per_launch": 103884468952, "source": "paper_2007_13394_amd/csrc/fft.hip",
+                 "sha256_16": "b1f48405701c827b"},
+    "r2c_x0": {"bytes_per_launch": 69053273764, "source": "paper_2007_13394_amd/csrc/fft.hip",
+               "sha256_16": "b1f48405701c827b"},
+    "readout_kick_drift": {"bytes_per_launch": 191412978182, "source": "paper_2007_13394_amd/csrc/particles.hip",
+                           "sha256_16": "d2062547cbdb218b"},
+    "paint": {"bytes_per_launch": 54963058920, "source": "paper_2007_13394_amd/csrc/paint.hip",
+              "sha256_16": "3b4dd91a2add5e4f"},
+    "sort_scatter": {"bytes_per_launch": 77764017512, "source": "paper_2007_13394_amd/csrc/sort.hip",
+                     "sha256_16": "0a3b8992aab2152c"},
 }
 
 
