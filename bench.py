@@ -219,8 +219,12 @@ def learned_vs_plain(steps=10, seeds=(200, 201, 202, 203)):
     the spectra averaged over the seeds."""
     from paper_2007_13394_amd import inputs as I
     from paper_2007_13394_amd import learn
+    from paper_2007_13394_amd import pm
     co = learn.time_steps("C4_coarse", steps)
     fi = learn.time_steps("C4_fine", steps, which=("plain",))
+    # the same steps with each call's guard flags checked by the next call
+    # (PM_FLAG_DEFER_GUARDS): no host wait between calls
+    cod = learn.time_steps("C4_coarse", steps, extra_flags=pm.PM_FLAG_DEFER_GUARDS)
     theta = learn.load_params(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2007_13394_amd",
                                            "c4_learned_theta.npy"))
     held = learn.heldout(I.config("C4_coarse"), I.config("C4_fine"), list(seeds), theta)
@@ -235,6 +239,9 @@ def learned_vs_plain(steps=10, seeds=(200, 201, 202, 203)):
             "learned_coarse_ms_per_step": round(co["learned_ms_per_step"], 3),
             "plain_coarse_ms_per_step": round(co["plain_ms_per_step"], 3),
             "plain_fine_ms_per_step": round(fi["plain_ms_per_step"], 3),
+            "deferred_guards": {"learned_coarse_ms_per_step": round(cod["learned_ms_per_step"], 3),
+                                "plain_coarse_ms_per_step": round(cod["plain_ms_per_step"], 3),
+                                "speedup_vs_fine": round(fi["plain_ms_per_step"] / cod["learned_ms_per_step"], 2)},
             "learned_particle_steps_per_s": co["particles"] / (co["learned_ms_per_step"] * 1e-3),
             "speedup_vs_fine": round(fi["plain_ms_per_step"] / co["learned_ms_per_step"], 2),
             "accuracy": {"k_range_hMpc": [round(v, 4) for v in held["k_range_hMpc"]], "held_out_seeds": per_seed,

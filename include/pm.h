@@ -76,9 +76,15 @@ enum {
                               global atomics and gathers the force: slower) */
     PM_FLAG_LEARNED = 8,   /* reserve the workspace of the learned force correction
                               (pm_learned_*; N a power of two >= 16) */
-    PM_FLAG_NU_PSEUDO = 16 /* pseudo-random neutrino velocities, one particle per
-                              site (n_shell 1, n_fib 0): initial conditions by
-                              pm_ic_pseudo instead of pm_ic */
+    PM_FLAG_NU_PSEUDO = 16, /* pseudo-random neutrino velocities, one particle per
+                               site (n_shell 1, n_fib 0): initial conditions by
+                               pm_ic_pseudo instead of pm_ic */
+    PM_FLAG_DEFER_GUARDS = 32 /* check each call's device flags without waiting for
+                                 it: the copy is queued at the end of the call and
+                                 read by the next guarded call after that call has
+                                 queued its own work, or by pm_sync.  The next call
+                                 (or pm_sync) returns the error; the failing call
+                                 returns PM_OK.  No host wait per call. */
 };
 
 /* Simulation parameters (Table 1 of the paper names the counts).  All
@@ -288,6 +294,11 @@ pm_status pm_segment_tags(pm_ctx *ctx, uint8_t *tags, void *stream);
 /* Declare that the particle arrays passed from now on are in canonical
  * segment order again (as written by pm_ic). */
 pm_status pm_reset_order(pm_ctx *ctx);
+
+/* With PM_FLAG_DEFER_GUARDS: wait for the last guarded call's device flags
+ * and return its status (PM_ERR_NAN, PM_ERR_OVERFLOW or PM_OK); PM_OK when
+ * no check is pending or without the flag.  Waits only for that call's end. */
+pm_status pm_sync(pm_ctx *ctx);
 
 /* Launch trace, for measuring kernel durations on the stream they run on.
  * pm_trace_begin makes every later kernel launch of this context record a

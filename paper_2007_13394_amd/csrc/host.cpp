@@ -233,9 +233,40 @@ void counts(const pm_config &c, int64_t *P, int64_t *nc, int64_t *nn, int *nseg)
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// The guard bits of a flag word read back as a status.
+static pm_status guard_status(int h, const char *which)
+{
+    if (h & pm::FLAG_NAN) return fail(PM_ERR_NAN, "a particle position or momentum became non-finite%s", which);
+    if (h & pm::FLAG_OVERFLOW) return fail(PM_ERR_OVERFLOW, "a density cell left the fixed-point range%s", which);
+    return PM_OK;
+}
+
+// PM_FLAG_DEFER_GUARDS: waits for the previous guarded call's flag copy (that
+// call's end only) and returns its status.
+static pm_status settle_guard(pm_ctx *c)
+{
+    if (!c->guard_pending) return PM_OK;
+    c->guard_pending = false;
+    HIPCHK(hipEventSynchronize(c->guard_ev[c->guard_slot]));
+    return guard_status(c->guard_host[c->guard_slot], " (in the previous call)");
+}
+
 pm_status check_guards(pm_ctx *c, hipStream_t s)
 {
     if (c->cfg.flags & PM_FLAG_NO_GUARDS) return PM_OK;
+    if (c->cfg.flags & PM_FLAG_DEFER_GUARDS) {
+        // this call's word goes to the other pinned slot and is cleared on the
+        // device behind the copy, so each copy holds one call's bits; then the
+        // previous call's copy, long done, is read
+        const int slot = c->guard_slot ^ 1;
+        HIPCHK(hipMemcpyAsync(c->guard_host + slot, c->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        LAUNCH(pm::K_FILL, pm::launch_fill_i32(c->ws.flag, 1, s));
+        HIPCHK(hipEventRecord(c->guard_ev[slot], s));
+        const pm_status prev = settle_guard(c);
+        c->guard_slot = slot;
+        c->guard_pending = true;
+        return prev;
+    }
     // through the pinned word (free here: a deferred sort verification is
     // settled before any readout)
     HIPCHK(hipMemcpyAsync(c->verify_host, c->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -244,8 +275,7 @@ pm_status check_guards(pm_ctx *c, hipStream_t s)
     if (h) {
         HIPCHK(hipMemsetAsync(c->ws.flag, 0, sizeof(int), s));
         HIPCHK(hipStreamSynchronize(s));
-        if (h & pm::FLAG_NAN) return fail(PM_ERR_NAN, "a particle position or momentum became non-finite");
-        return fail(PM_ERR_OVERFLOW, "a density cell left the fixed-point range");
+        return guard_status(h, "");
     }
     return PM_OK;
 }
@@ -712,6 +742,8 @@ pm_status pm_init(const pm_config *cfg, void *workspace, size_t workspace_bytes,
     }
     e = hipHostMalloc(reinterpret_cast<void **>(&c->verify_host), sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->verify_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->guard_host), 2 * sizeof(int), hipHostMallocDefault);
+    for (int k = 0; k < 2 && e == hipSuccess; k++) e = hipEventCreateWithFlags(&c->guard_ev[k], hipEventDisableTiming);
     if (e != hipSuccess) {
         pm_free(c);
         return fail(PM_ERR_DEVICE, "pinned flag copy: %s", hipGetErrorString(e));
@@ -726,6 +758,9 @@ void pm_free(pm_ctx *ctx)
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->verify_ev) (void)hipEventDestroy(ctx->verify_ev);
     if (ctx->verify_host) (void)hipHostFree(ctx->verify_host);
+    for (hipEvent_t e : ctx->guard_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->guard_host) (void)hipHostFree(ctx->guard_host);
     delete ctx;
 }
 
@@ -1066,6 +1101,12 @@ pm_status pm_segment_tags(pm_ctx *c, uint8_t *tags, void *stream)
     else
         LAUNCH(pm::K_COPY, pm::launch_tags_canonical(tags, c->P, c->nseg, c->ws.seg_off, s));
     return PM_OK;
+}
+
+pm_status pm_sync(pm_ctx *c)
+{
+    if (!c) return fail(PM_ERR_ARG, "ctx is NULL");
+    return settle_guard(c);
 }
 
 pm_status pm_reset_order(pm_ctx *c)

@@ -293,6 +293,12 @@ struct Ctx {
     bool verify_pending = false;
     int *verify_host = nullptr;
     hipEvent_t verify_ev = nullptr;
+    // PM_FLAG_DEFER_GUARDS: the flag word of the last guarded call, on its way
+    // to pinned guard_host[guard_slot] behind guard_ev[guard_slot]
+    bool guard_pending = false;
+    int guard_slot = 0;
+    int *guard_host = nullptr;   // two words
+    hipEvent_t guard_ev[2] = {nullptr, nullptr};
     char *static_scratch = nullptr;   // this device's fixed scratch array (pm_paint_static)
     // launch trace
     bool tracing = false;

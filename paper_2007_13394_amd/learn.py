@@ -63,11 +63,11 @@ def init_params(seed, device, hidden_scale=1.0):
     return torch.from_numpy(th).to(device)
 
 
-def make_ctx(cfg, learned=False, sort=False):
+def make_ctx(cfg, learned=False, sort=False, extra_flags=0):
     """Training contexts keep the particles in canonical order (no tile sort),
     since a force pair and the loss take segment masses by array position;
     timed runs sort."""
-    flags = (0 if sort else pm.PM_FLAG_NO_SORT) | (pm.PM_FLAG_LEARNED if learned else 0)
+    flags = (0 if sort else pm.PM_FLAG_NO_SORT) | (pm.PM_FLAG_LEARNED if learned else 0) | extra_flags
     return pm.Ctx(pm.make_config(cfg, flags=flags))
 
 
@@ -381,11 +381,13 @@ def load_params(path, device="cuda"):
     return torch.from_numpy(th).to(device)
 
 
-def time_steps(cfg_name, steps, device="cuda", seed=200, which=("learned", "plain")):
+def time_steps(cfg_name, steps, device="cuda", seed=200, which=("learned", "plain"), extra_flags=0):
     """ms per learned and/or plain step on a sorted context of `cfg_name`
     (parameters: the seeded initialisation with every entry perturbed by 1 %
     noise, so that every layer runs with non-zero weights), from the initial
-    conditions of `seed`."""
+    conditions of `seed`.  extra_flags: further context flags (with
+    PM_FLAG_DEFER_GUARDS the last step's check, pm_sync, is inside the
+    timed region)."""
     cfg = I.config(cfg_name)
     theta = init_params(1, device)
     theta += 0.01 * torch.from_numpy(np.random.default_rng(seed).standard_normal(theta.numel()).astype(np.float32)).to(
@@ -395,7 +397,7 @@ def time_steps(cfg_name, steps, device="cuda", seed=200, which=("learned", "plai
     for name, learned in (("learned", True), ("plain", False)):
         if name not in which:
             continue
-        ctx = make_ctx(cfg, learned=learned, sort=True)
+        ctx = make_ctx(cfg, learned=learned, sort=True, extra_flags=extra_flags)
         x, p = ctx.particles()
         w = torch.from_numpy(I.white_noise(seed, cfg["n_cdm"])).to(device)
         pm.pm_ic(ctx, w, x, p)
@@ -408,6 +410,7 @@ def time_steps(cfg_name, steps, device="cuda", seed=200, which=("learned", "plai
                 pm.pm_learned_step(ctx, theta, x, p, *c)
             else:
                 pm.pm_step(ctx, x, p, *c)
+        pm.pm_sync(ctx)
         torch.cuda.synchronize()
         out[name + "_ms_per_step"] = (time.perf_counter() - t0) / (len(calls) - 2) * 1e3
         out["particles"] = ctx.P

@@ -18,6 +18,7 @@ _lib = C.CDLL(_SO)
 
 PM_OK, PM_ERR_ARG, PM_ERR_SIZE, PM_ERR_DEVICE, PM_ERR_OVERFLOW, PM_ERR_NAN, PM_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 PM_FLAG_NO_FLIP, PM_FLAG_NO_GUARDS, PM_FLAG_NO_SORT = 1, 2, 4
+PM_FLAG_DEFER_GUARDS = 32
 
 
 class PMError(RuntimeError):
@@ -100,6 +101,7 @@ _sig("pm_trace_begin", [_vp, _i32])
 _sig("pm_attach_ids", [_vp, _vp])
 _sig("pm_segment_tags", [_vp, _vp, _vp])
 _sig("pm_reset_order", [_vp])
+_sig("pm_sync", [_vp])
 _sig("pm_trace_end", [_vp, _i32, _vp, _vp, C.POINTER(_i32)])
 _lib.pm_kernel_name.restype = C.c_char_p
 _lib.pm_kernel_name.argtypes = [_i32]
@@ -109,7 +111,7 @@ EXPORTS = ["pm_sizes", "pm_init", "pm_free", "pm_last_error", "pm_segments", "pm
            "pm_force", "pm_step", "pm_power", "pm_trace_begin", "pm_trace_end", "pm_kernel_name", "pm_attach_ids",
            "pm_segment_tags", "pm_reset_order", "pm_density", "pm_density_vjp", "pm_force_vjp", "pm_step_vjp",
            "pm_ic_vjp", "pm_net_nparam", "pm_learned_force", "pm_learned_step", "pm_learned_loss", "pm_adam",
-           "pm_power_mesh", "pm_net_table", "pm_net_table_vjp", "pm_ic_pseudo", "pm_paint_static"]
+           "pm_power_mesh", "pm_net_table", "pm_net_table_vjp", "pm_ic_pseudo", "pm_paint_static", "pm_sync"]
 
 
 def _check(st):
@@ -320,6 +322,10 @@ def pm_segment_tags(ctx, out=None, stream=None):
 
 def pm_reset_order(ctx):
     _check(_lib.pm_reset_order(ctx.h))
+
+
+def pm_sync(ctx):
+    _check(_lib.pm_sync(ctx.h))
 
 
 # ---- reverse mode (device float32 arrays; cotangents accumulate in place)

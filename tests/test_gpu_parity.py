@@ -378,6 +378,49 @@ def test_device_guards_report_overflow_and_nan(dev):
     assert e.value.status == pm.PM_ERR_NAN
 
 
+def test_deferred_guards(dev):
+    """PM_FLAG_DEFER_GUARDS: sorted steps give the same particles bit for bit
+    as with the default check; a step that makes a momentum non-finite
+    returns PM_OK and the next guarded call reports PM_ERR_NAN; pm_sync
+    reports a failure of the last call, and nothing once it is consumed."""
+    pm = _pm()
+    cfg = I.config("C1")
+    x, p = I.synthetic_state(cfg, seed=53)
+    runs = []
+    for flags in (0, pm.PM_FLAG_DEFER_GUARDS):
+        ctx = pm.Ctx(pm.make_config(cfg, flags=flags))
+        ids = torch.arange(ctx.P, dtype=torch.int32, device=dev)
+        pm.pm_attach_ids(ctx, ids)   # the order within a tile key varies run to run
+        xd, pd = torch.from_numpy(x).to(dev), torch.from_numpy(p).to(dev)
+        for c in CALLS:
+            pm.pm_step(ctx, xd, pd, *c)
+        pm.pm_sync(ctx)
+        pm.pm_attach_ids(ctx, None)
+        order = torch.argsort(ids.long())
+        runs.append((xd[:, order].cpu(), pd[:, order].cpu()))
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    # every step starts from finite positions (one momentum is NaN), as in
+    # the guard test above; states that came out non-finite are not stepped
+    ctx = pm.Ctx(pm.make_config(cfg, flags=pm.PM_FLAG_DEFER_GUARDS))
+    pn = p.copy()
+    pn[1, 1234] = np.nan
+
+    def state(mom):
+        pm.pm_reset_order(ctx)                  # a fresh state is in canonical order
+        return torch.from_numpy(x).to(dev), torch.from_numpy(mom).to(dev)
+
+    pm.pm_step(ctx, *state(pn), *CALLS[0])      # the failing call itself returns PM_OK
+    with pytest.raises(pm.PMError) as e:
+        pm.pm_step(ctx, *state(p), *CALLS[0])   # ... and the next guarded call reports it
+    assert e.value.status == pm.PM_ERR_NAN
+    pm.pm_sync(ctx)                             # that finite step's own check is clean
+    pm.pm_step(ctx, *state(pn), *CALLS[1])      # non-finite again, now reported by pm_sync
+    with pytest.raises(pm.PMError) as e:
+        pm.pm_sync(ctx)
+    assert e.value.status == pm.PM_ERR_NAN
+    pm.pm_sync(ctx)                             # consumed: nothing pending
+
+
 def test_sorted_step_after_caller_moves_particles(dev):
     """A sorted step leaves the tile counts of the positions it wrote for the
     next step's sort, which checks them after its scatter.  Here the caller
