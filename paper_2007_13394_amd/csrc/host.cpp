@@ -756,10 +756,17 @@ void pm_free(pm_ctx *ctx)
 {
     if (!ctx) return;
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-    if (ctx->verify_ev) (void)hipEventDestroy(ctx->verify_ev);
-    if (ctx->verify_host) (void)hipHostFree(ctx->verify_host);
+    // a flag copy queued into the pinned words may still be in flight
+    if (ctx->verify_ev) {
+        (void)hipEventSynchronize(ctx->verify_ev);
+        (void)hipEventDestroy(ctx->verify_ev);
+    }
     for (hipEvent_t e : ctx->guard_ev)
-        if (e) (void)hipEventDestroy(e);
+        if (e) {
+            (void)hipEventSynchronize(e);
+            (void)hipEventDestroy(e);
+        }
+    if (ctx->verify_host) (void)hipHostFree(ctx->verify_host);
     if (ctx->guard_host) (void)hipHostFree(ctx->guard_host);
     delete ctx;
 }
