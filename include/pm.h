@@ -255,12 +255,15 @@ pm_status pm_force(pm_ctx *ctx, const float *x, float *acc, void *stream);
  * the last call has a_kick1 = a_drift1 = a_force.  x, p: device [3][P],
  * updated in place.  Errors: PM_ERR_NAN if a result is non-finite,
  * PM_ERR_OVERFLOW if a density cell overflowed (checked at the end of the
- * call, which then waits for the stream, unless PM_FLAG_NO_GUARDS).
+ * call, which then waits for the stream, unless PM_FLAG_NO_GUARDS; with
+ * PM_FLAG_DEFER_GUARDS reported by the next guarded call or pm_sync).
  * On a sorting context the readout also counts the tile keys of the
  * positions it writes; the next call on the same x array sorts with those
- * counts and checks them after its scatter (one 4-byte read that waits for
- * the stream): if the caller changed x in between, the sort is redone from a
- * fresh count.  With PM_FLAG_NO_GUARDS every call counts afresh instead. */
+ * counts and checks them after its scatter.  The check (a 4-byte copy) is
+ * read back just before the readout, the paint and the force solve having
+ * been queued behind it: if the caller changed x in between, the sort is
+ * redone from a fresh count and the paint and the solve are queued again.
+ * With PM_FLAG_NO_GUARDS every call counts afresh instead. */
 pm_status pm_step(pm_ctx *ctx, float *x, float *p, double a_force, double a_kick0, double a_kick1,
                   double a_drift1, void *stream);
 
