@@ -278,7 +278,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU slab "
-              "decomposition is a design, not part of this build)", file=sys.stderr)
+              "decomposition is a design, not part of this library)", file=sys.stderr)
         sys.exit(2)
 
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))

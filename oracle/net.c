@@ -2,7 +2,7 @@
  * Oracle of the learned force correction (test infrastructure only; see
  * orc.h).  Plain FP64 loops, forward and reverse mode.
  *
- * The correction is an addition of this build to the method (the paper's
+ * The correction is an addition of this library to the method (the paper's
  * introduction motivates learned and differentiable extensions of fast
  * particle-mesh codes; it prescribes no network).  Definition:
  *   radial filter: g(k, a) = 1 + h(kt, a), kt = |k| / k_Nyq (k_Nyq = pi per
