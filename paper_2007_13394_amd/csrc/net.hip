@@ -429,19 +429,23 @@ constexpr int WPK_W2 = 0, WPK_W1 = NPAIR * NET_C * 4 * 8 * 2, WPK_W3 = WPK_W1 + 
               WPK_END = WPK_W3 + 27 * NET_C * 2;
 static_assert(WPK_END <= NET_WPK_BYTES && WPK_W1 % 16 == 0 && WPK_W3 % 16 == 0, "packed weight layout");
 
+// A grid of PACK_BLOCKS workgroups (one would wait on its strided weight
+// reads for 32 rounds).
+constexpr int PACK_BLOCKS = 32;
 __global__ __launch_bounds__(256) void k_pack_w(const float *__restrict__ th, uint16_t *wpk)
 {
     uint16_t *w2 = wpk + WPK_W2 / 2, *w1 = wpk + WPK_W1 / 2, *w3 = wpk + WPK_W3 / 2;
-    for (int e = threadIdx.x; e < NPAIR * NET_C * 4 * 8; e += 256) {
+    const int e0 = blockIdx.x * 256 + threadIdx.x, es = PACK_BLOCKS * 256;
+    for (int e = e0; e < NPAIR * NET_C * 4 * 8; e += es) {
         const int pr = e / (NET_C * 32), co = (e / 32) % NET_C, kg = (e / 8) % 4, j = e % 8;
         const int t = 2 * pr + kg / 2, ci = 8 * (kg % 2) + j;
         w2[e] = t < 27 ? to_bf16(th[NC2W + (co * NET_C + ci) * 27 + t]) : (uint16_t)0;
     }
-    for (int e = threadIdx.x; e < NET_C * 32; e += 256) {
+    for (int e = e0; e < NET_C * 32; e += es) {
         const int co = e / 32, t = e % 32;
         w1[e] = t < 27 ? to_bf16(th[NC1W + co * 27 + t]) : (uint16_t)0;
     }
-    for (int e = threadIdx.x; e < 27 * NET_C; e += 256) {
+    for (int e = e0; e < 27 * NET_C; e += es) {
         const int t = e / NET_C, ci = e % NET_C;
         w3[e] = to_bf16(th[NC3W + ci * 27 + t]);
     }
@@ -971,7 +975,7 @@ hipError_t launch_cnn_inf(const int64_t *q, double qs, const float *delta, const
 {
     if (n < 16 || n % 16 || n > 4096) return hipErrorInvalidValue;
     const int64_t M = (int64_t)n * n * n;
-    hipLaunchKernelGGL(k_pack_w, dim3(1), dim3(256), 0, s, th, wpk);
+    hipLaunchKernelGGL(k_pack_w, dim3(PACK_BLOCKS), dim3(256), 0, s, th, wpk);
     if (delta)
         hipLaunchKernelGGL(k_cnn12_inf<float>, dim3((unsigned)(M / (C2X * C2Y * IZ))), dim3(INF_T), 0, s, delta, qs, n,
                            th, wpk, a2);
